@@ -1,0 +1,96 @@
+"""Q2-P1disc assembly of the Stokes saddle-point matrix (eq. (2.1)).
+
+Velocity forms: 'laplace' is mu * grad u : grad v (section 2); 'sym' is
+2 nu(x) D(u) : D(v) with the symmetric gradient D (section 3), nu given per
+Gauss point.  The divergence block is B[q, v] = -int q div v, so that
+K = [[A, B^T], [B, 0]] is symmetric.  The sparsity pattern is the element
+connectivity (all couplings an element creates are stored, including those
+that integrate to zero); the Laplace form omits the cross-component velocity
+couplings, which it never creates.
+"""
+import numpy as np
+import scipy.sparse as sp
+
+from .q2 import quadrature_points, q2_tables, p1_tables
+
+_PTS, _WTS = quadrature_points()
+_PHI, _DPHI = q2_tables(_PTS)          # (q, a), (q, a, dir)
+_PSI = p1_tables(_PTS)                 # (q, m)
+
+
+def velocity_tables(form):
+    """M[q] with A_e = (h/2) * sum_q nu_q M[q]; local velocity dof = 3a + i."""
+    G = _DPHI                                               # (q, a, k)
+    lap = np.einsum("qak,qbk->qab", G, G)                   # (q, a, b)
+    eye = np.eye(3)
+    M = np.einsum("qab,ij->qaibj", lap, eye)
+    if form == "sym":
+        M = M + np.einsum("qaj,qbi->qaibj", G, G)
+    elif form != "laplace":
+        raise ValueError(form)
+    M = M * _WTS[:, None, None, None, None]
+    return M.reshape(27, 81, 81)
+
+
+def divergence_table():
+    """B_e = -(h/2)^2 * T with T[m, 3b+j] = sum_q w_q psi_m dphi_{b,j}."""
+    T = np.einsum("q,qm,qbj->mbj", _WTS, _PSI, _DPHI)
+    return T.reshape(4, 81)
+
+
+def load_table():
+    """int phi_a over the reference cube: F_e[3a+i] = (h/2)^3 * f_i * L[a]."""
+    return np.einsum("q,qa->a", _WTS, _PHI)
+
+
+def gauss_gradients(mesh, nodal_u):
+    """grad u at the 27 Gauss points of each element from the Q2 interpolant: (E, q, i, k)."""
+    ue = nodal_u[mesh.elem_node]                            # (E, a, i)
+    return np.einsum("eai,qak->eqik", ue, _DPHI) * (2.0 / mesh.h)
+
+
+def assemble(mesh, nu_q, form, f=(0.0, 0.0, 0.0)):
+    """Full (unconstrained) K in COO-summed CSR over all dofs and the load vector.
+
+    Full dof numbering: velocity 3*node + i, then pressure 3*n_nodes + 4*e + m.
+    nu_q: (E, 27) viscosity at Gauss points.
+    """
+    h = mesh.h
+    E = mesh.n_elem
+    nv = 3 * mesh.n_nodes
+    ntot = nv + 4 * E
+    M = velocity_tables(form)
+    Ae = (0.5 * h) * (nu_q @ M.reshape(27, 81 * 81)).reshape(E, 81, 81)
+    Be = -(0.5 * h) ** 2 * divergence_table()              # same for every element
+    vd = (3 * mesh.elem_node[:, :, None] + np.arange(3)[None, None, :]).reshape(E, 81)
+    pd = nv + 4 * np.arange(E)[:, None] + np.arange(4)[None, :]
+    if form == "laplace":
+        comp = np.tile(np.arange(3), 27)
+        mask = comp[:, None] == comp[None, :]
+    else:
+        mask = np.ones((81, 81), dtype=bool)
+    ii, jj = np.nonzero(mask)
+    rows = [vd[:, ii].ravel(), pd[:, :, None].repeat(81, 2).ravel(), vd[:, None, :].repeat(4, 1).ravel()]
+    cols = [vd[:, jj].ravel(), vd[:, None, :].repeat(4, 1).ravel(), pd[:, :, None].repeat(81, 2).ravel()]
+    vals = [Ae[:, ii, jj].ravel(), np.broadcast_to(Be, (E, 4, 81)).ravel(),
+            np.broadcast_to(Be, (E, 4, 81)).ravel()]
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    v = np.concatenate(vals)
+    K = sp.coo_matrix((v, (r, c)), shape=(ntot, ntot)).tocsr()
+    K.sort_indices()
+    L = load_table()
+    F = np.zeros(ntot)
+    fe = (0.5 * h) ** 3 * L[:, None] * np.asarray(f, dtype=np.float64)[None, :]   # (a, i)
+    np.add.at(F, vd.ravel(), np.broadcast_to(fe.ravel(), (E, 81)).ravel())
+    return K, F
+
+
+def eliminate(K, F, free_mask, fixed_values):
+    """Restrict to free dofs; move the fixed values to the right-hand side (lifting)."""
+    free = np.nonzero(free_mask)[0]
+    fixed = np.nonzero(~free_mask)[0]
+    Kff = K[free][:, free].tocsr()
+    Kff.sort_indices()
+    b = F[free] - K[free][:, fixed] @ fixed_values[fixed]
+    return Kff, b, free

@@ -1,0 +1,206 @@
+"""Problem builders: the manufactured unit-cube case and seeded voxel dies.
+
+A Problem holds exactly what the library's setup call receives: the CSR
+matrix K over free dofs (velocity 3*node+d first, then pressure 4*elem+m,
+each compacted in that order), node_dof / elem_node / elem_pdof / elem_part
+maps, the part hierarchy, and a right-hand side.
+"""
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+from .mesh import VoxelMesh, axis_segments, part_hierarchy, die_voxels, FACES
+from .assemble import assemble, eliminate, gauss_gradients
+
+
+@dataclass
+class Problem:
+    name: str
+    n: int
+    rowptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+    b: np.ndarray
+    n_nodes: int
+    node_dof: np.ndarray          # (n_nodes*3,) int32, -1 = Dirichlet
+    n_elem: int
+    elem_node: np.ndarray         # (n_elem*27,) int32
+    elem_pdof: np.ndarray         # (n_elem*4,) int32, -1 = pinned
+    elem_part: np.ndarray         # (n_elem,) int32
+    levels: int
+    n_parts: List[int]
+    part_parent: List[np.ndarray]
+    node_xyz: np.ndarray
+    x_exact: Optional[np.ndarray] = None
+    meta: dict = field(default_factory=dict)
+
+    def K(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.val, self.col, self.rowptr), shape=(self.n, self.n))
+
+    def with_hierarchy(self, elem_part, n_parts, part_parent, levels):
+        import copy
+        q = copy.copy(self)
+        q.elem_part = np.asarray(elem_part, dtype=np.int32)
+        q.n_parts = list(n_parts)
+        q.part_parent = [np.asarray(p, dtype=np.int32) for p in part_parent]
+        q.levels = levels
+        return q
+
+
+def uniform_segments(n, block):
+    return (np.arange(n) // block).astype(np.int64)
+
+
+def _number_dofs(mesh, dir_node, pinned_p):
+    nv = 3 * mesh.n_nodes
+    free = np.ones(nv + 4 * mesh.n_elem, dtype=bool)
+    free[(3 * np.nonzero(dir_node)[0][:, None] + np.arange(3)).ravel()] = False
+    for e, m in pinned_p:
+        free[nv + 4 * e + m] = False
+    idx = -np.ones(free.shape[0], dtype=np.int64)
+    idx[free] = np.arange(int(free.sum()))
+    node_dof = idx[:nv].astype(np.int32)
+    elem_pdof = idx[nv:].astype(np.int32)
+    return free, node_dof, elem_pdof
+
+
+def _build(name, mesh, nu_q, form, f, dir_node, dir_values, pinned_p, pin_values,
+           elem_part, n_parts, part_parent, levels, x_full=None, meta=None):
+    K, F = assemble(mesh, nu_q, form, f)
+    free, node_dof, elem_pdof = _number_dofs(mesh, dir_node, pinned_p)
+    fixed_vals = np.zeros(free.shape[0])
+    nv = 3 * mesh.n_nodes
+    fixed_vals[:nv] = dir_values.ravel()
+    for (e, m), v in zip(pinned_p, pin_values):
+        fixed_vals[nv + 4 * e + m] = v
+    Kff, b, free_idx = eliminate(K, F, free, fixed_vals)
+    x_exact = None if x_full is None else x_full[free_idx]
+    return Problem(name=name, n=Kff.shape[0], rowptr=Kff.indptr.astype(np.int64),
+                   col=Kff.indices.astype(np.int32), val=Kff.data.astype(np.float64), b=b,
+                   n_nodes=mesh.n_nodes, node_dof=node_dof, n_elem=mesh.n_elem,
+                   elem_node=mesh.elem_node.ravel().astype(np.int32), elem_pdof=elem_pdof,
+                   elem_part=np.asarray(elem_part, dtype=np.int32), levels=levels,
+                   n_parts=list(n_parts), part_parent=[np.asarray(p, np.int32) for p in part_parent],
+                   node_xyz=mesh.node_xyz, x_exact=x_exact, meta=meta or {})
+
+
+def manufactured_u(xyz):
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    return np.stack([x * x + y * z, -2 * x * y + x * z, y * y], axis=1)
+
+
+def manufactured_p(xyz):
+    return xyz[:, 0] + 2 * xyz[:, 1] - 3 * xyz[:, 2]
+
+
+MANUFACTURED_F = (-1.0, 2.0, -5.0)        # -lap u + grad p for the pair above
+
+
+def unit_cube_problem(n=4, block=2, levels=2, pin=True, form="laplace", mu=1.0):
+    """Unit cube, n^3 voxels, all-Dirichlet with the manufactured quadratic velocity.
+
+    Parts are block^3 voxel blocks; coarser levels group part blocks 2x2x2.
+    With pin=True the constant pressure mode of element 0 is fixed to its
+    exact value so that the pressure is unique.
+    """
+    mesh = VoxelMesh(np.ones((n, n, n), dtype=bool), 1.0 / n)
+    dir_node = np.zeros(mesh.n_nodes, dtype=bool)
+    for e, fc in mesh.boundary_faces():
+        dir_node[mesh.face_nodes(e, fc)] = True
+    uex = manufactured_u(mesh.node_xyz)
+    dir_values = np.where(dir_node[:, None], uex, 0.0)
+    # exact P1disc modes: p(c) + (h/2)(p_x xi + p_y eta + p_z zeta)
+    cen = (mesh.elem_ijk + 0.5) * mesh.h
+    pmodes = np.stack([manufactured_p(cen), np.full(mesh.n_elem, 0.5 * mesh.h * 1.0),
+                       np.full(mesh.n_elem, 0.5 * mesh.h * 2.0), np.full(mesh.n_elem, 0.5 * mesh.h * -3.0)], axis=1)
+    x_full = np.concatenate([uex.ravel(), pmodes.ravel()])
+    pinned = [(0, 0)] if pin else []
+    pin_vals = [pmodes[0, 0]] if pin else []
+    seg = uniform_segments(n, block)
+    elem_part, n_parts, part_parent = part_hierarchy(mesh, seg, seg, seg, levels)
+    nu_q = np.full((mesh.n_elem, 27), float(mu))
+    return _build(f"cube{n}_b{block}_L{levels}", mesh, nu_q, form, MANUFACTURED_F, dir_node, dir_values,
+                  pinned, pin_vals, elem_part, n_parts, part_parent, levels, x_full=x_full,
+                  meta=dict(kind="cube", nx=n, ny=n, nz=n, h=mesh.h, form=form, mu=mu, pin=pin))
+
+
+def carreau(gamma_dot, nu0, lam, n_exp):
+    """Carreau law (section 3): nu = nu0 (1 + (lam * gamma_dot)^2)^((n-1)/2)."""
+    return nu0 * (1.0 + (lam * gamma_dot) ** 2) ** ((n_exp - 1.0) / 2.0)
+
+
+def shear_rate(grad):
+    """gamma_dot = sqrt(2 D:D) with D the symmetric part of grad (last two axes i, k)."""
+    D = 0.5 * (grad + np.swapaxes(grad, -1, -2))
+    return np.sqrt(2.0 * np.sum(D * D, axis=(-1, -2)))
+
+
+def linearization_field(mesh, rng, lam, target=10.0):
+    """Seeded smooth velocity u_k = sum_q a_q sin(pi k_q . x + phi_q), scaled so max lam*gamma_dot = target."""
+    x = mesh.node_xyz
+    u = np.zeros((mesh.n_nodes, 3))
+    for _ in range(4):
+        a = rng.standard_normal(3)
+        k = rng.integers(1, 4, size=3)
+        ph = rng.uniform(0.0, 2.0 * np.pi)
+        u += a[None, :] * np.sin(np.pi * (x @ k) + ph)[:, None]
+    gd = shear_rate(gauss_gradients(mesh, u))
+    u *= target / (lam * gd.max())
+    return u
+
+
+def die_problem(nx=32, ny=16, nz=16, seed=0, nu0=1.0, lam=1.0, n_exp=0.5, levels=3,
+                frac3=0.0, masked=0.20, inflow_speed=1.0):
+    """Seeded die-like voxel channel with Carreau viscosity linearized at a smooth field.
+
+    Inflow: two rectangular windows on x = 0 with a parabolic x-velocity;
+    outflow: the x = x_max face (do-nothing); all other boundary faces no-slip.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    active = die_voxels(nx, ny, nz, rng, target=masked)
+    h = 1.0 / ny
+    mesh = VoxelMesh(active, h)
+    # boundary classification
+    dir_node = np.zeros(mesh.n_nodes, dtype=bool)
+    for e, fc in mesh.boundary_faces():
+        axis, side = FACES[fc]
+        if axis == 0 and side == 1 and mesh.elem_ijk[e, 0] == nx - 1:
+            continue                      # outflow: natural condition
+        dir_node[mesh.face_nodes(e, fc)] = True
+    # two inflow windows on x = 0 (voxel-aligned), one in each half of y
+    wins = []
+    for half in range(2):
+        wy = int(rng.integers(max(1, ny // 5), max(2, ny // 3) + 1))
+        wz = int(rng.integers(max(1, nz // 5), max(2, nz // 3) + 1))
+        ylo, yhi = (1, ny // 2 - wy) if half == 0 else (ny // 2, ny - 1 - wy)
+        y0 = int(rng.integers(ylo, max(ylo, yhi) + 1))
+        z0 = int(rng.integers(1, max(1, nz - 1 - wz) + 1))
+        wins.append((y0 * h, (y0 + wy) * h, z0 * h, (z0 + wz) * h))
+    g = np.zeros((mesh.n_nodes, 3))
+    xyz = mesh.node_xyz
+    on_in = dir_node & (mesh.node_lat[:, 0] == 0)
+    for (ya, yb, za, zb) in wins:
+        s = (xyz[:, 1] - ya) / (yb - ya)
+        t = (xyz[:, 2] - za) / (zb - za)
+        inside = on_in & (s >= 0) & (s <= 1) & (t >= 0) & (t <= 1)
+        g[inside, 0] = inflow_speed * 16.0 * s[inside] * (1 - s[inside]) * t[inside] * (1 - t[inside])
+    seg_rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    sx = axis_segments(nx, seg_rng, frac3)
+    sy = axis_segments(ny, seg_rng, frac3)
+    sz = axis_segments(nz, seg_rng, frac3)
+    elem_part, n_parts, part_parent = part_hierarchy(mesh, sx, sy, sz, levels)
+    uk = linearization_field(mesh, rng, lam)
+    gd = shear_rate(gauss_gradients(mesh, uk))                # (E, 27)
+    nu_q = carreau(gd, nu0, lam, n_exp)
+    return _build(f"die{nx}x{ny}x{nz}_s{seed}_L{levels}", mesh, nu_q, "sym", (0.0, 0.0, 0.0), dir_node, g,
+                  [], [], elem_part, n_parts, part_parent, levels,
+                  meta=dict(kind="die", nx=nx, ny=ny, nz=nz, h=h, seed=seed, nu0=nu0, lam=lam, n_exp=n_exp,
+                            masked=float(1.0 - active.mean()), windows=wins, frac3=frac3,
+                            nu_min=float(nu_q.min()), nu_max=float(nu_q.max())))
+
+
+def random_vector(n, seed):
+    """Seeded N(0, 1) vector (PCG64)."""
+    return np.random.Generator(np.random.PCG64(seed)).standard_normal(n)

@@ -1,0 +1,30 @@
+"""The relative scaled efficiency helper reproduces every percentage of Table 1."""
+import os
+
+from paper_2606_01433_amd.metrics import effic_rel, percentile
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table1.txt")
+
+
+def _rows():
+    rows = []
+    for line in open(GOLDEN):
+        if line.startswith("#") or not line.strip():
+            continue
+        role, n, p, lev, t, eff, it = line.split()
+        rows.append((role, float(n), int(p), int(lev), float(t), int(eff), float(it)))
+    return rows
+
+
+def test_table1_efficiencies():
+    rows = _rows()
+    assert len(rows) == 12
+    for role, n, p, lev, t, eff, _ in rows:
+        base = [r for r in rows if r[0] == role and r[2] == 2048 and r[3] == 3][0]
+        got = 100.0 * effic_rel(t, n, p, base[4], base[1], base[2])
+        assert abs(got - eff) <= 1.0, (role, n, p, lev, got, eff)
+
+
+def test_percentile_nearest_rank():
+    xs = list(range(1, 101))
+    assert percentile(xs, 50) == 50 and percentile(xs, 99) == 99 and percentile([5.0], 99) == 5.0

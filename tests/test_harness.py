@@ -1,0 +1,74 @@
+"""Pins of the seeded problem builder (it feeds both the oracle and the library)."""
+import itertools
+
+import numpy as np
+import pytest
+
+from harness import unit_cube_problem, die_problem
+from harness.problems import carreau, shear_rate
+
+
+@pytest.mark.parametrize("form", ["laplace", "sym"])
+@pytest.mark.parametrize("n", [2, 4])
+def test_manufactured_solution_is_exact(n, form):
+    """Q2/P1disc contains the quadratic velocity / linear pressure pair, so K x_exact = b."""
+    P = unit_cube_problem(n=n, block=max(1, n // 2), form=form)
+    r = P.K() @ P.x_exact - P.b
+    assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(P.b)
+
+
+def test_matrix_symmetric(cube4):
+    K = cube4.K()
+    assert abs(K - K.T).max() <= 1e-15 * abs(K).max()
+
+
+def _brute_force_nnz(P, cross_components):
+    """Count free-dof pairs that share an element (the element-connectivity pattern)."""
+    en = P.elem_node.reshape(-1, 27)
+    pairs = set()
+    for e in range(P.n_elem):
+        vd = [(int(P.node_dof[3 * v + d]), d) for v in en[e] for d in range(3)]
+        vd = [(g, d) for g, d in vd if g >= 0]
+        pd = [int(x) for x in P.elem_pdof[4 * e:4 * e + 4] if x >= 0]
+        for (g, d), (h, c) in itertools.product(vd, vd):
+            if cross_components or d == c:
+                pairs.add((g, h))
+        for q in pd:
+            for g, _ in vd:
+                pairs.add((q, g))
+                pairs.add((g, q))
+    return len(pairs)
+
+
+@pytest.mark.parametrize("form,cross", [("laplace", False), ("sym", True)])
+def test_pattern_is_element_connectivity(form, cross):
+    P = unit_cube_problem(n=4, form=form)
+    assert len(P.col) == _brute_force_nnz(P, cross)
+    # dof counts of the 4^3 cube: 7^3 free Q2 nodes, 64 elements x 4 modes minus the pin
+    assert P.n == 3 * 7 ** 3 + 4 * 64 - 1 == 1284
+
+
+def test_carreau_closed_forms():
+    g = np.array([0.0, 0.5, 2.0, 10.0])
+    assert np.all(carreau(g, 3.0, 7.0, 1.0) == 3.0)                       # n = 1: Newtonian
+    assert carreau(np.array([0.0]), 2.5, 10.0, 0.4)[0] == 2.5              # nu(0) = nu0
+    np.testing.assert_allclose(carreau(np.array([1.0]), 1.0, 1.0, 0.5), 2.0 ** (-0.25), rtol=1e-15)
+
+
+def test_shear_rate_of_simple_shear():
+    """u = (s y, 0, 0): D has entries s/2 at (x,y),(y,x), so gamma_dot = sqrt(2 * 2 (s/2)^2) = |s|."""
+    s = 3.0
+    grad = np.zeros((1, 3, 3))
+    grad[0, 0, 1] = s
+    np.testing.assert_allclose(shear_rate(grad), [s], rtol=1e-15)
+
+
+def test_die_generator_recipe():
+    P = die_problem(16, 8, 8, seed=0, levels=3)
+    m = P.meta
+    assert 0.17 <= m["masked"] <= 0.24
+    assert P.n_parts[0] > P.n_parts[1] >= 1
+    # outflow: free nodes exist on x = x_max, hence no pressure pin is needed
+    assert np.all(P.elem_pdof >= 0)
+    again = die_problem(16, 8, 8, seed=0, levels=3)
+    assert np.array_equal(again.val, P.val) and np.array_equal(again.b, P.b)
