@@ -1,0 +1,227 @@
+/*
+ * gdsw.h -- C ABI of the MI355X monolithic multilevel GDSW library.
+ *
+ * The library builds and applies the monolithic multilevel overlapping
+ * Schwarz preconditioner with GDSW coarse spaces for the saddle-point system
+ * K [u; p] = [F; 0] of eq. (2.1) (Q2 velocity, P1-discontinuous pressure),
+ * and solves that system with restarted flexible GMRES (section 3).
+ *
+ *   setup  : index/overlap maps (section 2.1), local blocks A_i = R_i K R_i^T
+ *            and their pivoted LU, the GDSW basis Phi (interface partition of
+ *            unity times translations / pressure constants, extended by
+ *            Phi_I = -A_II^{-1} A_{I,Gamma} Phi_Gamma), the Galerkin operator
+ *            A_0 = Phi^T K Phi, recursed over the levels of section 2.2, and a
+ *            direct factorization of the coarsest operator;
+ *   apply  : z = B r with B of eq. (2.2);
+ *   solve  : x with ||b - K x|| / ||b|| <= tol by FGMRES(m) preconditioned by B.
+ *
+ * All compute runs in HIP kernels on the current device.  Device pointers are
+ * plain hipMalloc'ed (or PyTorch-owned) memory; host pointers are ordinary
+ * process memory.  Every call is ordered on the hipStream_t passed as `stream`
+ * (NULL = the legacy default stream).
+ *
+ * Ownership: the library copies everything it keeps during gdsw_setup; the
+ * caller may free every input after it returns.  A context owns its device
+ * memory until gdsw_destroy.  Calls on one context must not overlap.
+ *
+ * Errors: every int-returning call returns one of the GDSW_* codes below;
+ * gdsw_last_error() gives a message for the calling thread's last failure.
+ */
+#ifndef GDSW_H
+#define GDSW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  GDSW_OK = 0,
+  GDSW_NOTCONV = 1,     /* solve: max_it reached; x holds the last iterate          */
+  GDSW_EINVAL = -1,     /* bad sizes, ids or inconsistent maps                      */
+  GDSW_ESINGULAR = -2,  /* zero pivot in a local or coarse factorization (level and
+                           part are named in gdsw_last_error())                    */
+  GDSW_ENOMEM = -3,     /* device allocation failed                                  */
+  GDSW_EHIP = -4        /* a HIP runtime call failed                                 */
+};
+
+enum { GDSW_COMBINE_RESTRICTED = 0, GDSW_COMBINE_ADDITIVE = 1 };
+enum { GDSW_FP64 = 0, GDSW_MIXED = 1 };
+
+/*
+ * The problem (eq. (2.1) after Dirichlet elimination) and its decomposition.
+ *
+ * Free dofs are numbered velocity first (3*node + d, compacted), then
+ * pressure (4*elem + m, compacted); K is the n x n CSR matrix over them.
+ *   rowptr, col, val : DEVICE pointers, CSR with sorted column indices.
+ *   node_dof  [n_nodes*3] HOST: free dof of (node, direction) or -1 (Dirichlet).
+ *   elem_node [n_elem*27] HOST: Q2 nodes of each element in local lexicographic
+ *             order (local node k sits at lattice offset (k%3, (k/3)%3, k/9)).
+ *   elem_pdof [n_elem*4]  HOST: pressure dofs, mode 0 = constant, 1..3 = the
+ *             linear modes in xi, eta, zeta; -1 = eliminated.
+ *   elem_part [n_elem]    HOST: level-1 part (subdomain) of each element.
+ *   levels    L >= 2: the number of levels of section 2.2 (levels 1..L-1 carry
+ *             overlapping local solves, level L is solved directly).
+ *   n_parts   [L-1] HOST: number of parts on levels 1..L-1.
+ *   part_parent [L-2] HOST pointers: part_parent[l-1][i] is the level-(l+1)
+ *             part that level-l part i belongs to.
+ * A coarse level (l >= 2) with a single part becomes the coarsest level.
+ */
+typedef struct gdsw_problem {
+  int64_t n;
+  const int64_t* rowptr;
+  const int32_t* col;
+  const double* val;
+  int32_t n_nodes;
+  const int32_t* node_dof;
+  int32_t n_elem;
+  const int32_t* elem_node;
+  const int32_t* elem_pdof;
+  const int32_t* elem_part;
+  int32_t levels;
+  const int32_t* n_parts;
+  const int32_t* const* part_parent;
+} gdsw_problem;
+
+/*
+ * overlap   : layers of the level's node graph added around each part's
+ *             closure (default 1; section 3 uses one layer on all levels).
+ * combine   : GDSW_COMBINE_RESTRICTED (default: every dof keeps the local
+ *             solution of its owning part) or GDSW_COMBINE_ADDITIVE (the
+ *             R_i^T sum printed in eq. (2.2)).
+ * precision : GDSW_FP64, or GDSW_MIXED (local factors, interior factors and
+ *             Phi_I in FP32; K, Galerkin accumulation, Krylov vectors,
+ *             Gram-Schmidt and the coarsest factorization in FP64).
+ * restart   : FGMRES restart length m (default 30).
+ * max_it    : cap on total inner iterations (default 1000).
+ * tol       : relative residual target (default 1e-8).
+ * no_coarse : 1 = omit the coarsest correction (one-level Schwarz for L = 2).
+ * panel     : LU panel width, 0 = built-in default.
+ * profile   : 1 = time every launch of the level-1 local-solve kernel with
+ *             HIP events on the caller's stream (reported by gdsw_get_stats).
+ */
+typedef struct gdsw_options {
+  int32_t overlap;
+  int32_t combine;
+  int32_t precision;
+  int32_t restart;
+  int32_t max_it;
+  double tol;
+  int32_t no_coarse;
+  int32_t panel;
+  int32_t profile;
+} gdsw_options;
+
+typedef struct gdsw_solve_info {
+  int32_t iterations;    /* total inner FGMRES iterations                     */
+  int32_t restarts;      /* completed cycles                                  */
+  int32_t converged;     /* 1 if the true relative residual reached tol      */
+  double rel_residual;   /* true ||b - K x||_2 / ||b||_2 in FP64              */
+  double ms_apply, ms_spmv, ms_orth, ms_total;   /* wall-clock per phase     */
+} gdsw_solve_info;
+
+/* Sizes and algorithmic work of a built hierarchy (for reporting). */
+typedef struct gdsw_stats {
+  int32_t levels;                 /* effective number of levels               */
+  int64_t n[8];                   /* rows of the level-l operator, l = 1..L    */
+  int32_t parts[8];               /* parts on level l (0 on the coarsest)      */
+  int64_t sum_ni[8];              /* sum of local block sizes on level l       */
+  int32_t max_ni[8];
+  int64_t factor_bytes[8];        /* bytes of local LU factors on level l      */
+  double factor_flops[8];         /* sum (2/3) n_i^3 on level l                */
+  double interior_flops[8];       /* interior LU + extension solves on level l */
+  int64_t nnz[8];                 /* nonzeros of the level-l operator          */
+  double ms_maps, ms_extract, ms_factor, ms_basis, ms_galerkin, ms_coarse, ms_total;
+  /* profile = 1 only: event-timed level-1 local-solve launches since setup */
+  int64_t local_solve_launches;
+  double ms_local_solve;          /* summed kernel time                         */
+  double local_solve_bytes;       /* algorithmic bytes of one launch: sum_i n_i^2 s + 20 n_i */
+} gdsw_stats;
+
+/* Index maps of one level, host copies owned by the context (valid until
+ * gdsw_destroy).  Lists are concatenated with int64 offsets [count+1]. */
+typedef struct gdsw_maps_view {
+  int32_t n_dof;           /* rows of this level's operator                 */
+  int32_t n_parts;
+  const int64_t* dom_ptr;  /* overlapping dof sets D_i, sorted               */
+  const int32_t* dom;
+  const int64_t* int_ptr;  /* interior dof sets I_i, sorted                  */
+  const int32_t* inter;
+  int32_t n_gamma_nodes;   /* interface nodes, ascending                    */
+  const int32_t* gamma_nodes;
+  int32_t n_entities;      /* interface entities ordered by smallest node     */
+  const int64_t* ent_ptr;
+  const int32_t* ent_nodes;
+  const int32_t* ent_kind; /* 0 vertex, 1 edge, 2 face                      */
+  int32_t n_coarse;        /* columns of Phi = coarse dofs of the next level  */
+  const int32_t* col_entity; /* entity of a velocity column, -1-part for a pressure column */
+  const int32_t* col_dir;  /* 0..2 velocity direction, 3 pressure           */
+  const int32_t* owner;    /* [n_dof] part that owns each dof (restricted combine) */
+} gdsw_maps_view;
+
+typedef struct gdsw_ctx gdsw_ctx;   /* opaque */
+
+/* Fill `opt` with the defaults listed above. */
+void gdsw_default_options(gdsw_options* opt);
+
+/* Build the hierarchy (section 2.1 for each level, recursion of section 2.2).
+ * prob: see gdsw_problem; K is read during the call and copied.
+ * opt : NULL = defaults.
+ * out : receives a new context on success (NULL on failure).
+ * Returns GDSW_EINVAL for inconsistent input, GDSW_ESINGULAR if a local,
+ * interior or coarse block has a zero pivot, GDSW_ENOMEM or GDSW_EHIP. */
+int gdsw_setup(const gdsw_problem* prob, const gdsw_options* opt, void* stream, gdsw_ctx** out);
+
+/* z = B r, B of eq. (2.2).  r, z: DEVICE FP64 vectors of length n (may not alias). */
+int gdsw_apply(gdsw_ctx* ctx, const double* r, double* z, void* stream);
+
+/* Solve K x = b by FGMRES(restart) preconditioned by B (section 3), x0 = 0.
+ * b, x: DEVICE FP64 vectors of length n.  Synchronizes the stream once per
+ * inner iteration (to read the Hessenberg column).  Returns GDSW_OK or
+ * GDSW_NOTCONV (x then holds the last iterate); info may be NULL. */
+int gdsw_solve(gdsw_ctx* ctx, const double* b, double* x, void* stream, gdsw_solve_info* info);
+
+/* y = K x with the level-1 operator (CSR SpMV).  x, y: DEVICE FP64, length n. */
+int gdsw_spmv(gdsw_ctx* ctx, const double* x, double* y, void* stream);
+
+/* Sum of the local solutions of one level in the library's scatter order:
+ * w holds the local vectors of all parts back to back (part i's block has the
+ * length of D_i, entries in D_i order); z[g] = 0.0 + sum over the parts whose
+ * block holds g, ascending part id (restricted combine: only the owner).
+ * w, z: DEVICE FP64.  level is 1-based and must carry local solves. */
+int gdsw_scatter_local(gdsw_ctx* ctx, int32_t level, const double* w, double* z, void* stream);
+
+/* Host views of the index maps of a level that carries local solves (1-based). */
+int gdsw_export_maps(gdsw_ctx* ctx, int32_t level, gdsw_maps_view* out);
+
+/* Sizes, algorithmic work and setup timings of the hierarchy. */
+int gdsw_get_stats(gdsw_ctx* ctx, gdsw_stats* out);
+
+/* Host-only dry run: validates the problem and builds the index maps of every
+ * level (no device allocation, no kernel launch; K's device arrays are not
+ * read).  For inspection and admission control.  Returns GDSW_EINVAL for
+ * inconsistent input. */
+typedef struct gdsw_plan gdsw_plan;   /* opaque */
+int gdsw_plan_create(const gdsw_problem* prob, const gdsw_options* opt, gdsw_plan** out);
+/* Number of levels carrying local solves, and whether a direct coarsest level follows. */
+int gdsw_plan_levels(gdsw_plan* plan, int32_t* schwarz_levels, int32_t* has_coarsest);
+/* Host views of the maps of level `level` (1-based), valid until gdsw_plan_destroy. */
+int gdsw_plan_maps(gdsw_plan* plan, int32_t level, gdsw_maps_view* out);
+void gdsw_plan_destroy(gdsw_plan* plan);
+
+/* Estimated device bytes the context of this problem would hold (for admission
+ * control); host-only integer work, no device allocation. Returns 0 on error. */
+size_t gdsw_footprint_bytes(const gdsw_problem* prob, const gdsw_options* opt);
+
+/* Release every device and host resource of the context (NULL is a no-op). */
+void gdsw_destroy(gdsw_ctx* ctx);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char* gdsw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,216 @@
+// Preconditioner apply, eq. (2.2): local solves R_i^T A_i^{-1} R_i, the
+// ordered combination of overlapping values, the coarse restriction Phi^T r,
+// the prolongation Phi y and the coarsest direct solve.
+#include "common.h"
+#include "kernels.h"
+
+namespace gdsw {
+
+namespace {
+
+constexpr int PW = 64;   // triangle / panel width of the blocked substitution
+
+// One workgroup per part: gather r (pivoted), forward substitution with unit L,
+// backward substitution with U, write the local solution in D_i order.
+// Each 64-wide panel: one wave solves the diagonal triangle with lane shuffles,
+// then all waves stream the panel below (or above) as a GEMV.
+template <typename T>
+__global__ __launch_bounds__(256) void k_local_solve(const int64_t* __restrict__ dom_ptr, const int* __restrict__ gidx,
+                                                     const int64_t* __restrict__ blk_off, const T* __restrict__ blocks,
+                                                     const double* __restrict__ r, double* __restrict__ w) {
+  extern __shared__ unsigned char smem_raw[];
+  T* x = reinterpret_cast<T*>(smem_raw);
+  const int i = blockIdx.x;
+  const int64_t base = dom_ptr[i];
+  const int n = (int)(dom_ptr[i + 1] - base);
+  const T* A = blocks + blk_off[i];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int a = tid; a < n; a += 256) x[a] = (T)r[gidx[base + a]];
+  __syncthreads();
+  for (int p0 = 0; p0 < n; p0 += PW) {
+    const int pw = min(PW, n - p0);
+    if (wid == 0) {
+      T xv = (lane < pw) ? x[p0 + lane] : T(0);
+      const T* col = A + (p0 + lane) + (int64_t)p0 * n;
+      for (int j = 0; j < pw; ++j) {
+        const T xj = __shfl(xv, j, WAVE);
+        if (lane > j && lane < pw) xv -= col[(int64_t)j * n] * xj;
+      }
+      if (lane < pw) x[p0 + lane] = xv;
+    }
+    __syncthreads();
+    for (int rr = p0 + pw + tid; rr < n; rr += 256) {
+      const T* Ar = A + rr + (int64_t)p0 * n;
+      T acc = T(0);
+#pragma unroll 16
+      for (int j = 0; j < pw; ++j) acc += Ar[(int64_t)j * n] * x[p0 + j];
+      x[rr] -= acc;
+    }
+    __syncthreads();
+  }
+  for (int p0 = ((n - 1) / PW) * PW; p0 >= 0; p0 -= PW) {
+    const int pw = min(PW, n - p0);
+    if (wid == 0) {
+      T xv = (lane < pw) ? x[p0 + lane] : T(0);
+      const T* col = A + (p0 + lane) + (int64_t)p0 * n;
+      for (int j = pw - 1; j >= 0; --j) {
+        if (lane == j) xv = xv / col[(int64_t)j * n];
+        const T xj = __shfl(xv, j, WAVE);
+        if (lane < j) xv -= col[(int64_t)j * n] * xj;
+      }
+      if (lane < pw) x[p0 + lane] = xv;
+    }
+    __syncthreads();
+    for (int rr = tid; rr < p0; rr += 256) {
+      const T* Ar = A + rr + (int64_t)p0 * n;
+      T acc = T(0);
+#pragma unroll 16
+      for (int j = 0; j < pw; ++j) acc += Ar[(int64_t)j * n] * x[p0 + j];
+      x[rr] -= acc;
+    }
+    __syncthreads();
+  }
+  for (int a = tid; a < n; a += 256) w[base + a] = (double)x[a];
+}
+
+__global__ void k_scatter_sum(int64_t n, const int64_t* __restrict__ sc_ptr, const int* __restrict__ sc_pos,
+                              const double* __restrict__ w, double* __restrict__ z) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  double s = 0.0;
+  for (int64_t k = sc_ptr[g]; k < sc_ptr[g + 1]; ++k) s += w[sc_pos[k]];
+  z[g] = s;
+}
+
+// rc[c] = sum of r over the interface dofs of column c + Phi_I columns of the parts holding c.
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict(int n_coarse, const int64_t* __restrict__ col_ptr,
+                                                  const int* __restrict__ col_dofs, const int64_t* __restrict__ cp_ptr,
+                                                  const int* __restrict__ cp_part, const int* __restrict__ cp_lc,
+                                                  const int64_t* __restrict__ int_ptr, const int* __restrict__ inter,
+                                                  const int64_t* __restrict__ phi_off, const T* __restrict__ phi,
+                                                  const double* __restrict__ r, double* __restrict__ rc) {
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= n_coarse) return;
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int64_t k = col_ptr[c] + lane; k < col_ptr[c + 1]; k += 64) s += r[col_dofs[k]];
+  for (int64_t t = cp_ptr[c]; t < cp_ptr[c + 1]; ++t) {
+    const int i = cp_part[t];
+    const int64_t ib = int_ptr[i];
+    const int nI = (int)(int_ptr[i + 1] - ib);
+    const T* ph = phi + phi_off[i] + (int64_t)cp_lc[t] * nI;
+    const int* I = inter + ib;
+    for (int a = lane; a < nI; a += 64) s += (double)ph[a] * r[I[a]];
+  }
+  s = wave_sum(s);
+  if (lane == 0) rc[c] = s;
+}
+
+template <typename T>
+__global__ void k_prolong_add(int64_t n, const int* __restrict__ dof_gcol, const int* __restrict__ dof_ipart,
+                              const int* __restrict__ dof_irow, const int64_t* __restrict__ int_ptr,
+                              const int64_t* __restrict__ pc_ptr, const int* __restrict__ pcols,
+                              const int64_t* __restrict__ phi_off, const T* __restrict__ phi,
+                              const double* __restrict__ y, double* __restrict__ z) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const int gc = dof_gcol[g];
+  double p = 0.0;
+  if (gc >= 0) {
+    p = y[gc];
+  } else {
+    const int i = dof_ipart[g];
+    if (i >= 0) {
+      const int a = dof_irow[g];
+      const int nI = (int)(int_ptr[i + 1] - int_ptr[i]);
+      const int m = (int)(pc_ptr[i + 1] - pc_ptr[i]);
+      const T* ph = phi + phi_off[i] + a;
+      const int* pc = pcols + pc_ptr[i];
+      for (int c = 0; c < m; ++c) p += (double)ph[(int64_t)c * nI] * y[pc[c]];
+    }
+  }
+  z[g] += p;
+}
+
+constexpr int GEMV_CHUNK = 64;
+
+__global__ __launch_bounds__(256) void k_gemv_partial(int n, const double* __restrict__ A,
+                                                      const double* __restrict__ x, double* __restrict__ partial) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int c0 = blockIdx.y * GEMV_CHUNK;
+  if (r >= n) return;
+  const int c1 = min(n, c0 + GEMV_CHUNK);
+  double acc = 0.0;
+  for (int c = c0; c < c1; ++c) acc += A[r + (int64_t)c * n] * x[c];
+  partial[(int64_t)blockIdx.y * n + r] = acc;
+}
+
+__global__ void k_gemv_reduce(int n, int chunks, const double* __restrict__ partial, double* __restrict__ y) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double s = 0.0;
+  for (int q = 0; q < chunks; ++q) s += partial[(int64_t)q * n + r];
+  y[r] = s;
+}
+
+}  // namespace
+
+template <typename T>
+void local_solves(int nparts, int max_n, const int64_t* dom_ptr, const int* gidx, const int64_t* blk_off,
+                  const T* blocks, const double* r, double* w, hipStream_t s) {
+  if (nparts == 0) return;
+  const size_t lds = (size_t)max_n * sizeof(T);
+  hipLaunchKernelGGL((k_local_solve<T>), dim3(nparts), dim3(256), lds, s, dom_ptr, gidx, blk_off, blocks, r, w);
+  GDSW_LAUNCH_CHECK();
+}
+
+void scatter_sum(int64_t n, const int64_t* sc_ptr, const int* sc_pos, const double* w, double* z, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_sum, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, sc_ptr, sc_pos, w, z);
+  GDSW_LAUNCH_CHECK();
+}
+
+template <typename T>
+void restrict_phi(int n_coarse, const int64_t* col_ptr, const int* col_dofs, const int64_t* cp_ptr,
+                  const int* cp_part, const int* cp_lc, const int64_t* int_ptr, const int* inter,
+                  const int64_t* phi_off, const T* phi, const double* r, double* rc, hipStream_t s) {
+  hipLaunchKernelGGL((k_restrict<T>), dim3(blocks_for(n_coarse, 4)), dim3(256), 0, s, n_coarse, col_ptr, col_dofs,
+                     cp_ptr, cp_part, cp_lc, int_ptr, inter, phi_off, phi, r, rc);
+  GDSW_LAUNCH_CHECK();
+}
+
+template <typename T>
+void prolong_add(int64_t n, const int* dof_gcol, const int* dof_ipart, const int* dof_irow, const int64_t* int_ptr,
+                 const int64_t* pc_ptr, const int* pcols, const int64_t* phi_off, const T* phi, const double* y,
+                 double* z, hipStream_t s) {
+  hipLaunchKernelGGL((k_prolong_add<T>), dim3(blocks_for(n, 256)), dim3(256), 0, s, n, dof_gcol, dof_ipart, dof_irow,
+                     int_ptr, pc_ptr, pcols, phi_off, phi, y, z);
+  GDSW_LAUNCH_CHECK();
+}
+
+int dense_gemv_partials(int n) { return (int)blocks_for(n, GEMV_CHUNK) * n; }
+
+void dense_gemv(int n, const double* Ainv, const double* x, double* y, double* partial, hipStream_t s) {
+  const int chunks = (int)blocks_for(n, GEMV_CHUNK);
+  hipLaunchKernelGGL(k_gemv_partial, dim3(blocks_for(n, 256), chunks), dim3(256), 0, s, n, Ainv, x, partial);
+  GDSW_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_gemv_reduce, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, chunks, partial, y);
+  GDSW_LAUNCH_CHECK();
+}
+
+template void local_solves<double>(int, int, const int64_t*, const int*, const int64_t*, const double*,
+                                   const double*, double*, hipStream_t);
+template void local_solves<float>(int, int, const int64_t*, const int*, const int64_t*, const float*, const double*,
+                                  double*, hipStream_t);
+template void restrict_phi<double>(int, const int64_t*, const int*, const int64_t*, const int*, const int*,
+                                   const int64_t*, const int*, const int64_t*, const double*, const double*, double*,
+                                   hipStream_t);
+template void restrict_phi<float>(int, const int64_t*, const int*, const int64_t*, const int*, const int*,
+                                  const int64_t*, const int*, const int64_t*, const float*, const double*, double*,
+                                  hipStream_t);
+template void prolong_add<double>(int64_t, const int*, const int*, const int*, const int64_t*, const int64_t*,
+                                  const int*, const int64_t*, const double*, const double*, double*, hipStream_t);
+template void prolong_add<float>(int64_t, const int*, const int*, const int*, const int64_t*, const int64_t*,
+                                 const int*, const int64_t*, const float*, const double*, double*, hipStream_t);
+
+}  // namespace gdsw

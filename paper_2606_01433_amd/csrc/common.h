@@ -1,0 +1,64 @@
+// Shared definitions of the HIP library: error handling, launch helpers and
+// wave64 reductions for CDNA4 (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+namespace gdsw {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& msg) : std::runtime_error(msg), code(c) {}
+};
+
+#define GDSW_HIP(expr)                                                                        \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) {                                                                   \
+      int code_ = (e_ == hipErrorOutOfMemory) ? -3 : -4;                                      \
+      throw ::gdsw::Error(code_, std::string(#expr) + ": " + hipGetErrorString(e_) + " (" +   \
+                                     __FILE__ + ":" + std::to_string(__LINE__) + ")");        \
+    }                                                                                         \
+  } while (0)
+
+#define GDSW_LAUNCH_CHECK() GDSW_HIP(hipGetLastError())
+
+constexpr int WAVE = 64;
+
+inline unsigned blocks_for(int64_t n, int per_block) {
+  return (unsigned)((n + per_block - 1) / per_block);
+}
+
+// Fixed-shape butterfly sum over the 64 lanes of a wavefront (deterministic).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+  return v;
+}
+
+// Lower bound of `key` in the sorted array a[0..n).
+__device__ __forceinline__ int lower_bound_i32(const int* a, int n, int key) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Index of the segment of ptr[0..nseg] (non-decreasing, ptr[0] = 0) holding position k.
+__device__ __forceinline__ int segment_of(const int64_t* ptr, int nseg, int64_t k) {
+  int lo = 0, hi = nseg;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (ptr[mid] <= k) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace gdsw

@@ -1,0 +1,954 @@
+// Runtime of the multilevel GDSW library: hierarchy construction (section 2.1
+// per level, recursion of section 2.2), the apply of eq. (2.2) and restarted
+// FGMRES (section 3), behind the C ABI declared in include/gdsw.h.
+#include "../../include/gdsw.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+#include "maps.h"
+
+namespace gdsw {
+
+namespace {
+
+thread_local std::string g_last_error;
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Device memory owned by a context; released together on destroy.
+class Arena {
+ public:
+  ~Arena() { release(); }
+  void* alloc(size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    void* p = nullptr;
+    GDSW_HIP(hipMalloc(&p, bytes));
+    ptrs_.push_back(p);
+    bytes_ += bytes;
+    return p;
+  }
+  template <typename T> T* alloc_n(size_t n) { return static_cast<T*>(alloc(n * sizeof(T))); }
+  void free_one(void* p) {
+    auto it = std::find(ptrs_.begin(), ptrs_.end(), p);
+    if (it != ptrs_.end()) {
+      (void)hipFree(p);
+      ptrs_.erase(it);
+    }
+  }
+  void release() {
+    for (void* p : ptrs_) (void)hipFree(p);
+    ptrs_.clear();
+  }
+  size_t bytes() const { return bytes_; }
+
+ private:
+  std::vector<void*> ptrs_;
+  size_t bytes_ = 0;
+};
+
+template <typename T>
+T* upload(Arena& a, const std::vector<T>& v, hipStream_t s) {
+  T* d = a.alloc_n<T>(v.size());
+  if (!v.empty()) GDSW_HIP(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return d;
+}
+
+struct Level {
+  int index = 0;                 // 1-based level number
+  int nparts = 0;
+  int64_t n = 0;                 // rows of this level's operator
+  CsrDev K;
+  LevelMaps maps;
+  // local blocks
+  int max_n = 0;
+  int64_t sum_n = 0, sum_n2 = 0;
+  std::vector<int> dims;
+  std::vector<int64_t> blk_off_h;
+  int64_t* dom_ptr = nullptr;
+  int* dom = nullptr;
+  int64_t* blk_off = nullptr;
+  int* dim = nullptr;
+  void* blocks = nullptr;        // double or float
+  int* piv = nullptr;
+  int* perm = nullptr;
+  int* gidx = nullptr;
+  int* info = nullptr;
+  int64_t* sc_ptr = nullptr;
+  int* sc_pos = nullptr;
+  double* w = nullptr;           // local solutions, sum_n
+  // coarse space (absent on the last Schwarz level when the coarsest correction is dropped)
+  bool has_coarse = false;
+  int n_coarse = 0;
+  int64_t* int_ptr = nullptr;
+  int* inter = nullptr;
+  int* dof_gcol = nullptr;
+  int* dof_ipart = nullptr;
+  int* dof_irow = nullptr;
+  int64_t* pc_ptr = nullptr;
+  int* pcols = nullptr;
+  int64_t* cp_ptr = nullptr;
+  int* cp_part = nullptr;
+  int* cp_lc = nullptr;
+  int64_t* col_ptr = nullptr;
+  int* col_dofs = nullptr;
+  int64_t* phi_off = nullptr;
+  void* phi = nullptr;           // double or float, |I_i| x m_i column-major per part
+  int* iinfo = nullptr;
+  int* bad = nullptr;            // set by the basis/Galerkin kernels on non-element-local couplings
+  int max_ni = 0;
+  double* rc = nullptr;          // restricted residual (n_coarse)
+  double* yc = nullptr;          // coarse correction (n_coarse)
+  double interior_flops = 0.0;
+};
+
+}  // namespace
+
+}  // namespace gdsw
+
+struct gdsw_ctx {
+  gdsw::Arena arena;
+  gdsw_options opt;
+  int mixed = 0;
+  std::vector<gdsw::Level> levels;     // Schwarz levels
+  bool has_coarsest = false;
+  int nc = 0;                          // coarsest order
+  double* ainv = nullptr;              // coarsest inverse (column-major)
+  double* gemv_partial = nullptr;
+  int64_t nnz_coarsest = 0;
+  gdsw_stats stats;
+  // FGMRES workspace
+  int ws_m = -1;
+  double *V = nullptr, *Z = nullptr, *wv = nullptr, *dpart = nullptr, *hdev = nullptr, *ydev = nullptr;
+  double* hhost = nullptr;
+  // event pairs around level-1 local-solve launches (profile = 1)
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  ~gdsw_ctx() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
+};
+
+namespace gdsw {
+namespace {
+
+int64_t checked_i32(int64_t v, const char* what) {
+  if (v > INT32_MAX) throw Error(GDSW_EINVAL, std::string(what) + " exceeds the int32 index range");
+  return v;
+}
+
+template <typename T>
+void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
+  Arena& A = C->arena;
+  const LevelMaps& m = L.maps;
+  const int N = L.nparts;
+  L.dims.resize(N);
+  L.blk_off_h.resize(N);
+  L.max_n = 0;
+  L.sum_n = 0;
+  L.sum_n2 = 0;
+  for (int i = 0; i < N; ++i) {
+    const int ni = (int)(m.dom_ptr[i + 1] - m.dom_ptr[i]);
+    L.dims[i] = ni;
+    L.blk_off_h[i] = L.sum_n2;
+    L.sum_n2 += (int64_t)ni * ni;
+    L.sum_n += ni;
+    L.max_n = std::max(L.max_n, ni);
+  }
+  L.dom_ptr = upload(A, m.dom_ptr, s);
+  L.dom = upload(A, m.dom, s);
+  L.blk_off = upload(A, L.blk_off_h, s);
+  L.dim = upload(A, L.dims, s);
+  T* blocks = A.alloc_n<T>((size_t)L.sum_n2);
+  L.blocks = blocks;
+  GDSW_HIP(hipMemsetAsync(blocks, 0, (size_t)L.sum_n2 * sizeof(T), s));
+  extract_blocks<T>(L.K, N, L.sum_n, L.dom_ptr, L.dom, L.blk_off, blocks, s);
+  L.piv = A.alloc_n<int>((size_t)L.sum_n);
+  L.info = A.alloc_n<int>(N);
+  GDSW_HIP(hipMemsetAsync(L.info, 0, N * sizeof(int), s));
+  LuBatch b;
+  b.count = N;
+  b.max_n = L.max_n;
+  b.off = L.blk_off;
+  b.dim = L.dim;
+  b.piv = L.piv;
+  b.poff = L.dom_ptr;
+  b.info = L.info;
+  lu_batched<T>(b, blocks, s);
+  L.perm = A.alloc_n<int>((size_t)L.sum_n);
+  lu_build_perm(b, L.perm, s);
+  L.gidx = A.alloc_n<int>((size_t)L.sum_n);
+  make_gather_index(N, L.sum_n, L.dom_ptr, L.dom, L.perm, L.gidx, s);
+  // ordered combination lists: every position holding g (additive) or the owner's only (restricted)
+  std::vector<int64_t> sc_ptr(L.n + 1, 0);
+  std::vector<int> sc_pos;
+  const bool additive = C->opt.combine == GDSW_COMBINE_ADDITIVE;
+  if (additive) {
+    for (int64_t k = 0; k < L.sum_n; ++k) sc_ptr[m.dom[k] + 1]++;
+    for (int64_t g = 0; g < L.n; ++g) sc_ptr[g + 1] += sc_ptr[g];
+    sc_pos.resize(L.sum_n);
+    std::vector<int64_t> fill(sc_ptr.begin(), sc_ptr.end() - 1);
+    for (int64_t k = 0; k < L.sum_n; ++k) sc_pos[fill[m.dom[k]]++] = (int)k;
+  } else {
+    sc_pos.resize(L.n);
+    for (int64_t g = 0; g < L.n; ++g) {
+      const int i = m.owner[g];
+      const int* D = m.dom.data() + m.dom_ptr[i];
+      const int ni = L.dims[i];
+      const int a = (int)(std::lower_bound(D, D + ni, (int)g) - D);
+      if (a >= ni || D[a] != g) throw Error(GDSW_EINVAL, "owner part does not hold its dof");
+      sc_pos[g] = (int)(m.dom_ptr[i] + a);
+      sc_ptr[g + 1] = g + 1;
+    }
+  }
+  L.sc_ptr = upload(A, sc_ptr, s);
+  L.sc_pos = upload(A, sc_pos, s);
+  L.w = A.alloc_n<double>((size_t)L.sum_n);
+}
+
+// GDSW basis of the level and the Galerkin operator of the next one.
+template <typename T>
+CsrDev coarse_level(gdsw_ctx* C, Level& L, hipStream_t s, std::vector<int64_t>& a0_rowptr_h,
+                    std::vector<int>& a0_col_h) {
+  Arena& A = C->arena;
+  const LevelMaps& m = L.maps;
+  const int N = L.nparts;
+  L.has_coarse = true;
+  L.n_coarse = m.n_coarse;
+  L.int_ptr = upload(A, m.int_ptr, s);
+  L.inter = upload(A, m.inter, s);
+  L.dof_gcol = upload(A, m.dof_gcol, s);
+  L.dof_ipart = upload(A, m.dof_ipart, s);
+  L.dof_irow = upload(A, m.dof_irow, s);
+  L.pc_ptr = upload(A, m.pc_ptr, s);
+  L.pcols = upload(A, m.pcols, s);
+  L.cp_ptr = upload(A, m.cp_ptr, s);
+  L.cp_part = upload(A, m.cp_part, s);
+  L.cp_lc = upload(A, m.cp_lc, s);
+  L.col_ptr = upload(A, m.col_ptr, s);
+  L.col_dofs = upload(A, m.col_dofs, s);
+  int64_t* z_ptr = upload(A, m.z_ptr, s);
+  int* z_dof = upload(A, m.z_dof, s);
+  int* z_lc = upload(A, m.z_lc, s);
+  std::vector<int64_t> aii_off(N), phi_off(N + 1), v_off(N), c_off(N);
+  std::vector<int> ni(N), mi(N);
+  int64_t aii_tot = 0, phi_tot = 0, v_tot = 0, c_tot = 0;
+  int max_ni = 0, max_m = 0;
+  double iflops = 0.0;
+  for (int i = 0; i < N; ++i) {
+    const int nI = (int)(m.int_ptr[i + 1] - m.int_ptr[i]);
+    const int mm = (int)(m.pc_ptr[i + 1] - m.pc_ptr[i]);
+    const int nZ = (int)(m.z_ptr[i + 1] - m.z_ptr[i]);
+    ni[i] = nI;
+    mi[i] = mm;
+    aii_off[i] = aii_tot;
+    aii_tot += (int64_t)nI * nI;
+    phi_off[i] = phi_tot;
+    phi_tot += (int64_t)nI * mm;
+    v_off[i] = v_tot;
+    v_tot += (int64_t)nZ * mm;
+    c_off[i] = c_tot;
+    c_tot += (int64_t)mm * mm;
+    max_ni = std::max(max_ni, nI);
+    max_m = std::max(max_m, mm);
+    iflops += (2.0 / 3.0) * nI * (double)nI * nI + 2.0 * nI * (double)nI * mm;
+  }
+  phi_off[N] = phi_tot;
+  L.max_ni = max_ni;
+  L.interior_flops = iflops;
+  int64_t* d_aii_off = upload(A, aii_off, s);
+  L.phi_off = upload(A, phi_off, s);
+  int64_t* d_v_off = upload(A, v_off, s);
+  int64_t* d_c_off = upload(A, c_off, s);
+  int* d_ni = upload(A, ni, s);
+  int* d_mi = upload(A, mi, s);
+  T* aii = A.alloc_n<T>((size_t)aii_tot);
+  GDSW_HIP(hipMemsetAsync(aii, 0, (size_t)aii_tot * sizeof(T), s));
+  double* rhs = A.alloc_n<double>((size_t)phi_tot);
+  GDSW_HIP(hipMemsetAsync(rhs, 0, (size_t)phi_tot * sizeof(double), s));
+  int* bad = A.alloc_n<int>(1);
+  GDSW_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+  L.bad = bad;
+  extract_interior<T>(L.K, N, (int64_t)m.inter.size(), L.int_ptr, L.inter, L.dof_ipart, L.dof_irow, L.dof_gcol,
+                      L.pc_ptr, L.pcols, d_aii_off, aii, L.phi_off, rhs, bad, s);
+  int* ipiv = A.alloc_n<int>(m.inter.size());
+  L.iinfo = A.alloc_n<int>(N);
+  GDSW_HIP(hipMemsetAsync(L.iinfo, 0, N * sizeof(int), s));
+  LuBatch b;
+  b.count = N;
+  b.max_n = max_ni;
+  b.off = d_aii_off;
+  b.dim = d_ni;
+  b.piv = ipiv;
+  b.poff = L.int_ptr;
+  b.info = L.iinfo;
+  lu_batched<T>(b, aii, s);
+  T* phi;
+  if (sizeof(T) == sizeof(double)) {
+    phi = reinterpret_cast<T*>(rhs);
+  } else {
+    phi = A.alloc_n<T>((size_t)phi_tot);
+    convert<double, T>(rhs, phi, phi_tot, s);
+  }
+  lu_solve_batched<T>(b, aii, phi, L.phi_off, d_mi, max_m, s);
+  L.phi = phi;
+  // Galerkin product
+  double* W = A.alloc_n<double>((size_t)phi_tot);
+  double* V = A.alloc_n<double>((size_t)v_tot);
+  double* Cm = A.alloc_n<double>((size_t)c_tot);
+  galerkin_wv<T>(L.K, N, (int64_t)m.inter.size(), (int64_t)m.z_dof.size(), L.int_ptr, L.inter, L.dof_ipart,
+                 L.dof_irow, L.dof_gcol, L.pc_ptr, L.pcols, L.phi_off, phi, z_ptr, z_dof, d_v_off, W, V, bad, s);
+  galerkin_local<T>(N, (int64_t)m.pcols.size(), L.int_ptr, L.pc_ptr, L.phi_off, phi, W, z_ptr, z_lc, d_v_off, V,
+                    d_c_off, Cm, s);
+  coarse_pattern(m, a0_rowptr_h, a0_col_h);
+  CsrDev K0;
+  K0.n = m.n_coarse;
+  K0.nnz = (int64_t)a0_col_h.size();
+  int64_t* rp = upload(A, a0_rowptr_h, s);
+  int* cl = upload(A, a0_col_h, s);
+  double* val = A.alloc_n<double>((size_t)K0.nnz);
+  galerkin_assemble(L.K, L.col_ptr, L.col_dofs, L.dof_gcol, L.cp_ptr, L.cp_part, L.cp_lc, L.pc_ptr, L.pcols, d_c_off,
+                    Cm, rp, cl, val, m.n_coarse, bad, s);
+  K0.rowptr = rp;
+  K0.col = cl;
+  K0.val = val;
+  L.rc = A.alloc_n<double>(m.n_coarse);
+  L.yc = A.alloc_n<double>(m.n_coarse);
+  return K0;
+}
+
+void coarsest_inverse(gdsw_ctx* C, const CsrDev& K, hipStream_t s) {
+  Arena& A = C->arena;
+  const int n = (int)K.n;
+  C->nc = n;
+  double* D = A.alloc_n<double>((size_t)n * n);
+  GDSW_HIP(hipMemsetAsync(D, 0, (size_t)n * n * sizeof(double), s));
+  csr_to_dense(K, D, s);
+  std::vector<int64_t> off0 = {0};
+  std::vector<int> dim0 = {n};
+  int64_t* d_off = upload(A, off0, s);
+  int* d_dim = upload(A, dim0, s);
+  int* piv = A.alloc_n<int>(n);
+  int* info = A.alloc_n<int>(1);
+  GDSW_HIP(hipMemsetAsync(info, 0, sizeof(int), s));
+  LuBatch b;
+  b.count = 1;
+  b.max_n = n;
+  b.off = d_off;
+  b.dim = d_dim;
+  b.piv = piv;
+  b.poff = d_off;
+  b.info = info;
+  lu_batched<double>(b, D, s);
+  double* X = A.alloc_n<double>((size_t)n * n);
+  set_identity<double>(X, n, s);
+  lu_solve_batched<double>(b, D, X, d_off, d_dim, n, s);
+  C->ainv = X;
+  C->gemv_partial = A.alloc_n<double>((size_t)dense_gemv_partials(n));
+  int hinfo = 0;
+  GDSW_HIP(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, s));
+  GDSW_HIP(hipStreamSynchronize(s));
+  A.free_one(D);
+  if (hinfo != 0)
+    throw Error(GDSW_ESINGULAR, "coarsest operator (order " + std::to_string(n) + ") has a zero pivot at column " +
+                                    std::to_string(hinfo - 1));
+}
+
+void check_info(const int* dinfo, int N, const std::string& what, int level, hipStream_t s) {
+  std::vector<int> h(N);
+  GDSW_HIP(hipMemcpyAsync(h.data(), dinfo, N * sizeof(int), hipMemcpyDeviceToHost, s));
+  GDSW_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < N; ++i)
+    if (h[i] != 0)
+      throw Error(GDSW_ESINGULAR, what + " of level " + std::to_string(level) + ", part " + std::to_string(i) +
+                                      " has a zero pivot at column " + std::to_string(h[i] - 1));
+}
+
+struct Plan {
+  std::vector<LevelMesh> meshes;
+  std::vector<LevelMaps> maps;
+  int schwarz = 0;        // levels with local solves
+  bool coarsest = false;  // a direct coarsest level follows
+};
+
+void validate_problem(const gdsw_problem* p) {
+  if (!p) throw Error(GDSW_EINVAL, "problem is NULL");
+  if (p->levels < 2 || p->levels > 8) throw Error(GDSW_EINVAL, "levels must be in [2, 8]");
+  if (!p->n_parts || !p->node_dof || !p->elem_node || !p->elem_pdof || !p->elem_part)
+    throw Error(GDSW_EINVAL, "a required host array is NULL");
+  if (p->levels > 2 && !p->part_parent) throw Error(GDSW_EINVAL, "part_parent is NULL");
+}
+
+Plan plan_levels(const gdsw_problem* p, const gdsw_options& o) {
+  validate_problem(p);
+  Plan P;
+  P.meshes.emplace_back();
+  std::string err = build_level1_mesh(p->n, p->n_nodes, p->node_dof, p->n_elem, p->elem_node, p->elem_pdof,
+                                      p->elem_part, p->n_parts[0], P.meshes[0]);
+  if (!err.empty()) throw Error(GDSW_EINVAL, err);
+  const int L = p->levels;
+  for (int l = 1; l < L; ++l) {
+    P.maps.emplace_back();
+    build_maps(P.meshes[l - 1], o.overlap, P.maps.back());
+    P.schwarz = l;
+    const bool last = (l == L - 1);
+    if (last) {
+      P.coarsest = !o.no_coarse;
+      break;
+    }
+    if (P.maps.back().n_coarse == 0) throw Error(GDSW_EINVAL, "coarse space of level " + std::to_string(l) + " is empty");
+    const int nxt = p->n_parts[l];
+    if (nxt <= 0) throw Error(GDSW_EINVAL, "n_parts must be positive");
+    P.meshes.emplace_back();
+    err = build_next_mesh(P.meshes[l - 1], P.maps.back(), p->part_parent[l - 1], nxt, P.meshes[l]);
+    if (!err.empty()) throw Error(GDSW_EINVAL, err);
+    if (nxt == 1) {          // a single part: this coarse problem becomes the coarsest
+      P.coarsest = true;
+      break;
+    }
+  }
+  if (P.coarsest && P.maps.back().n_coarse == 0) throw Error(GDSW_EINVAL, "coarsest space is empty");
+  return P;
+}
+
+template <typename T>
+void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
+  const double t0 = now_ms();
+  Plan P = plan_levels(p, C->opt);
+  const double t1 = now_ms();
+  gdsw_stats& st = C->stats;
+  std::memset(&st, 0, sizeof(st));
+  st.ms_maps = t1 - t0;
+  // level-1 operator: a private copy of the caller's CSR
+  CsrDev K;
+  K.n = p->n;
+  int64_t nnz = 0;
+  GDSW_HIP(hipMemcpyAsync(&nnz, p->rowptr + p->n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  GDSW_HIP(hipStreamSynchronize(s));
+  if (nnz <= 0) throw Error(GDSW_EINVAL, "K has no nonzero");
+  K.nnz = nnz;
+  {
+    int64_t* rp = C->arena.alloc_n<int64_t>(p->n + 1);
+    int* cl = C->arena.alloc_n<int>((size_t)nnz);
+    double* vl = C->arena.alloc_n<double>((size_t)nnz);
+    GDSW_HIP(hipMemcpyAsync(rp, p->rowptr, (p->n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    GDSW_HIP(hipMemcpyAsync(cl, p->col, nnz * sizeof(int), hipMemcpyDeviceToDevice, s));
+    GDSW_HIP(hipMemcpyAsync(vl, p->val, nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+    K.rowptr = rp;
+    K.col = cl;
+    K.val = vl;
+  }
+  C->levels.resize(P.schwarz);
+  hipEvent_t ev[3];
+  for (auto& e : ev) GDSW_HIP(hipEventCreate(&e));
+  GDSW_HIP(hipEventRecord(ev[0], s));
+  float ms_factor = 0, ms_basis = 0;
+  for (int l = 0; l < P.schwarz; ++l) {
+    Level& L = C->levels[l];
+    L.index = l + 1;
+    L.nparts = P.meshes[l].n_parts;
+    L.n = K.n;
+    L.K = K;
+    L.maps = std::move(P.maps[l]);
+    factor_level<T>(C, L, s);
+    GDSW_HIP(hipEventRecord(ev[1], s));
+    st.n[l] = L.n;
+    st.parts[l] = L.nparts;
+    st.sum_ni[l] = L.sum_n;
+    st.max_ni[l] = L.max_n;
+    st.factor_bytes[l] = L.sum_n2 * (int64_t)sizeof(T);
+    st.nnz[l] = K.nnz;
+    double f = 0;
+    for (int d : L.dims) f += (2.0 / 3.0) * d * (double)d * d;
+    st.factor_flops[l] = f;
+    const bool needs_coarse = (l + 1 < P.schwarz) || P.coarsest;
+    if (needs_coarse) {
+      std::vector<int64_t> rp;
+      std::vector<int> cl;
+      K = coarse_level<T>(C, L, s, rp, cl);
+      st.interior_flops[l] = L.interior_flops;
+    }
+    GDSW_HIP(hipEventRecord(ev[2], s));
+    GDSW_HIP(hipEventSynchronize(ev[2]));
+    float a = 0, b = 0;
+    GDSW_HIP(hipEventElapsedTime(&a, ev[0], ev[1]));
+    GDSW_HIP(hipEventElapsedTime(&b, ev[1], ev[2]));
+    ms_factor += a;
+    ms_basis += b;
+    GDSW_HIP(hipEventRecord(ev[0], s));
+    check_info(L.info, L.nparts, "local block", L.index, s);
+    if (L.has_coarse) {
+      check_info(L.iinfo, L.nparts, "interior block", L.index, s);
+      int hb = 0;
+      GDSW_HIP(hipMemcpyAsync(&hb, L.bad, sizeof(int), hipMemcpyDeviceToHost, s));
+      GDSW_HIP(hipStreamSynchronize(s));
+      if (hb)
+        throw Error(GDSW_EINVAL, "level " + std::to_string(L.index) +
+                                     ": K couples dofs that share no element (not an element-assembled operator)");
+    }
+  }
+  st.levels = P.schwarz + (P.coarsest ? 1 : 0);
+  {
+    const Level& L1 = C->levels[0];
+    double bytes = 0;
+    for (int d : L1.dims) bytes += (double)d * d * sizeof(T) + 20.0 * d;
+    st.local_solve_bytes = bytes;
+  }
+  if (P.coarsest) {
+    C->has_coarsest = true;
+    C->nnz_coarsest = K.nnz;
+    const double tc = now_ms();
+    coarsest_inverse(C, K, s);
+    st.ms_coarse = now_ms() - tc;
+    st.n[P.schwarz] = K.n;
+    st.nnz[P.schwarz] = K.nnz;
+    st.factor_flops[P.schwarz] = (2.0 / 3.0) * K.n * (double)K.n * K.n + 2.0 * K.n * (double)K.n * K.n;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  st.ms_factor = ms_factor;
+  st.ms_basis = ms_basis;
+  st.ms_total = now_ms() - t0;
+}
+
+hipEvent_t next_event(gdsw_ctx* C) {
+  if (C->ev_used == C->ev_pool.size()) {
+    hipEvent_t e;
+    GDSW_HIP(hipEventCreate(&e));
+    C->ev_pool.push_back(e);
+  }
+  return C->ev_pool[C->ev_used++];
+}
+
+// Sum the recorded launch durations into the statistics and recycle the events.
+void drain_events(gdsw_ctx* C) {
+  for (size_t k = 0; k + 1 < C->ev_used; k += 2) {
+    GDSW_HIP(hipEventSynchronize(C->ev_pool[k + 1]));
+    float ms = 0;
+    GDSW_HIP(hipEventElapsedTime(&ms, C->ev_pool[k], C->ev_pool[k + 1]));
+    C->stats.ms_local_solve += ms;
+    C->stats.local_solve_launches++;
+  }
+  C->ev_used = 0;
+}
+
+template <typename T>
+void apply_level(gdsw_ctx* C, int l, const double* r, double* z, hipStream_t s) {
+  Level& L = C->levels[l];
+  const bool prof = C->opt.profile && l == 0;
+  if (prof) {
+    if (C->ev_used + 2 > 4096) drain_events(C);
+    GDSW_HIP(hipEventRecord(next_event(C), s));
+  }
+  local_solves<T>(L.nparts, L.max_n, L.dom_ptr, L.gidx, L.blk_off, static_cast<const T*>(L.blocks), r, L.w, s);
+  if (prof) GDSW_HIP(hipEventRecord(next_event(C), s));
+  scatter_sum(L.n, L.sc_ptr, L.sc_pos, L.w, z, s);
+  if (!L.has_coarse) return;
+  const T* phi = static_cast<const T*>(L.phi);
+  restrict_phi<T>(L.n_coarse, L.col_ptr, L.col_dofs, L.cp_ptr, L.cp_part, L.cp_lc, L.int_ptr, L.inter, L.phi_off, phi,
+                  r, L.rc, s);
+  if (l + 1 < (int)C->levels.size()) apply_level<T>(C, l + 1, L.rc, L.yc, s);
+  else dense_gemv(C->nc, C->ainv, L.rc, L.yc, C->gemv_partial, s);
+  prolong_add<T>(L.n, L.dof_gcol, L.dof_ipart, L.dof_irow, L.int_ptr, L.pc_ptr, L.pcols, L.phi_off, phi, L.yc, z, s);
+}
+
+void apply_any(gdsw_ctx* C, const double* r, double* z, hipStream_t s) {
+  if (C->mixed) apply_level<float>(C, 0, r, z, s);
+  else apply_level<double>(C, 0, r, z, s);
+}
+
+void ensure_workspace(gdsw_ctx* C) {
+  const int m = C->opt.restart;
+  if (C->ws_m == m) return;
+  const int64_t n = C->levels[0].n;
+  Arena& A = C->arena;
+  C->V = A.alloc_n<double>((size_t)n * (m + 1));
+  C->Z = A.alloc_n<double>((size_t)n * m);
+  C->wv = A.alloc_n<double>((size_t)n);
+  C->dpart = A.alloc_n<double>((size_t)multi_dot_blocks(n) * (m + 2));
+  C->hdev = A.alloc_n<double>((size_t)2 * (m + 2) + 2);
+  C->ydev = A.alloc_n<double>((size_t)m + 1);
+  if (!C->hhost) GDSW_HIP(hipHostMalloc((void**)&C->hhost, sizeof(double) * (2 * 256 + 8), hipHostMallocDefault));
+  C->ws_m = m;
+}
+
+int solve_impl(gdsw_ctx* C, const double* b, double* x, hipStream_t s, gdsw_solve_info* info) {
+  const double t0 = now_ms();
+  ensure_workspace(C);
+  const int m = C->opt.restart;
+  const int64_t n = C->levels[0].n;
+  const CsrDev& K = C->levels[0].K;
+  double* V = C->V;
+  double* Z = C->Z;
+  double* w = C->wv;
+  double* h1 = C->hdev;               // [m+1]
+  double* h2 = C->hdev + (m + 1);     // [m+1]
+  double* nr = C->hdev + 2 * (m + 1); // [1]
+  double* hh = C->hhost;
+  auto fetch = [&](int count) {
+    GDSW_HIP(hipMemcpyAsync(hh, C->hdev, count * sizeof(double), hipMemcpyDeviceToHost, s));
+    GDSW_HIP(hipStreamSynchronize(s));
+  };
+  multi_dot(n, 1, b, n, b, C->dpart, nr, s);
+  GDSW_HIP(hipMemcpyAsync(hh, nr, sizeof(double), hipMemcpyDeviceToHost, s));
+  GDSW_HIP(hipStreamSynchronize(s));
+  const double bnorm = std::sqrt(hh[0]);
+  GDSW_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s));
+  gdsw_solve_info inf;
+  std::memset(&inf, 0, sizeof(inf));
+  if (bnorm == 0.0) {
+    inf.converged = 1;
+    if (info) *info = inf;
+    return GDSW_OK;
+  }
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  int its = 0;
+  double ms_apply = 0, ms_spmv = 0, ms_orth = 0;
+  const bool timing = std::getenv("GDSW_PHASE_TIMING") != nullptr;
+  auto tick = [&](double& acc, double& last) {
+    if (!timing) return;
+    GDSW_HIP(hipStreamSynchronize(s));
+    const double t = now_ms();
+    acc += t - last;
+    last = t;
+  };
+  while (true) {
+    spmv(K, x, V, s);
+    residual_from(n, b, V, s);
+    multi_dot(n, 1, V, n, V, C->dpart, nr, s);
+    GDSW_HIP(hipMemcpyAsync(hh, nr, sizeof(double), hipMemcpyDeviceToHost, s));
+    GDSW_HIP(hipStreamSynchronize(s));
+    const double beta = std::sqrt(hh[0]);
+    inf.rel_residual = beta / bnorm;
+    if (inf.rel_residual <= C->opt.tol) {
+      inf.converged = 1;
+      break;
+    }
+    if (its >= C->opt.max_it) break;
+    scale_by_inv_norm(n, V, nr, V, s);
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      double last = now_ms(), dummy = 0;
+      if (timing) {
+        GDSW_HIP(hipStreamSynchronize(s));
+        last = now_ms();
+      }
+      double* vj = V + (int64_t)j * n;
+      double* zj = Z + (int64_t)j * n;
+      apply_any(C, vj, zj, s);
+      tick(ms_apply, last);
+      spmv(K, zj, w, s);
+      tick(ms_spmv, last);
+      multi_dot(n, j + 1, V, n, w, C->dpart, h1, s);
+      multi_axpy(n, j + 1, V, n, h1, w, s);
+      multi_dot(n, j + 1, V, n, w, C->dpart, h2, s);
+      multi_axpy(n, j + 1, V, n, h2, w, s);
+      multi_dot(n, 1, w, n, w, C->dpart, nr, s);
+      scale_by_inv_norm(n, w, nr, V + (int64_t)(j + 1) * n, s);
+      fetch(2 * (m + 1) + 1);
+      tick(ms_orth, last);
+      (void)dummy;
+      double* Hj = H.data() + (size_t)j * (m + 1);
+      for (int i = 0; i <= j; ++i) Hj[i] = hh[i] + hh[(m + 1) + i];
+      Hj[j + 1] = std::sqrt(hh[2 * (m + 1)]);
+      const bool breakdown = Hj[j + 1] == 0.0;
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * Hj[i] + sn[i] * Hj[i + 1];
+        Hj[i + 1] = -sn[i] * Hj[i] + cs[i] * Hj[i + 1];
+        Hj[i] = t;
+      }
+      const double den = std::hypot(Hj[j], Hj[j + 1]);
+      cs[j] = den > 0 ? Hj[j] / den : 1.0;
+      sn[j] = den > 0 ? Hj[j + 1] / den : 0.0;
+      Hj[j] = den;
+      Hj[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++its;
+      k = j + 1;
+      if (std::fabs(g[j + 1]) / bnorm <= C->opt.tol || its >= C->opt.max_it || breakdown) break;
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int q = i + 1; q < k; ++q) t -= H[(size_t)q * (m + 1) + i] * y[q];
+      const double d = H[(size_t)i * (m + 1) + i];
+      y[i] = d != 0.0 ? t / d : 0.0;
+    }
+    for (int i = 0; i < k; ++i) hh[i] = -y[i];
+    GDSW_HIP(hipMemcpyAsync(C->ydev, hh, k * sizeof(double), hipMemcpyHostToDevice, s));
+    multi_axpy(n, k, Z, n, C->ydev, x, s);
+    GDSW_HIP(hipStreamSynchronize(s));   // the host buffer is reused by the next fetch
+    inf.restarts++;
+  }
+  inf.iterations = its;
+  inf.ms_apply = ms_apply;
+  inf.ms_spmv = ms_spmv;
+  inf.ms_orth = ms_orth;
+  inf.ms_total = now_ms() - t0;
+  if (info) *info = inf;
+  return inf.converged ? GDSW_OK : GDSW_NOTCONV;
+}
+
+int fail(const Error& e) {
+  g_last_error = e.what();
+  return e.code;
+}
+
+}  // namespace
+}  // namespace gdsw
+
+using gdsw::Error;
+
+extern "C" {
+
+void gdsw_default_options(gdsw_options* o) {
+  if (!o) return;
+  o->overlap = 1;
+  o->combine = GDSW_COMBINE_RESTRICTED;
+  o->precision = GDSW_FP64;
+  o->restart = 30;
+  o->max_it = 1000;
+  o->tol = 1e-8;
+  o->no_coarse = 0;
+  o->panel = 0;
+  o->profile = 0;
+}
+
+const char* gdsw_last_error(void) { return gdsw::g_last_error.c_str(); }
+
+int gdsw_setup(const gdsw_problem* prob, const gdsw_options* opt, void* stream, gdsw_ctx** out) {
+  if (!out) {
+    gdsw::g_last_error = "out is NULL";
+    return GDSW_EINVAL;
+  }
+  *out = nullptr;
+  gdsw_ctx* C = new (std::nothrow) gdsw_ctx();
+  if (!C) {
+    gdsw::g_last_error = "host allocation failed";
+    return GDSW_ENOMEM;
+  }
+  try {
+    gdsw_default_options(&C->opt);
+    if (opt) C->opt = *opt;
+    if (C->opt.overlap < 0 || C->opt.restart < 1 || C->opt.restart > 250 || C->opt.max_it < 0 ||
+        !(C->opt.tol >= 0.0) || (C->opt.combine != 0 && C->opt.combine != 1) ||
+        (C->opt.precision != 0 && C->opt.precision != 1))
+      throw Error(GDSW_EINVAL, "invalid options");
+    C->mixed = C->opt.precision == GDSW_MIXED;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (C->mixed) gdsw::setup_impl<float>(C, prob, s);
+    else gdsw::setup_impl<double>(C, prob, s);
+    GDSW_HIP(hipStreamSynchronize(s));
+  } catch (const Error& e) {
+    delete C;
+    return gdsw::fail(e);
+  } catch (const std::bad_alloc&) {
+    delete C;
+    gdsw::g_last_error = "host allocation failed";
+    return GDSW_ENOMEM;
+  }
+  *out = C;
+  return GDSW_OK;
+}
+
+int gdsw_apply(gdsw_ctx* C, const double* r, double* z, void* stream) {
+  if (!C || !r || !z || r == z) {
+    gdsw::g_last_error = "gdsw_apply: NULL or aliased argument";
+    return GDSW_EINVAL;
+  }
+  try {
+    gdsw::apply_any(C, r, z, static_cast<hipStream_t>(stream));
+  } catch (const Error& e) {
+    return gdsw::fail(e);
+  }
+  return GDSW_OK;
+}
+
+int gdsw_solve(gdsw_ctx* C, const double* b, double* x, void* stream, gdsw_solve_info* info) {
+  if (!C || !b || !x || b == x) {
+    gdsw::g_last_error = "gdsw_solve: NULL or aliased argument";
+    return GDSW_EINVAL;
+  }
+  try {
+    return gdsw::solve_impl(C, b, x, static_cast<hipStream_t>(stream), info);
+  } catch (const Error& e) {
+    return gdsw::fail(e);
+  }
+}
+
+int gdsw_spmv(gdsw_ctx* C, const double* x, double* y, void* stream) {
+  if (!C || !x || !y) {
+    gdsw::g_last_error = "gdsw_spmv: NULL argument";
+    return GDSW_EINVAL;
+  }
+  try {
+    gdsw::spmv(C->levels[0].K, x, y, static_cast<hipStream_t>(stream));
+  } catch (const Error& e) {
+    return gdsw::fail(e);
+  }
+  return GDSW_OK;
+}
+
+int gdsw_scatter_local(gdsw_ctx* C, int32_t level, const double* w, double* z, void* stream) {
+  if (!C || !w || !z || level < 1 || level > (int)C->levels.size()) {
+    gdsw::g_last_error = "gdsw_scatter_local: bad argument";
+    return GDSW_EINVAL;
+  }
+  try {
+    gdsw::Level& L = C->levels[level - 1];
+    gdsw::scatter_sum(L.n, L.sc_ptr, L.sc_pos, w, z, static_cast<hipStream_t>(stream));
+  } catch (const Error& e) {
+    return gdsw::fail(e);
+  }
+  return GDSW_OK;
+}
+
+static void fill_view(const gdsw::LevelMaps& m, int64_t n_dof, int nparts, gdsw_maps_view* out) {
+  out->n_dof = (int32_t)n_dof;
+  out->n_parts = nparts;
+  out->dom_ptr = m.dom_ptr.data();
+  out->dom = m.dom.data();
+  out->int_ptr = m.int_ptr.data();
+  out->inter = m.inter.data();
+  out->n_gamma_nodes = (int32_t)m.gamma_nodes.size();
+  out->gamma_nodes = m.gamma_nodes.data();
+  out->n_entities = (int32_t)m.ent_kind.size();
+  out->ent_ptr = m.ent_ptr.data();
+  out->ent_nodes = m.ent_nodes.data();
+  out->ent_kind = m.ent_kind.data();
+  out->n_coarse = m.n_coarse;
+  out->col_entity = m.col_entity.data();
+  out->col_dir = m.col_dir.data();
+  out->owner = m.owner.data();
+}
+
+int gdsw_export_maps(gdsw_ctx* C, int32_t level, gdsw_maps_view* out) {
+  if (!C || !out || level < 1 || level > (int)C->levels.size()) {
+    gdsw::g_last_error = "gdsw_export_maps: bad argument";
+    return GDSW_EINVAL;
+  }
+  const gdsw::Level& L = C->levels[level - 1];
+  fill_view(L.maps, L.n, L.nparts, out);
+  return GDSW_OK;
+}
+
+struct gdsw_plan {
+  gdsw::Plan P;
+};
+
+int gdsw_plan_create(const gdsw_problem* prob, const gdsw_options* opt, gdsw_plan** out) {
+  if (!out) {
+    gdsw::g_last_error = "out is NULL";
+    return GDSW_EINVAL;
+  }
+  *out = nullptr;
+  try {
+    gdsw_options o;
+    gdsw_default_options(&o);
+    if (opt) o = *opt;
+    gdsw_plan* p = new gdsw_plan();
+    try {
+      p->P = gdsw::plan_levels(prob, o);
+    } catch (...) {
+      delete p;
+      throw;
+    }
+    *out = p;
+  } catch (const Error& e) {
+    return gdsw::fail(e);
+  } catch (const std::bad_alloc&) {
+    gdsw::g_last_error = "host allocation failed";
+    return GDSW_ENOMEM;
+  }
+  return GDSW_OK;
+}
+
+int gdsw_plan_levels(gdsw_plan* plan, int32_t* schwarz_levels, int32_t* has_coarsest) {
+  if (!plan) {
+    gdsw::g_last_error = "plan is NULL";
+    return GDSW_EINVAL;
+  }
+  if (schwarz_levels) *schwarz_levels = plan->P.schwarz;
+  if (has_coarsest) *has_coarsest = plan->P.coarsest ? 1 : 0;
+  return GDSW_OK;
+}
+
+int gdsw_plan_maps(gdsw_plan* plan, int32_t level, gdsw_maps_view* out) {
+  if (!plan || !out || level < 1 || level > (int)plan->P.maps.size()) {
+    gdsw::g_last_error = "gdsw_plan_maps: bad argument";
+    return GDSW_EINVAL;
+  }
+  const gdsw::LevelMesh& mesh = plan->P.meshes[level - 1];
+  fill_view(plan->P.maps[level - 1], mesh.n_dof, mesh.n_parts, out);
+  return GDSW_OK;
+}
+
+void gdsw_plan_destroy(gdsw_plan* plan) { delete plan; }
+
+int gdsw_get_stats(gdsw_ctx* C, gdsw_stats* out) {
+  if (!C || !out) {
+    gdsw::g_last_error = "gdsw_get_stats: NULL argument";
+    return GDSW_EINVAL;
+  }
+  try {
+    gdsw::drain_events(C);
+  } catch (const Error& e) {
+    return gdsw::fail(e);
+  }
+  *out = C->stats;
+  return GDSW_OK;
+}
+
+size_t gdsw_footprint_bytes(const gdsw_problem* prob, const gdsw_options* opt) {
+  try {
+    gdsw_options o;
+    gdsw_default_options(&o);
+    if (opt) o = *opt;
+    gdsw::Plan P = gdsw::plan_levels(prob, o);
+    const size_t s = (o.precision == GDSW_MIXED) ? 4 : 8;
+    size_t total = 0;
+    size_t n_last = 0;
+    for (size_t l = 0; l < P.maps.size(); ++l) {
+      const gdsw::LevelMaps& m = P.maps[l];
+      const size_t N = m.dom_ptr.size() - 1;
+      size_t n2 = 0, sn = 0;
+      for (size_t i = 0; i < N; ++i) {
+        const size_t ni = (size_t)(m.dom_ptr[i + 1] - m.dom_ptr[i]);
+        n2 += ni * ni;
+        sn += ni;
+      }
+      total += n2 * s + sn * 24;
+      size_t phi = 0;
+      for (size_t i = 0; i < N; ++i)
+        phi += (size_t)(m.int_ptr[i + 1] - m.int_ptr[i]) * (size_t)(m.pc_ptr[i + 1] - m.pc_ptr[i]);
+      total += phi * (s + 8) + m.owner.size() * 24;
+      n_last = (size_t)m.n_coarse;
+    }
+    if (P.coarsest) total += 2 * n_last * n_last * 8;
+    const size_t n = (size_t)prob->n;
+    total += (size_t)(o.restart * 2 + 4) * n * 8;
+    return total;
+  } catch (...) {
+    return 0;
+  }
+}
+
+void gdsw_destroy(gdsw_ctx* C) {
+  if (!C) return;
+  if (C->hhost) (void)hipHostFree(C->hhost);
+  delete C;
+}
+
+}  // extern "C"

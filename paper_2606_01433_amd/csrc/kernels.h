@@ -1,0 +1,108 @@
+// Host-callable launchers of the HIP kernels (all enqueue on the given stream).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gdsw {
+
+constexpr int LU_NB = 32;   // LU panel width
+
+// A batch of dense column-major square matrices with per-matrix order (ld = order).
+struct LuBatch {
+  int count = 0;
+  int max_n = 0;
+  const int64_t* off = nullptr;    // element offset of matrix i
+  const int* dim = nullptr;        // order of matrix i
+  int* piv = nullptr;              // pivots, matrix i at poff[i]
+  const int64_t* poff = nullptr;
+  int* info = nullptr;             // first zero pivot (1-based) or 0
+};
+
+template <typename T> void lu_batched(const LuBatch& b, T* A, hipStream_t s);
+template <typename T>
+void lu_solve_batched(const LuBatch& b, const T* A, T* X, const int64_t* xoff, const int* nrhs, int max_rhs,
+                      hipStream_t s);
+void lu_build_perm(const LuBatch& b, int* perm, hipStream_t s);
+
+// ---- setup ----------------------------------------------------------------
+struct CsrDev {
+  int64_t n = 0;
+  int64_t nnz = 0;
+  const int64_t* rowptr = nullptr;
+  const int* col = nullptr;
+  const double* val = nullptr;
+};
+
+// Dense local blocks A_i = K[D_i, D_i] (blocks pre-zeroed).
+template <typename T>
+void extract_blocks(const CsrDev& K, int nparts, int64_t total_rows, const int64_t* dom_ptr, const int* dom,
+                    const int64_t* blk_off, T* blocks, hipStream_t s);
+// Interior blocks K[I_i, I_i] and right-hand sides -K[I_i, Gamma] Phi_Gamma (both pre-zeroed).
+template <typename T>
+void extract_interior(const CsrDev& K, int nparts, int64_t total_rows, const int64_t* int_ptr, const int* inter,
+                      const int* dof_ipart, const int* dof_irow, const int* dof_gcol, const int64_t* pc_ptr,
+                      const int* pcols, const int64_t* aii_off, T* aii, const int64_t* rhs_off, double* rhs,
+                      int* bad, hipStream_t s);
+// gidx[k] = D_i[perm_i[a]] for the pivoted gather of the local solves.
+void make_gather_index(int nparts, int64_t total, const int64_t* dom_ptr, const int* dom, const int* perm,
+                       int* gidx, hipStream_t s);
+// Galerkin pieces of part i: W = K[I_i, :] Phi (|I_i| x m_i), V = K[Z_i, I_i] Phi_I (|Z_i| x m_i).
+template <typename T>
+void galerkin_wv(const CsrDev& K, int nparts, int64_t total_irows, int64_t total_zrows, const int64_t* int_ptr,
+                 const int* inter, const int* dof_ipart, const int* dof_irow, const int* dof_gcol,
+                 const int64_t* pc_ptr, const int* pcols, const int64_t* phi_off, const T* phi,
+                 const int64_t* z_ptr, const int* z_dof, const int64_t* v_off, double* W, double* V,
+                 int* bad, hipStream_t s);
+// C_i = Phi_I^T W + (V rows summed into their columns), m_i x m_i, column-major.
+template <typename T>
+void galerkin_local(int nparts, int64_t total_crows, const int64_t* int_ptr, const int64_t* pc_ptr,
+                    const int64_t* phi_off, const T* phi, const double* W, const int64_t* z_ptr, const int* z_lc,
+                    const int64_t* v_off, const double* V, const int64_t* c_off, double* C, hipStream_t s);
+// A_0 values: interface-interface couplings of K, then every part's C_i in ascending part order.
+// The kernels taking `bad` set it to 1 if K couples dofs that share no element of the level
+// (the Galerkin decomposition then does not apply; setup reports GDSW_EINVAL).
+void galerkin_assemble(const CsrDev& K, const int64_t* col_ptr, const int* col_dofs, const int* dof_gcol,
+                       const int64_t* cp_ptr, const int* cp_part, const int* cp_lc, const int64_t* pc_ptr,
+                       const int* pcols, const int64_t* c_off, const double* C, const int64_t* a0_rowptr, const int* a0_col,
+                       double* a0_val, int n_coarse, int* bad, hipStream_t s);
+// Dense column-major copy of a CSR matrix (pre-zeroed).
+void csr_to_dense(const CsrDev& K, double* D, hipStream_t s);
+template <typename T> void set_identity(T* X, int n, hipStream_t s);
+template <typename S, typename D> void convert(const S* in, D* out, int64_t n, hipStream_t s);
+
+// ---- apply ----------------------------------------------------------------
+// w[k] = local solutions: per part, gather r at gidx, forward/backward TRSV with the LU in place.
+template <typename T>
+void local_solves(int nparts, int max_n, const int64_t* dom_ptr, const int* gidx, const int64_t* blk_off,
+                  const T* blocks, const double* r, double* w, hipStream_t s);
+// z[g] = 0.0 + sum_k w[pos[k]] over sc_ptr[g]..sc_ptr[g+1]
+void scatter_sum(int64_t n, const int64_t* sc_ptr, const int* sc_pos, const double* w, double* z, hipStream_t s);
+// rc = Phi^T r
+template <typename T>
+void restrict_phi(int n_coarse, const int64_t* col_ptr, const int* col_dofs, const int64_t* cp_ptr,
+                  const int* cp_part, const int* cp_lc, const int64_t* int_ptr, const int* inter,
+                  const int64_t* phi_off, const T* phi, const double* r, double* rc, hipStream_t s);
+// z += Phi y
+template <typename T>
+void prolong_add(int64_t n, const int* dof_gcol, const int* dof_ipart, const int* dof_irow, const int64_t* int_ptr,
+                 const int64_t* pc_ptr, const int* pcols, const int64_t* phi_off, const T* phi, const double* y,
+                 double* z, hipStream_t s);
+// y = Ainv x for a dense n x n column-major matrix (two passes, deterministic).
+void dense_gemv(int n, const double* Ainv, const double* x, double* y, double* partial, hipStream_t s);
+int dense_gemv_partials(int n);
+
+// ---- Krylov ---------------------------------------------------------------
+void spmv(const CsrDev& K, const double* x, double* y, hipStream_t s);
+// h[c] = V[:, c] . w for c < ncols (V column-major, ld n); partial has blocks*ncols doubles.
+void multi_dot(int64_t n, int ncols, const double* V, int64_t ldv, const double* w, double* partial, double* h,
+               hipStream_t s);
+int multi_dot_blocks(int64_t n);
+// w -= V[:, 0..ncols) h
+void multi_axpy(int64_t n, int ncols, const double* V, int64_t ldv, const double* h, double* w, hipStream_t s);
+// y = alpha * x   (alpha read from device: 1 / sqrt(*nrm2))
+void scale_by_inv_norm(int64_t n, const double* x, const double* nrm2, double* y, hipStream_t s);
+// y = b - y
+void residual_from(int64_t n, const double* b, double* y, hipStream_t s);
+
+}  // namespace gdsw

@@ -1,0 +1,127 @@
+// Kernels of the FGMRES(m) iteration (section 3): CSR SpMV with K,
+// classical Gram-Schmidt with reorthogonalisation (dot blocks and AXPY
+// blocks), norms and scaling.  Reductions use a fixed two-pass tree, so the
+// results do not depend on scheduling.
+#include "common.h"
+#include "kernels.h"
+
+namespace gdsw {
+
+namespace {
+
+constexpr int DOT_BLOCK_ROWS = 4096;
+constexpr int DOT_MAXC = 32;
+
+__global__ __launch_bounds__(256) void k_spmv(CsrDev K, const double* __restrict__ x, double* __restrict__ y) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= K.n) return;
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int64_t e = K.rowptr[row] + lane; e < K.rowptr[row + 1]; e += 64) s += K.val[e] * x[K.col[e]];
+  s = wave_sum(s);
+  if (lane == 0) y[row] = s;
+}
+
+// partial[b * ncols + c] = sum over this block's rows of V[r, c0 + c] w[r]
+__global__ __launch_bounds__(256) void k_multi_dot_partial(int64_t n, int ncols, const double* __restrict__ V,
+                                                           int64_t ldv, const double* __restrict__ w,
+                                                           double* __restrict__ partial) {
+  __shared__ double red[4][DOT_MAXC];
+  const int64_t r0 = (int64_t)blockIdx.x * DOT_BLOCK_ROWS;
+  const int64_t r1 = min(n, r0 + DOT_BLOCK_ROWS);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int c0 = 0; c0 < ncols; c0 += DOT_MAXC) {
+    const int nc = min(DOT_MAXC, ncols - c0);
+    double acc[DOT_MAXC];
+#pragma unroll
+    for (int c = 0; c < DOT_MAXC; ++c) acc[c] = 0.0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+      const double wr = w[r];
+#pragma unroll
+      for (int c = 0; c < DOT_MAXC; ++c)
+        if (c < nc) acc[c] += V[r + (int64_t)(c0 + c) * ldv] * wr;
+    }
+#pragma unroll
+    for (int c = 0; c < DOT_MAXC; ++c) {
+      if (c < nc) {
+        const double t = wave_sum(acc[c]);
+        if (lane == 0) red[wid][c] = t;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < nc) {
+      const int c = threadIdx.x;
+      partial[(int64_t)blockIdx.x * ncols + c0 + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_multi_dot_reduce(int nblocks, int ncols, const double* __restrict__ partial, double* __restrict__ h) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * ncols + c];
+  h[c] = s;
+}
+
+__global__ __launch_bounds__(256) void k_multi_axpy(int64_t n, int ncols, const double* __restrict__ V, int64_t ldv,
+                                                    const double* __restrict__ h, double* __restrict__ w) {
+  __shared__ double hs[256];
+  for (int c = threadIdx.x; c < ncols && c < 256; c += blockDim.x) hs[c] = h[c];
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double acc = 0.0;
+  for (int c = 0; c < ncols; ++c) acc += V[r + (int64_t)c * ldv] * hs[c];
+  w[r] -= acc;
+}
+
+__global__ void k_scale_inv_norm(int64_t n, const double* __restrict__ x, const double* __restrict__ nrm2,
+                                 double* __restrict__ y) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const double nr = sqrt(nrm2[0]);
+  y[r] = (nr > 0.0) ? x[r] / nr : 0.0;
+}
+
+__global__ void k_residual_from(int64_t n, const double* __restrict__ b, double* __restrict__ y) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) y[r] = b[r] - y[r];
+}
+
+}  // namespace
+
+void spmv(const CsrDev& K, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_spmv, dim3(blocks_for(K.n, 4)), dim3(256), 0, s, K, x, y);
+  GDSW_LAUNCH_CHECK();
+}
+
+int multi_dot_blocks(int64_t n) { return (int)blocks_for(n, DOT_BLOCK_ROWS); }
+
+void multi_dot(int64_t n, int ncols, const double* V, int64_t ldv, const double* w, double* partial, double* h,
+               hipStream_t s) {
+  const int nb = multi_dot_blocks(n);
+  hipLaunchKernelGGL(k_multi_dot_partial, dim3(nb), dim3(256), 0, s, n, ncols, V, ldv, w, partial);
+  GDSW_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_multi_dot_reduce, dim3(blocks_for(ncols, 64)), dim3(64), 0, s, nb, ncols, partial, h);
+  GDSW_LAUNCH_CHECK();
+}
+
+void multi_axpy(int64_t n, int ncols, const double* V, int64_t ldv, const double* h, double* w, hipStream_t s) {
+  if (ncols > 256) throw Error(-1, "multi_axpy: more than 256 columns");
+  hipLaunchKernelGGL(k_multi_axpy, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, ncols, V, ldv, h, w);
+  GDSW_LAUNCH_CHECK();
+}
+
+void scale_by_inv_norm(int64_t n, const double* x, const double* nrm2, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_inv_norm, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, x, nrm2, y);
+  GDSW_LAUNCH_CHECK();
+}
+
+void residual_from(int64_t n, const double* b, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual_from, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, b, y);
+  GDSW_LAUNCH_CHECK();
+}
+
+}  // namespace gdsw

@@ -1,0 +1,432 @@
+// Batched dense LU with partial pivoting and multi-right-hand-side solves.
+//
+// The local saddle-point blocks A_i = R_i K R_i^T of section 2.1 are
+// indefinite (zero pressure block), so they are factored with row pivoting:
+// P A = L U, L unit lower, U upper, stored in place, column-major, leading
+// dimension = order.  Pivot rows follow the LAPACK convention (ipiv[j] = row
+// swapped with row j at step j); ties in the pivot search go to the lowest row.
+//
+// Right-looking blocked algorithm over panels of NB columns, one launch per
+// phase and panel for the whole (uneven) batch:
+//   panel : factor A[k:n, k:k+jb] (one workgroup per matrix; wave shuffles
+//           find the pivot);
+//   swap  : apply the panel's interchanges to the other columns and solve
+//           U12 = L11^{-1} A12 (one thread per column);
+//   update: A22 -= L21 U12 with MFMA (16x16x4, FP64 or FP32), 64x64 tiles.
+#include "common.h"
+#include "kernels.h"
+
+namespace gdsw {
+
+namespace {
+
+// 16x16x4 MFMA: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; result
+// register q of lane l holds D[row(l / 16, q)][l % 16].  The row map differs
+// between the FP64 and FP32 instructions (measured on gfx950).
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mac(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int q) { return lk + 4 * q; }
+};
+template <> struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mac(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int q) { return 4 * lk + q; }
+};
+
+constexpr int TILE = 64;
+
+// C[M x N] -= A[M x K] * B[K x N] on the 64x64 tile (ty, tx); K <= KMAX.
+// Column-major operands.  Four waves, each owning a 32x32 quarter computed as
+// 2x2 MFMA blocks.  The MFMA computes the transposed product (B^T A^T): its
+// columns are rows of C, so the 16 lanes of a lane group store 16 consecutive
+// rows of one column of C (128-byte runs for FP64).
+template <typename T, int KMAX>
+__device__ __forceinline__ void gemm_sub_tile(T* __restrict__ C, int64_t ldc, const T* __restrict__ A,
+                                              int64_t lda, const T* __restrict__ B, int64_t ldb, int M,
+                                              int N, int K, int ty, int tx, T* sA, T* sB) {
+  const int tid = threadIdx.x;
+  const int r0 = ty * TILE, c0 = tx * TILE;
+  const int Kp = (K + 3) & ~3;
+  // sA[k*64 + r] = A[r0 + r, k];  sB[k*64 + c] = B[k, c0 + c]   (zero padded)
+  for (int e = tid; e < Kp * TILE; e += 256) {
+    const int r = e & (TILE - 1), k = e >> 6;
+    const int gr = r0 + r;
+    sA[e] = (gr < M && k < K) ? A[gr + (int64_t)k * lda] : T(0);
+  }
+  for (int e = tid; e < Kp * TILE; e += 256) {
+    const int k = e % Kp, c = e / Kp;
+    const int gc = c0 + c;
+    sB[k * TILE + c] = (gc < N && k < K) ? B[k + (int64_t)gc * ldb] : T(0);
+  }
+  __syncthreads();
+  const int lane = tid & 63, w = tid >> 6;
+  const int wy = w >> 1, wx = w & 1;
+  typedef typename Mfma<T>::v4 v4;
+  v4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4{0, 0, 0, 0};
+  const int li = lane & 15, lk = lane >> 4;
+  for (int kk = 0; kk < Kp; kk += 4) {
+    T av[2], bv[2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) av[rb] = sA[(kk + lk) * TILE + wy * 32 + rb * 16 + li];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) bv[cb] = sB[(kk + lk) * TILE + wx * 32 + cb * 16 + li];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) acc[cb][rb] = Mfma<T>::mac(bv[cb], av[rb], acc[cb][rb]);
+  }
+  // acc[cb][rb][q]: output column c0 + wx*32 + cb*16 + row(lk, q), row r0 + wy*32 + rb*16 + li
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gr = r0 + wy * 32 + rb * 16 + li;
+        const int gc = c0 + wx * 32 + cb * 16 + Mfma<T>::row(lk, q);
+        if (gr < M && gc < N) C[gr + (int64_t)gc * ldc] -= acc[cb][rb][q];
+      }
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void k_lu_panel(T* __restrict__ Ab, const int64_t* __restrict__ off,
+                                                  const int* __restrict__ dim, int* __restrict__ pivb,
+                                                  const int64_t* __restrict__ poff, int* __restrict__ info,
+                                                  int k) {
+  const int i = blockIdx.x;
+  const int n = dim[i];
+  if (k >= n) return;
+  const int jb = min(NB, n - k);
+  T* A = Ab + off[i];
+  int* piv = pivb + poff[i];
+  __shared__ double s_val[4];
+  __shared__ int s_idx[4];
+  __shared__ int s_p;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int j = k; j < k + jb; ++j) {
+    T* colj = A + (int64_t)j * n;
+    double best = -1.0;
+    int bi = n;
+    for (int r = j + tid; r < n; r += 256) {
+      const double v = fabs((double)colj[r]);
+      if (v > best) {
+        best = v;
+        bi = r;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o, WAVE);
+      const int oi = __shfl_xor(bi, o, WAVE);
+      if (ov > best || (ov == best && oi < bi)) {
+        best = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      s_val[w] = best;
+      s_idx[w] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double b = s_val[0];
+      int p = s_idx[0];
+      for (int q = 1; q < 4; ++q)
+        if (s_val[q] > b || (s_val[q] == b && s_idx[q] < p)) {
+          b = s_val[q];
+          p = s_idx[q];
+        }
+      if (p >= n || !(b > 0.0)) {         // zero (or NaN) column: singular
+        if (info[i] == 0) info[i] = j + 1;
+        if (p >= n) p = j;
+      }
+      piv[j] = p;
+      s_p = p;
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (p != j) {
+      for (int c = tid; c < jb; c += 256) {
+        T* cc = A + (int64_t)(k + c) * n;
+        const T t = cc[j];
+        cc[j] = cc[p];
+        cc[p] = t;
+      }
+    }
+    __syncthreads();
+    const T pv = colj[j];
+    if (pv != T(0)) {
+      for (int r = j + 1 + tid; r < n; r += 256) colj[r] = colj[r] / pv;
+    }
+    __syncthreads();
+    for (int r = j + 1 + tid; r < n; r += 256) {
+      const T l = colj[r];
+      for (int c = j + 1; c < k + jb; ++c) {
+        T* cc = A + (int64_t)c * n;
+        cc[r] -= l * cc[j];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Interchanges of panel k on every non-panel column; U12 = L11^{-1} A12 right of the panel.
+template <typename T, int NB>
+__global__ __launch_bounds__(64) void k_lu_swap_trsm(T* __restrict__ Ab, const int64_t* __restrict__ off,
+                                                     const int* __restrict__ dim, const int* __restrict__ pivb,
+                                                     const int64_t* __restrict__ poff, int k) {
+  const int i = blockIdx.x;
+  const int n = dim[i];
+  if (k >= n) return;
+  const int jb = min(NB, n - k);
+  T* A = Ab + off[i];
+  const int* piv = pivb + poff[i];
+  __shared__ T L11[NB * NB];
+  for (int t = threadIdx.x; t < jb * jb; t += 64) {
+    const int r = t % jb, c = t / jb;
+    L11[t] = A[(k + r) + (int64_t)(k + c) * n];
+  }
+  __syncthreads();
+  const int c = blockIdx.y * 64 + threadIdx.x;
+  if (c >= n || (c >= k && c < k + jb)) return;
+  T* col = A + (int64_t)c * n;
+  for (int j = k; j < k + jb; ++j) {
+    const int p = piv[j];
+    if (p != j) {
+      const T t = col[j];
+      col[j] = col[p];
+      col[p] = t;
+    }
+  }
+  if (c < k + jb) return;
+  T x[NB];
+#pragma unroll
+  for (int r = 0; r < NB; ++r) x[r] = (r < jb) ? col[k + r] : T(0);
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if (j < jb) {
+#pragma unroll
+      for (int r = j + 1; r < NB; ++r)
+        if (r < jb) x[r] -= L11[r + j * jb] * x[j];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NB; ++r)
+    if (r < jb) col[k + r] = x[r];
+}
+
+// mode 0: LU trailing update; 1: forward-solve update of X; 2: backward-solve update of X.
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void k_gemm_update(T* __restrict__ Ab, const int64_t* __restrict__ off,
+                                                     const int* __restrict__ dim, T* __restrict__ Xb,
+                                                     const int64_t* __restrict__ xoff, const int* __restrict__ nrhs,
+                                                     int k, int mode, int tiles_n) {
+  // blockIdx.x = tile + tiles_n^2 * matrix; tiles are (ty, tx) with ty fastest
+  const int tiles = tiles_n * tiles_n;
+  const int i = blockIdx.x / tiles;
+  const int tl = blockIdx.x - i * tiles;
+  const int n = dim[i];
+  if (k >= n) return;
+  const int jb = min(NB, n - k);
+  const int ty = tl % tiles_n;
+  const int tx = tl / tiles_n;
+  T* A = Ab + off[i];
+  int M, N;
+  T* C;
+  const T *Ap, *Bp;
+  int64_t ldc, ldb;
+  if (mode == 0) {
+    M = N = n - k - jb;
+    C = A + (k + jb) + (int64_t)(k + jb) * n;
+    Ap = A + (k + jb) + (int64_t)k * n;
+    Bp = A + k + (int64_t)(k + jb) * n;
+    ldc = ldb = n;
+  } else {
+    T* X = Xb + xoff[i];
+    N = nrhs[i];
+    ldc = ldb = n;
+    if (mode == 1) {
+      M = n - k - jb;
+      C = X + (k + jb);
+      Ap = A + (k + jb) + (int64_t)k * n;
+      Bp = X + k;
+    } else {
+      M = k;
+      C = X;
+      Ap = A + (int64_t)k * n;
+      Bp = X + k;
+    }
+  }
+  if (ty * TILE >= M || tx * TILE >= N) return;
+  __shared__ T sA[NB * TILE];
+  __shared__ T sB[NB * TILE];
+  gemm_sub_tile<T, NB>(C, ldc, Ap, n, Bp, ldb, M, N, jb, ty, tx, sA, sB);
+}
+
+// Row interchanges of the whole factorization applied to each right-hand side.
+template <typename T>
+__global__ void k_getrs_swap(const int* __restrict__ dim, const int* __restrict__ pivb,
+                             const int64_t* __restrict__ poff, T* __restrict__ Xb,
+                             const int64_t* __restrict__ xoff, const int* __restrict__ nrhs) {
+  const int i = blockIdx.x;
+  const int c = blockIdx.y * blockDim.x + threadIdx.x;
+  if (c >= nrhs[i]) return;
+  const int n = dim[i];
+  const int* piv = pivb + poff[i];
+  T* x = Xb + xoff[i] + (int64_t)c * n;
+  for (int j = 0; j < n; ++j) {
+    const int p = piv[j];
+    if (p != j) {
+      const T t = x[j];
+      x[j] = x[p];
+      x[p] = t;
+    }
+  }
+}
+
+// Diagonal block solve of the forward (unit L) or backward (U) sweep for rows k..k+jb.
+template <typename T, int NB>
+__global__ __launch_bounds__(64) void k_getrs_diag(const T* __restrict__ Ab, const int64_t* __restrict__ off,
+                                                   const int* __restrict__ dim, T* __restrict__ Xb,
+                                                   const int64_t* __restrict__ xoff, const int* __restrict__ nrhs,
+                                                   int k, int upper) {
+  const int i = blockIdx.x;
+  const int n = dim[i];
+  if (k >= n) return;
+  const int jb = min(NB, n - k);
+  const T* A = Ab + off[i];
+  __shared__ T D[NB * NB];
+  for (int t = threadIdx.x; t < jb * jb; t += 64) {
+    const int r = t % jb, c = t / jb;
+    D[t] = A[(k + r) + (int64_t)(k + c) * n];
+  }
+  __syncthreads();
+  const int c = blockIdx.y * 64 + threadIdx.x;
+  if (c >= nrhs[i]) return;
+  T* col = Xb + xoff[i] + (int64_t)c * n + k;
+  T x[NB];
+#pragma unroll
+  for (int r = 0; r < NB; ++r) x[r] = (r < jb) ? col[r] : T(0);
+  if (!upper) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+      if (j < jb) {
+#pragma unroll
+        for (int r = j + 1; r < NB; ++r)
+          if (r < jb) x[r] -= D[r + j * jb] * x[j];
+      }
+  } else {
+#pragma unroll
+    for (int j = NB - 1; j >= 0; --j)
+      if (j < jb) {
+        x[j] = x[j] / D[j + j * jb];
+#pragma unroll
+        for (int r = 0; r < NB; ++r)
+          if (r < j) x[r] -= D[r + j * jb] * x[j];
+      }
+  }
+#pragma unroll
+  for (int r = 0; r < NB; ++r)
+    if (r < jb) col[r] = x[r];
+}
+
+template <typename T>
+__global__ void k_build_perm(const int* __restrict__ dim, const int* __restrict__ pivb,
+                             const int64_t* __restrict__ poff, int* __restrict__ perm, int nbatch) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nbatch) return;
+  const int n = dim[i];
+  const int* piv = pivb + poff[i];
+  int* p = perm + poff[i];
+  for (int a = 0; a < n; ++a) p[a] = a;
+  for (int j = 0; j < n; ++j) {
+    const int q = piv[j];
+    if (q != j) {
+      const int t = p[j];
+      p[j] = p[q];
+      p[q] = t;
+    }
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
+  constexpr int NB = LU_NB;
+  const unsigned colblocks = blocks_for(b.max_n, 64);
+  for (int k = 0; k < b.max_n; k += NB) {
+    hipLaunchKernelGGL((k_lu_panel<T, NB>), dim3(b.count), dim3(256), 0, s, A, b.off, b.dim, b.piv, b.poff,
+                       b.info, k);
+    GDSW_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_lu_swap_trsm<T, NB>), dim3(b.count, colblocks), dim3(64), 0, s, A, b.off, b.dim,
+                       b.piv, b.poff, k);
+    GDSW_LAUNCH_CHECK();
+    const int rest = b.max_n - k - NB;
+    if (rest > 0) {
+      const int t = (int)blocks_for(rest, TILE);
+      hipLaunchKernelGGL((k_gemm_update<T, NB>), dim3(b.count * t * t), dim3(256), 0, s, A, b.off, b.dim,
+                         (T*)nullptr, (const int64_t*)nullptr, (const int*)nullptr, k, 0, t);
+      GDSW_LAUNCH_CHECK();
+    }
+  }
+}
+
+template <typename T>
+void lu_solve_batched(const LuBatch& b, const T* A, T* X, const int64_t* xoff, const int* nrhs, int max_rhs,
+                      hipStream_t s) {
+  constexpr int NB = LU_NB;
+  const unsigned rhsblocks = blocks_for(max_rhs, 64);
+  hipLaunchKernelGGL((k_getrs_swap<T>), dim3(b.count, rhsblocks), dim3(64), 0, s, b.dim, b.piv, b.poff, X, xoff,
+                     nrhs);
+  GDSW_LAUNCH_CHECK();
+  const int tn = (int)blocks_for(max_rhs, TILE);
+  const int tm = (int)blocks_for(b.max_n, TILE);
+  const int tiles = (tm > tn ? tm : tn);
+  for (int k = 0; k < b.max_n; k += NB) {
+    hipLaunchKernelGGL((k_getrs_diag<T, NB>), dim3(b.count, rhsblocks), dim3(64), 0, s, A, b.off, b.dim, X, xoff,
+                       nrhs, k, 0);
+    GDSW_LAUNCH_CHECK();
+    if (b.max_n - k - NB > 0) {
+      hipLaunchKernelGGL((k_gemm_update<T, NB>), dim3(b.count * tiles * tiles), dim3(256), 0, s, (T*)A, b.off,
+                         b.dim, X, xoff, nrhs, k, 1, tiles);
+      GDSW_LAUNCH_CHECK();
+    }
+  }
+  const int last = ((b.max_n - 1) / NB) * NB;
+  for (int k = last; k >= 0; k -= NB) {
+    hipLaunchKernelGGL((k_getrs_diag<T, NB>), dim3(b.count, rhsblocks), dim3(64), 0, s, A, b.off, b.dim, X, xoff,
+                       nrhs, k, 1);
+    GDSW_LAUNCH_CHECK();
+    if (k > 0) {
+      hipLaunchKernelGGL((k_gemm_update<T, NB>), dim3(b.count * tiles * tiles), dim3(256), 0, s, (T*)A, b.off,
+                         b.dim, X, xoff, nrhs, k, 2, tiles);
+      GDSW_LAUNCH_CHECK();
+    }
+  }
+}
+
+void lu_build_perm(const LuBatch& b, int* perm, hipStream_t s) {
+  hipLaunchKernelGGL((k_build_perm<double>), dim3(blocks_for(b.count, 64)), dim3(64), 0, s, b.dim, b.piv, b.poff,
+                     perm, b.count);
+  GDSW_LAUNCH_CHECK();
+}
+
+template void lu_batched<double>(const LuBatch&, double*, hipStream_t);
+template void lu_batched<float>(const LuBatch&, float*, hipStream_t);
+template void lu_solve_batched<double>(const LuBatch&, const double*, double*, const int64_t*, const int*, int,
+                                       hipStream_t);
+template void lu_solve_batched<float>(const LuBatch&, const float*, float*, const int64_t*, const int*, int,
+                                      hipStream_t);
+
+}  // namespace gdsw

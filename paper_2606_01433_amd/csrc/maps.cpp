@@ -1,0 +1,433 @@
+// Host-side index maps of one GDSW level (section 2.1) and the coarse mesh
+// that the recursion of section 2.2 works on.  Integer graph work only.
+#include "maps.h"
+
+#include <algorithm>
+#include <numeric>
+#include <string>
+
+namespace gdsw {
+
+namespace {
+
+// Sort and deduplicate each segment of a CSR list in place, then compact.
+void sort_unique_segments(std::vector<int64_t>& ptr, std::vector<int>& val) {
+  const int64_t nseg = (int64_t)ptr.size() - 1;
+  int64_t w = 0;
+  int64_t start = 0;
+  for (int64_t s = 0; s < nseg; ++s) {
+    const int64_t a = start, b = ptr[s + 1];
+    std::sort(val.begin() + a, val.begin() + b);
+    const int64_t seg_begin = w;
+    for (int64_t k = a; k < b; ++k) {
+      if (k == a || val[k] != val[k - 1]) val[w++] = val[k];
+    }
+    start = b;
+    ptr[s] = seg_begin;
+  }
+  ptr[nseg] = w;
+  val.resize(w);
+}
+
+// elements containing each node (CSR)
+void node_elements(const LevelMesh& mesh, std::vector<int64_t>& ptr, std::vector<int>& el) {
+  ptr.assign(mesh.n_nodes + 1, 0);
+  for (int e = 0; e < mesh.n_elem; ++e)
+    for (int64_t k = mesh.en_ptr[e]; k < mesh.en_ptr[e + 1]; ++k) ptr[mesh.en[k] + 1]++;
+  for (int v = 0; v < mesh.n_nodes; ++v) ptr[v + 1] += ptr[v];
+  el.assign(ptr[mesh.n_nodes], 0);
+  std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+  for (int e = 0; e < mesh.n_elem; ++e)
+    for (int64_t k = mesh.en_ptr[e]; k < mesh.en_ptr[e + 1]; ++k) el[fill[mesh.en[k]]++] = e;
+}
+
+bool same_set(const LevelMaps& m, int u, int v) {
+  const int64_t a0 = m.s_ptr[u], a1 = m.s_ptr[u + 1], b0 = m.s_ptr[v], b1 = m.s_ptr[v + 1];
+  if (a1 - a0 != b1 - b0) return false;
+  for (int64_t k = 0; k < a1 - a0; ++k)
+    if (m.s[a0 + k] != m.s[b0 + k]) return false;
+  return true;
+}
+
+}  // namespace
+
+std::string build_level1_mesh(int64_t n, int n_nodes, const int* node_dof, int n_elem,
+                              const int* elem_node, const int* elem_pdof, const int* elem_part,
+                              int n_parts, LevelMesh& out) {
+  if (n <= 0 || n > INT32_MAX) return "n out of range";
+  if (n_nodes <= 0 || n_elem <= 0 || n_parts <= 0) return "empty mesh or partition";
+  out.n_dof = (int)n;
+  out.n_nodes = n_nodes;
+  out.node_dof.assign(node_dof, node_dof + (size_t)n_nodes * 3);
+  out.n_elem = n_elem;
+  out.en.assign(elem_node, elem_node + (size_t)n_elem * 27);
+  out.en_ptr.resize(n_elem + 1);
+  for (int e = 0; e <= n_elem; ++e) out.en_ptr[e] = (int64_t)e * 27;
+  out.elem_pdof.assign(elem_pdof, elem_pdof + (size_t)n_elem * 4);
+  out.elem_part.assign(elem_part, elem_part + n_elem);
+  out.n_parts = n_parts;
+  // every free dof exactly once
+  std::vector<char> seen(n, 0);
+  auto mark = [&](int g) -> bool {
+    if (g < -1 || g >= n) return false;
+    if (g >= 0) {
+      if (seen[g]) return false;
+      seen[g] = 1;
+    }
+    return true;
+  };
+  for (size_t k = 0; k < out.node_dof.size(); ++k)
+    if (!mark(out.node_dof[k])) return "node_dof: id out of range or repeated";
+  for (size_t k = 0; k < out.elem_pdof.size(); ++k)
+    if (!mark(out.elem_pdof[k])) return "elem_pdof: id out of range or repeated";
+  for (int64_t g = 0; g < n; ++g)
+    if (!seen[g]) return "dof " + std::to_string(g) + " is not referenced by node_dof/elem_pdof";
+  for (int v : out.en)
+    if (v < 0 || v >= n_nodes) return "elem_node: node id out of range";
+  std::vector<int> cnt(n_parts, 0);
+  for (int p : out.elem_part) {
+    if (p < 0 || p >= n_parts) return "elem_part: part id out of range";
+    cnt[p]++;
+  }
+  for (int i = 0; i < n_parts; ++i)
+    if (!cnt[i]) return "level-1 part " + std::to_string(i) + " has no element";
+  // node graph: two nodes of one element whose lattice offsets differ by at most one per axis
+  int pa[27 * 26], pb[27 * 26];
+  int npairs = 0;
+  for (int a = 0; a < 27; ++a)
+    for (int b = 0; b < 27; ++b) {
+      if (a == b) continue;
+      const int dx = a % 3 - b % 3, dy = (a / 3) % 3 - (b / 3) % 3, dz = a / 9 - b / 9;
+      if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) {
+        pa[npairs] = a;
+        pb[npairs] = b;
+        ++npairs;
+      }
+    }
+  std::vector<int64_t> cntp(n_nodes + 1, 0);
+  for (int e = 0; e < n_elem; ++e)
+    for (int k = 0; k < npairs; ++k) cntp[out.en[(size_t)e * 27 + pa[k]] + 1]++;
+  for (int v = 0; v < n_nodes; ++v) cntp[v + 1] += cntp[v];
+  std::vector<int> nb(cntp[n_nodes]);
+  std::vector<int64_t> fill(cntp.begin(), cntp.end() - 1);
+  for (int e = 0; e < n_elem; ++e) {
+    const int* nodes = &out.en[(size_t)e * 27];
+    for (int k = 0; k < npairs; ++k) nb[fill[nodes[pa[k]]]++] = nodes[pb[k]];
+  }
+  sort_unique_segments(cntp, nb);
+  out.adj_ptr = std::move(cntp);
+  out.adj = std::move(nb);
+  return "";
+}
+
+void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m) {
+  const int N = mesh.n_parts;
+  const int nn = mesh.n_nodes;
+  std::vector<int64_t> ne_ptr;
+  std::vector<int> ne;
+  node_elements(mesh, ne_ptr, ne);
+  // S(v)
+  m.s_ptr = ne_ptr;
+  m.s.resize(ne.size());
+  for (size_t k = 0; k < ne.size(); ++k) m.s[k] = mesh.elem_part[ne[k]];
+  sort_unique_segments(m.s_ptr, m.s);
+  auto nS = [&](int v) { return m.s_ptr[v + 1] - m.s_ptr[v]; };
+  auto has_free = [&](int v) {
+    return mesh.node_dof[3 * v] >= 0 || mesh.node_dof[3 * v + 1] >= 0 || mesh.node_dof[3 * v + 2] >= 0;
+  };
+  // interface nodes and entities (components of equal-S classes, in order of their smallest node)
+  m.gamma_nodes.clear();
+  for (int v = 0; v < nn; ++v)
+    if (has_free(v) && nS(v) >= 2) m.gamma_nodes.push_back(v);
+  m.node_ent.assign(nn, -1);
+  std::vector<char> is_gamma(nn, 0);
+  for (int v : m.gamma_nodes) is_gamma[v] = 1;
+  m.ent_ptr.assign(1, 0);
+  m.ent_nodes.clear();
+  m.ent_kind.clear();
+  std::vector<int> stack;
+  for (int v : m.gamma_nodes) {
+    if (m.node_ent[v] >= 0) continue;
+    const int E = (int)m.ent_kind.size();
+    const int64_t first = (int64_t)m.ent_nodes.size();
+    m.node_ent[v] = E;
+    stack.assign(1, v);
+    while (!stack.empty()) {
+      const int u = stack.back();
+      stack.pop_back();
+      m.ent_nodes.push_back(u);
+      for (int64_t k = mesh.adj_ptr[u]; k < mesh.adj_ptr[u + 1]; ++k) {
+        const int w = mesh.adj[k];
+        if (is_gamma[w] && m.node_ent[w] < 0 && same_set(m, u, w)) {
+          m.node_ent[w] = E;
+          stack.push_back(w);
+        }
+      }
+    }
+    std::sort(m.ent_nodes.begin() + first, m.ent_nodes.end());
+    const int64_t cnt = (int64_t)m.ent_nodes.size() - first;
+    const int64_t ns = nS(v);
+    m.ent_kind.push_back(cnt == 1 ? 0 : (ns == 2 ? 2 : 1));
+    m.ent_ptr.push_back((int64_t)m.ent_nodes.size());
+  }
+  const int n_ent = (int)m.ent_kind.size();
+  m.es_ptr.assign(n_ent + 1, 0);
+  m.es.clear();
+  for (int E = 0; E < n_ent; ++E) {
+    const int v = m.ent_nodes[m.ent_ptr[E]];
+    for (int64_t k = m.s_ptr[v]; k < m.s_ptr[v + 1]; ++k) m.es.push_back(m.s[k]);
+    m.es_ptr[E + 1] = (int64_t)m.es.size();
+  }
+  // coarse columns: (entity, direction) with a free dof, then one pressure column per part
+  m.col_entity.clear();
+  m.col_dir.clear();
+  m.col_ptr.assign(1, 0);
+  m.col_dofs.clear();
+  m.ent_col.assign((size_t)n_ent * 3, -1);
+  for (int E = 0; E < n_ent; ++E) {
+    for (int d = 0; d < 3; ++d) {
+      const size_t before = m.col_dofs.size();
+      for (int64_t k = m.ent_ptr[E]; k < m.ent_ptr[E + 1]; ++k) {
+        const int g = mesh.node_dof[3 * m.ent_nodes[k] + d];
+        if (g >= 0) m.col_dofs.push_back(g);
+      }
+      if (m.col_dofs.size() > before) {
+        std::sort(m.col_dofs.begin() + before, m.col_dofs.end());
+        m.ent_col[(size_t)E * 3 + d] = (int)m.col_entity.size();
+        m.col_entity.push_back(E);
+        m.col_dir.push_back(d);
+        m.col_ptr.push_back((int64_t)m.col_dofs.size());
+      }
+    }
+  }
+  std::vector<std::vector<int>> part_elems(N);
+  for (int e = 0; e < mesh.n_elem; ++e) part_elems[mesh.elem_part[e]].push_back(e);
+  m.part_col.assign(N, -1);
+  for (int i = 0; i < N; ++i) {
+    const size_t before = m.col_dofs.size();
+    for (int e : part_elems[i]) {
+      const int g = mesh.elem_pdof[4 * e];
+      if (g >= 0) m.col_dofs.push_back(g);
+    }
+    if (m.col_dofs.size() > before) {
+      std::sort(m.col_dofs.begin() + before, m.col_dofs.end());
+      m.part_col[i] = (int)m.col_entity.size();
+      m.col_entity.push_back(-1 - i);
+      m.col_dir.push_back(3);
+      m.col_ptr.push_back((int64_t)m.col_dofs.size());
+    }
+  }
+  m.n_coarse = (int)m.col_entity.size();
+  // per-dof tables
+  const int n = mesh.n_dof;
+  m.owner.assign(n, -1);
+  m.dof_gcol.assign(n, -1);
+  m.dof_ipart.assign(n, -1);
+  m.dof_irow.assign(n, -1);
+  for (int v = 0; v < nn; ++v) {
+    if (nS(v) == 0) continue;
+    const int own = m.s[m.s_ptr[v]];
+    for (int d = 0; d < 3; ++d) {
+      const int g = mesh.node_dof[3 * v + d];
+      if (g < 0) continue;
+      m.owner[g] = own;
+      if (is_gamma[v]) m.dof_gcol[g] = m.ent_col[(size_t)m.node_ent[v] * 3 + d];
+    }
+  }
+  for (int e = 0; e < mesh.n_elem; ++e)
+    for (int q = 0; q < 4; ++q) {
+      const int g = mesh.elem_pdof[4 * e + q];
+      if (g < 0) continue;
+      m.owner[g] = mesh.elem_part[e];
+      if (q == 0) m.dof_gcol[g] = m.part_col[mesh.elem_part[e]];
+    }
+  // overlapping and interior sets
+  std::vector<int> stamp(nn, -1), depth(nn, 0);
+  std::vector<int> layer, frontier, next;
+  m.dom_ptr.assign(1, 0);
+  m.dom.clear();
+  m.int_ptr.assign(1, 0);
+  m.inter.clear();
+  m.pc_ptr.assign(1, 0);
+  m.pcols.clear();
+  m.z_ptr.assign(1, 0);
+  m.z_dof.clear();
+  m.z_lc.clear();
+  std::vector<int> dofs, idofs;
+  std::vector<std::pair<int, int>> zs;
+  for (int i = 0; i < N; ++i) {
+    layer.clear();
+    for (int e : part_elems[i])
+      for (int64_t k = mesh.en_ptr[e]; k < mesh.en_ptr[e + 1]; ++k) {
+        const int v = mesh.en[k];
+        if (stamp[v] != i) {
+          stamp[v] = i;
+          depth[v] = 0;
+          layer.push_back(v);
+        }
+      }
+    const size_t n_closure = layer.size();
+    frontier.assign(layer.begin(), layer.end());
+    for (int l = 0; l < delta; ++l) {
+      next.clear();
+      for (int u : frontier)
+        for (int64_t k = mesh.adj_ptr[u]; k < mesh.adj_ptr[u + 1]; ++k) {
+          const int w = mesh.adj[k];
+          if (stamp[w] != i) {
+            stamp[w] = i;
+            depth[w] = l + 1;
+            next.push_back(w);
+          }
+        }
+      layer.insert(layer.end(), next.begin(), next.end());
+      frontier.swap(next);
+    }
+    dofs.clear();
+    idofs.clear();
+    zs.clear();
+    for (size_t k = 0; k < layer.size(); ++k) {
+      const int v = layer[k];
+      for (int d = 0; d < 3; ++d) {
+        const int g = mesh.node_dof[3 * v + d];
+        if (g >= 0) dofs.push_back(g);
+      }
+    }
+    for (size_t k = 0; k < n_closure; ++k) {
+      const int v = layer[k];
+      const bool interior = nS(v) == 1 && m.s[m.s_ptr[v]] == i;
+      for (int d = 0; d < 3; ++d) {
+        const int g = mesh.node_dof[3 * v + d];
+        if (g < 0) continue;
+        if (interior) idofs.push_back(g);
+        else if (is_gamma[v]) zs.push_back({m.dof_gcol[g], g});
+      }
+    }
+    for (int e : part_elems[i])
+      for (int q = 0; q < 4; ++q) {
+        const int g = mesh.elem_pdof[4 * e + q];
+        if (g < 0) continue;
+        dofs.push_back(g);
+        if (q > 0) idofs.push_back(g);
+        else zs.push_back({m.dof_gcol[g], g});
+      }
+    std::sort(dofs.begin(), dofs.end());
+    std::sort(idofs.begin(), idofs.end());
+    m.dom.insert(m.dom.end(), dofs.begin(), dofs.end());
+    m.dom_ptr.push_back((int64_t)m.dom.size());
+    for (size_t a = 0; a < idofs.size(); ++a) {
+      m.dof_ipart[idofs[a]] = i;
+      m.dof_irow[idofs[a]] = (int)a;
+    }
+    m.inter.insert(m.inter.end(), idofs.begin(), idofs.end());
+    m.int_ptr.push_back((int64_t)m.inter.size());
+    // coarse columns of the part: every column of an interface dof in its closure
+    const size_t pc0 = m.pcols.size();
+    for (auto& z : zs) m.pcols.push_back(z.first);
+    std::sort(m.pcols.begin() + pc0, m.pcols.end());
+    m.pcols.erase(std::unique(m.pcols.begin() + pc0, m.pcols.end()), m.pcols.end());
+    m.pc_ptr.push_back((int64_t)m.pcols.size());
+    // interface dofs of the closure, keyed by their local column
+    for (auto& z : zs) {
+      const int lc = (int)(std::lower_bound(m.pcols.begin() + pc0, m.pcols.end(), z.first) -
+                           (m.pcols.begin() + pc0));
+      z.first = lc;
+    }
+    std::sort(zs.begin(), zs.end());
+    for (auto& z : zs) {
+      m.z_lc.push_back(z.first);
+      m.z_dof.push_back(z.second);
+    }
+    m.z_ptr.push_back((int64_t)m.z_dof.size());
+  }
+  // per coarse column: the parts that hold it
+  std::vector<int64_t> cnt(m.n_coarse + 1, 0);
+  for (int i = 0; i < N; ++i)
+    for (int64_t k = m.pc_ptr[i]; k < m.pc_ptr[i + 1]; ++k) cnt[m.pcols[k] + 1]++;
+  for (int c = 0; c < m.n_coarse; ++c) cnt[c + 1] += cnt[c];
+  m.cp_ptr = cnt;
+  m.cp_part.assign(cnt[m.n_coarse], 0);
+  m.cp_lc.assign(cnt[m.n_coarse], 0);
+  std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+  for (int i = 0; i < N; ++i)
+    for (int64_t k = m.pc_ptr[i]; k < m.pc_ptr[i + 1]; ++k) {
+      const int c = m.pcols[k];
+      m.cp_part[fill[c]] = i;
+      m.cp_lc[fill[c]] = (int)(k - m.pc_ptr[i]);
+      fill[c]++;
+    }
+}
+
+std::string build_next_mesh(const LevelMesh& mesh, const LevelMaps& m, const int* parent,
+                            int n_parts_next, LevelMesh& out) {
+  const int n_ent = (int)m.ent_kind.size();
+  const int N = mesh.n_parts;
+  out.n_dof = m.n_coarse;
+  out.n_nodes = n_ent;
+  out.node_dof = m.ent_col;
+  out.n_elem = N;
+  // element i's nodes: entities E with i in S(E), ascending
+  std::vector<int64_t> cnt(N + 1, 0);
+  for (int E = 0; E < n_ent; ++E)
+    for (int64_t k = m.es_ptr[E]; k < m.es_ptr[E + 1]; ++k) cnt[m.es[k] + 1]++;
+  for (int i = 0; i < N; ++i) cnt[i + 1] += cnt[i];
+  out.en_ptr = cnt;
+  out.en.assign(cnt[N], 0);
+  std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+  for (int E = 0; E < n_ent; ++E)
+    for (int64_t k = m.es_ptr[E]; k < m.es_ptr[E + 1]; ++k) out.en[fill[m.es[k]]++] = E;
+  out.elem_pdof.assign((size_t)N * 4, -1);
+  for (int i = 0; i < N; ++i) out.elem_pdof[(size_t)4 * i] = m.part_col[i];
+  out.elem_part.resize(N);
+  std::vector<int> pc(n_parts_next, 0);
+  for (int i = 0; i < N; ++i) {
+    const int p = parent[i];
+    if (p < 0 || p >= n_parts_next) return "part_parent: id out of range";
+    out.elem_part[i] = p;
+    pc[p]++;
+  }
+  for (int j = 0; j < n_parts_next; ++j)
+    if (!pc[j]) return "coarse part " + std::to_string(j) + " has no fine part";
+  out.n_parts = n_parts_next;
+  // entity graph: E ~ F if some node of E is adjacent to some node of F
+  std::vector<int64_t> ac(n_ent + 1, 0);
+  for (int u : m.gamma_nodes) {
+    const int E = m.node_ent[u];
+    for (int64_t k = mesh.adj_ptr[u]; k < mesh.adj_ptr[u + 1]; ++k) {
+      const int F = m.node_ent[mesh.adj[k]];
+      if (F >= 0 && F != E) ac[E + 1]++;
+    }
+  }
+  for (int E = 0; E < n_ent; ++E) ac[E + 1] += ac[E];
+  std::vector<int> nb(ac[n_ent]);
+  std::vector<int64_t> af(ac.begin(), ac.end() - 1);
+  for (int u : m.gamma_nodes) {
+    const int E = m.node_ent[u];
+    for (int64_t k = mesh.adj_ptr[u]; k < mesh.adj_ptr[u + 1]; ++k) {
+      const int F = m.node_ent[mesh.adj[k]];
+      if (F >= 0 && F != E) nb[af[E]++] = F;
+    }
+  }
+  sort_unique_segments(ac, nb);
+  out.adj_ptr = std::move(ac);
+  out.adj = std::move(nb);
+  return "";
+}
+
+void coarse_pattern(const LevelMaps& m, std::vector<int64_t>& rowptr, std::vector<int>& col) {
+  rowptr.assign(m.n_coarse + 1, 0);
+  col.clear();
+  std::vector<int> row;
+  for (int c = 0; c < m.n_coarse; ++c) {
+    row.clear();
+    for (int64_t k = m.cp_ptr[c]; k < m.cp_ptr[c + 1]; ++k) {
+      const int i = m.cp_part[k];
+      row.insert(row.end(), m.pcols.begin() + m.pc_ptr[i], m.pcols.begin() + m.pc_ptr[i + 1]);
+    }
+    std::sort(row.begin(), row.end());
+    row.erase(std::unique(row.begin(), row.end()), row.end());
+    col.insert(col.end(), row.begin(), row.end());
+    rowptr[c + 1] = (int64_t)col.size();
+  }
+}
+
+}  // namespace gdsw

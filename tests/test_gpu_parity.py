@@ -1,0 +1,199 @@
+"""GPU parity of the HIP library against the FP64 oracle (through the C ABI).
+
+Every case prints its name before it touches the GPU.  Tolerances:
+  * index maps and the ordered combination of overlapping values: bit-exact;
+  * FP64 apply: ||z_gpu - z_oracle|| / ||z_oracle|| <= 1e-10;
+  * FP64 solve: true relative residual <= tol, and the solution agrees with
+    the direct solve to within the conditioning-scaled tolerance;
+  * mixed precision: true residual <= 1e-8 after FGMRES (the FP32 factors only
+    enter the preconditioner), apply error reported against FP64.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from harness import unit_cube_problem, die_problem, random_vector
+from tests.conftest import cached
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_01433_amd import gdsw
+    gdsw.load_library()
+    return gdsw
+
+
+def _cases():
+    return {
+        "cube4_L2": lambda: unit_cube_problem(),
+        "cube8_L3": lambda: unit_cube_problem(n=8, block=2, levels=3),
+        "die16_L3": lambda: die_problem(16, 8, 8, seed=0, levels=3),
+        "die16_L4_uneven": lambda: die_problem(16, 8, 8, seed=3, levels=4, frac3=0.3),
+    }
+
+
+def _problem(name):
+    return cached(("gpu", name), _cases()[name])
+
+
+def _orc(name, combine="RAS", no_coarse=False):
+    P = _problem(name)
+    return cached(("orc", name, combine, no_coarse), lambda: oracle.setup(P, combine=combine, no_coarse=no_coarse))
+
+
+def _dev(x):
+    return torch.as_tensor(np.asarray(x, dtype=np.float64), device="cuda")
+
+
+def test_mfma_layout_and_lu_via_tiny_solve(gd):
+    """Single part covering a 2^3 cube, no coarse level: the apply is K^{-1} (one dense LU of order n)."""
+    P = unit_cube_problem(n=2, block=2)
+    P = P.with_hierarchy(np.zeros(P.n_elem), [1], [], 2)
+    _say("tiny single-part exact inverse, n =", P.n)
+    with gd.Context(P, no_coarse=True) as ctx:
+        r = random_vector(P.n, 11)
+        z = ctx.apply(_dev(r)).cpu().numpy()
+    x = np.linalg.solve(P.K().toarray(), r)
+    assert np.linalg.norm(z - x) <= 1e-11 * np.linalg.norm(x)
+
+
+@pytest.mark.parametrize("name", list(_cases()))
+def test_maps_export_bit_exact(gd, name):
+    P = _problem(name)
+    _say("maps", name)
+    H = _orc(name)
+    with gd.Context(P) as ctx:
+        for k, lev in enumerate(H.levels):
+            m = ctx.export_maps(k + 1)
+            assert np.array_equal(m["dom"], np.concatenate(lev.maps.dom))
+            assert np.array_equal(m["inter"], np.concatenate(lev.maps.inter))
+            assert np.array_equal(m["ent_nodes"], np.concatenate(lev.maps.entities))
+            assert np.array_equal(m["col_entity"], lev.maps.col_entity)
+            assert np.array_equal(m["owner"], lev.owner)
+
+
+@pytest.mark.parametrize("combine", ["RAS", "AS"])
+@pytest.mark.parametrize("name", list(_cases()))
+def test_apply_parity_fp64(gd, name, combine):
+    P = _problem(name)
+    H = _orc(name, combine)
+    _say("apply fp64", name, combine, "n =", P.n)
+    with gd.Context(P, combine=combine) as ctx:
+        for seed in (0, 1):
+            r = random_vector(P.n, seed)
+            z = ctx.apply(_dev(r)).cpu().numpy()
+            zo = oracle.apply(H, r)
+            err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+            _say("  seed", seed, "rel err", err)
+            assert err <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["cube4_L2", "die16_L3"])
+def test_apply_mixed_precision_error(gd, name):
+    P = _problem(name)
+    H = _orc(name)
+    _say("apply mixed", name)
+    with gd.Context(P, precision="mixed") as ctx:
+        r = random_vector(P.n, 5)
+        z = ctx.apply(_dev(r)).cpu().numpy()
+    zo = oracle.apply(H, r)
+    err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+    _say("  mixed rel err vs fp64 oracle", err)
+    assert err <= 1e-3
+
+
+@pytest.mark.parametrize("combine", ["RAS", "AS"])
+def test_scatter_is_bit_exact(gd, cube4, combine):
+    """Given identical local vectors, the ordered combination equals the oracle's sum bit for bit."""
+    H = _orc("cube4_L2", combine)
+    lev = H.levels[0]
+    rng = np.random.Generator(np.random.PCG64(9))
+    ws = [rng.standard_normal(len(D)) for D in lev.maps.dom]
+    ws[2][::7] = -0.0
+    zo = np.zeros(cube4.n)
+    for i, (D, w) in enumerate(zip(lev.maps.dom, ws)):
+        if lev.owner is not None:
+            w = np.where(lev.owner[D] == i, w, 0.0)
+        zo[D] += w
+    _say("scatter", combine)
+    with gd.Context(cube4, combine=combine) as ctx:
+        z = ctx.scatter_local(1, _dev(np.concatenate(ws))).cpu().numpy()
+    assert np.array_equal(z.view(np.uint64), zo.view(np.uint64))
+
+
+def test_single_subdomain_converges_in_one_iteration(gd, cube4):
+    P = cube4.with_hierarchy(np.zeros(cube4.n_elem), [1], [], 2)
+    _say("single subdomain one-level")
+    with gd.Context(P, no_coarse=True, tol=1e-10) as ctx:
+        x, info = ctx.solve(_dev(P.b))
+    assert info["iterations"] == 1 and info["converged"]
+    assert np.abs(x.cpu().numpy() - P.x_exact).max() <= 1e-9
+
+
+@pytest.mark.parametrize("name,tol", [("cube4_L2", 1e-10), ("cube8_L3", 1e-10), ("die16_L3", 1e-8),
+                                      ("die16_L4_uneven", 1e-8)])
+def test_solve_parity(gd, name, tol):
+    P = _problem(name)
+    K = P.K()
+    H = _orc(name)
+    xo, info_o = oracle.fgmres(lambda v: K @ v, lambda v: oracle.apply(H, v), P.b, tol=tol)
+    _say("solve", name, "oracle iterations", info_o["iterations"])
+    with gd.Context(P, tol=tol) as ctx:
+        x, info = ctx.solve(_dev(P.b))
+    x = x.cpu().numpy()
+    _say("  gpu iterations", info["iterations"], "rel residual", info["rel_residual"])
+    assert info["converged"]
+    assert np.linalg.norm(K @ x - P.b) <= tol * np.linalg.norm(P.b) * 1.0001
+    assert abs(info["iterations"] - info_o["iterations"]) <= 2
+    xd = oracle.solve_direct(P)
+    assert np.linalg.norm(x - xd) <= 1e3 * tol * np.linalg.norm(xd)
+    if P.x_exact is not None:
+        assert np.abs(x - P.x_exact).max() <= 1e-6
+
+
+def test_mixed_precision_solve(gd):
+    P = _problem("die16_L3")
+    _say("solve mixed die16_L3")
+    with gd.Context(P, precision="mixed", tol=1e-8) as ctx:
+        x, info = ctx.solve(_dev(P.b))
+    x = x.cpu().numpy()
+    assert info["converged"]
+    assert np.linalg.norm(P.K() @ x - P.b) <= 1e-8 * np.linalg.norm(P.b) * 1.0001
+
+
+def test_singular_local_block_is_reported(gd, cube4):
+    import copy
+    P = copy.copy(cube4)
+    P.val = cube4.val.copy()
+    K = cube4.K()
+    g = int(cube4.node_dof[3 * 40])          # a free velocity dof
+    assert g >= 0
+    rows = np.repeat(np.arange(P.n), np.diff(P.rowptr))
+    P.val[(rows == g) | (P.col == g)] = 0.0
+    _say("singular block")
+    with pytest.raises(gd.GdswError, match="ESINGULAR"):
+        gd.Context(P)
+
+
+def test_repeat_runs_bitwise(gd):
+    P = _problem("die16_L3")
+    r = _dev(random_vector(P.n, 2))
+    _say("repeat runs")
+    with gd.Context(P) as ctx:
+        z1 = ctx.apply(r).cpu().numpy()
+        z2 = ctx.apply(r).cpu().numpy()
+    with gd.Context(P) as ctx2:
+        z3 = ctx2.apply(r).cpu().numpy()
+    assert np.array_equal(z1, z2) and np.array_equal(z1, z3)
