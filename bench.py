@@ -126,7 +126,9 @@ def main():
                    "n_dofs": int(P.n), "nnz": int(len(P.col)), "parts": st0["parts"][:st0["levels"]],
                    "level_dofs": st0["n"][:st0["levels"]], "iterations": iters,
                    "true_rel_residual": res, "precision": args.precision,
-                   "ms_setup": st0["ms_total"], "ms_solve": infos[-1]["ms_total"]},
+                   "ms_setup": st0["ms_total"], "ms_solve": infos[-1]["ms_total"],
+                   "ms_setup_phases": {"host_maps": st0["ms_maps"], "factor": st0["ms_factor"],
+                                       "basis_galerkin": st0["ms_basis"], "coarsest": st0["ms_coarse"]}},
         "roofline": {"kernel": "k_local_solve (level-1 batched pivoted LU forward/backward substitution)",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,

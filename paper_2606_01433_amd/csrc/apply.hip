@@ -9,41 +9,60 @@ namespace gdsw {
 namespace {
 
 constexpr int PW = 64;   // triangle / panel width of the blocked substitution
+constexpr int BIG_BATCH = 512;   // batches this large use two wavefronts per matrix
 
-// One workgroup per part: gather r (pivoted), forward substitution with unit L,
-// backward substitution with U, write the local solution in D_i order.
-// Each 64-wide panel: one wave solves the diagonal triangle with lane shuffles,
-// then all waves stream the panel below (or above) as a GEMV.
-template <typename T>
-__global__ __launch_bounds__(256) void k_local_solve(const int64_t* __restrict__ dom_ptr, const int* __restrict__ gidx,
-                                                     const int64_t* __restrict__ blk_off, const T* __restrict__ blocks,
-                                                     const double* __restrict__ r, double* __restrict__ w) {
+// ---------------------------------------------------------------------------
+// Local solves w_i = A_i^{-1} R_i r with the pivoted LU stored in place.
+// Forward substitution with unit L, then backward with U, in 64-wide panels:
+// the diagonal triangle is solved by one wave (lane j's value is broadcast with
+// readlane; U's diagonal reciprocals are formed in parallel first), then the
+// panel is applied to the remaining rows as a GEMV in row-outer order (each
+// thread streams its row's 64 panel entries with all loads in flight).  The
+// gathered right-hand side lives in LDS.
+//
+// NW wavefronts per matrix share the GEMV rows: two for batches that fill the
+// chip (all matrices resident at once), four for small batches.  Matrices are
+// visited largest first (`order`), so the big ones do not form the tail.
+// FIRST only separates the level-1 launch from deeper levels in profiles.
+// ---------------------------------------------------------------------------
+template <typename T, bool FIRST, int NW>
+__global__ __launch_bounds__(64 * NW) void k_local_solve_wg(const int* __restrict__ order,
+                                                            const int64_t* __restrict__ dom_ptr,
+                                                            const int* __restrict__ gidx,
+                                                            const int64_t* __restrict__ blk_off,
+                                                            const T* __restrict__ blocks,
+                                                            const double* __restrict__ r, double* __restrict__ w) {
+  constexpr int NT = 64 * NW;
   extern __shared__ unsigned char smem_raw[];
   T* x = reinterpret_cast<T*>(smem_raw);
-  const int i = blockIdx.x;
+  const int i = order[blockIdx.x];
   const int64_t base = dom_ptr[i];
   const int n = (int)(dom_ptr[i + 1] - base);
   const T* A = blocks + blk_off[i];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  for (int a = tid; a < n; a += 256) x[a] = (T)r[gidx[base + a]];
+  for (int a = tid; a < n; a += NT) x[a] = (T)r[gidx[base + a]];
   __syncthreads();
   for (int p0 = 0; p0 < n; p0 += PW) {
     const int pw = min(PW, n - p0);
     if (wid == 0) {
-      T xv = (lane < pw) ? x[p0 + lane] : T(0);
-      const T* col = A + (p0 + lane) + (int64_t)p0 * n;
-      for (int j = 0; j < pw; ++j) {
-        const T xj = __shfl(xv, j, WAVE);
-        if (lane > j && lane < pw) xv -= col[(int64_t)j * n] * xj;
-      }
-      if (lane < pw) x[p0 + lane] = xv;
+      const int row = p0 + lane;
+      T d[PW];
+#pragma unroll
+      for (int j = 0; j < PW; ++j) d[j] = (lane < pw && j < lane) ? A[row + (int64_t)(p0 + j) * n] : T(0);
+      T xv = (lane < pw) ? x[row] : T(0);
+#pragma unroll
+      for (int j = 0; j < PW; ++j) xv -= d[j] * lane_value(xv, j);
+      if (lane < pw) x[row] = xv;
     }
     __syncthreads();
-    for (int rr = p0 + pw + tid; rr < n; rr += 256) {
+    for (int rr = p0 + pw + tid; rr < n; rr += NT) {
       const T* Ar = A + rr + (int64_t)p0 * n;
+      T v[PW];
+#pragma unroll
+      for (int j = 0; j < PW; ++j) v[j] = (j < pw) ? Ar[(int64_t)j * n] : T(0);
       T acc = T(0);
-#pragma unroll 16
-      for (int j = 0; j < pw; ++j) acc += Ar[(int64_t)j * n] * x[p0 + j];
+#pragma unroll
+      for (int j = 0; j < PW; ++j) acc += v[j] * x[p0 + min(j, pw - 1)];   // v[j] = 0 past pw
       x[rr] -= acc;
     }
     __syncthreads();
@@ -51,26 +70,34 @@ __global__ __launch_bounds__(256) void k_local_solve(const int64_t* __restrict__
   for (int p0 = ((n - 1) / PW) * PW; p0 >= 0; p0 -= PW) {
     const int pw = min(PW, n - p0);
     if (wid == 0) {
-      T xv = (lane < pw) ? x[p0 + lane] : T(0);
-      const T* col = A + (p0 + lane) + (int64_t)p0 * n;
-      for (int j = pw - 1; j >= 0; --j) {
-        if (lane == j) xv = xv / col[(int64_t)j * n];
-        const T xj = __shfl(xv, j, WAVE);
-        if (lane < j) xv -= col[(int64_t)j * n] * xj;
+      const int row = p0 + lane;
+      T d[PW];
+#pragma unroll
+      for (int j = 0; j < PW; ++j)
+        d[j] = (lane < pw && j > lane && j < pw) ? A[row + (int64_t)(p0 + j) * n] : T(0);
+      const T rd = (lane < pw) ? T(1) / A[row + (int64_t)row * n] : T(0);
+      T xv = (lane < pw) ? x[row] : T(0);
+#pragma unroll
+      for (int j = PW - 1; j >= 0; --j) {
+        if (lane == j) xv *= rd;
+        xv -= d[j] * lane_value(xv, j);
       }
-      if (lane < pw) x[p0 + lane] = xv;
+      if (lane < pw) x[row] = xv;
     }
     __syncthreads();
-    for (int rr = tid; rr < p0; rr += 256) {
+    for (int rr = tid; rr < p0; rr += NT) {
       const T* Ar = A + rr + (int64_t)p0 * n;
+      T v[PW];
+#pragma unroll
+      for (int j = 0; j < PW; ++j) v[j] = (j < pw) ? Ar[(int64_t)j * n] : T(0);
       T acc = T(0);
-#pragma unroll 16
-      for (int j = 0; j < pw; ++j) acc += Ar[(int64_t)j * n] * x[p0 + j];
+#pragma unroll
+      for (int j = 0; j < PW; ++j) acc += v[j] * x[p0 + min(j, pw - 1)];
       x[rr] -= acc;
     }
     __syncthreads();
   }
-  for (int a = tid; a < n; a += 256) w[base + a] = (double)x[a];
+  for (int a = tid; a < n; a += NT) w[base + a] = (double)x[a];
 }
 
 __global__ void k_scatter_sum(int64_t n, const int64_t* __restrict__ sc_ptr, const int* __restrict__ sc_pos,
@@ -157,11 +184,24 @@ __global__ void k_gemv_reduce(int n, int chunks, const double* __restrict__ part
 }  // namespace
 
 template <typename T>
-void local_solves(int nparts, int max_n, const int64_t* dom_ptr, const int* gidx, const int64_t* blk_off,
-                  const T* blocks, const double* r, double* w, hipStream_t s) {
+void local_solves(int nparts, int max_n, const int* order, const int64_t* dom_ptr, const int* gidx,
+                  const int64_t* blk_off, const T* blocks, const double* r, double* w, bool first_level,
+                  hipStream_t s) {
   if (nparts == 0) return;
   const size_t lds = (size_t)max_n * sizeof(T);
-  hipLaunchKernelGGL((k_local_solve<T>), dim3(nparts), dim3(256), lds, s, dom_ptr, gidx, blk_off, blocks, r, w);
+  if (lds > 64 * 1024) throw Error(-1, "local block too large for the LDS-resident right-hand side");
+  const bool big = nparts >= BIG_BATCH;
+#define GDSW_LS(F, NW)                                                                                        \
+  hipLaunchKernelGGL((k_local_solve_wg<T, F, NW>), dim3(nparts), dim3(64 * NW), lds, s, order, dom_ptr, gidx, \
+                     blk_off, blocks, r, w)
+  if (big) {
+    if (first_level) GDSW_LS(true, 2);
+    else GDSW_LS(false, 2);
+  } else {
+    if (first_level) GDSW_LS(true, 4);
+    else GDSW_LS(false, 4);
+  }
+#undef GDSW_LS
   GDSW_LAUNCH_CHECK();
 }
 
@@ -198,10 +238,10 @@ void dense_gemv(int n, const double* Ainv, const double* x, double* y, double* p
   GDSW_LAUNCH_CHECK();
 }
 
-template void local_solves<double>(int, int, const int64_t*, const int*, const int64_t*, const double*,
-                                   const double*, double*, hipStream_t);
-template void local_solves<float>(int, int, const int64_t*, const int*, const int64_t*, const float*, const double*,
-                                  double*, hipStream_t);
+template void local_solves<double>(int, int, const int*, const int64_t*, const int*, const int64_t*,
+                                   const double*, const double*, double*, bool, hipStream_t);
+template void local_solves<float>(int, int, const int*, const int64_t*, const int*, const int64_t*, const float*,
+                                  const double*, double*, bool, hipStream_t);
 template void restrict_phi<double>(int, const int64_t*, const int*, const int64_t*, const int*, const int*,
                                    const int64_t*, const int*, const int64_t*, const double*, const double*, double*,
                                    hipStream_t);

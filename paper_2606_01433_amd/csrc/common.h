@@ -39,6 +39,18 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Value of v held by lane l (l wave-uniform), via v_readlane.
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ int lane_value(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
 // Lower bound of `key` in the sorted array a[0..n).
 __device__ __forceinline__ int lower_bound_i32(const int* a, int n, int key) {
   int lo = 0, hi = n;

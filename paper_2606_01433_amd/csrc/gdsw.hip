@@ -74,6 +74,7 @@ struct Level {
   int max_n = 0;
   int64_t sum_n = 0, sum_n2 = 0;
   std::vector<int> dims;
+  std::vector<int> order_h;
   std::vector<int64_t> blk_off_h;
   int64_t* dom_ptr = nullptr;
   int* dom = nullptr;
@@ -84,6 +85,7 @@ struct Level {
   int* perm = nullptr;
   int* gidx = nullptr;
   int* info = nullptr;
+  int* order = nullptr;          // parts by decreasing block size (apply visiting order)
   int64_t* sc_ptr = nullptr;
   int* sc_pos = nullptr;
   double* w = nullptr;           // local solutions, sum_n
@@ -168,6 +170,13 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
   L.dom_ptr = upload(A, m.dom_ptr, s);
   L.dom = upload(A, m.dom, s);
   L.blk_off = upload(A, L.blk_off_h, s);
+  {
+    std::vector<int> ord(N);
+    for (int i = 0; i < N; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return L.dims[a] > L.dims[b]; });
+    L.order_h = ord;
+    L.order = upload(A, L.order_h, s);
+  }
   L.dim = upload(A, L.dims, s);
   T* blocks = A.alloc_n<T>((size_t)L.sum_n2);
   L.blocks = blocks;
@@ -311,6 +320,8 @@ CsrDev coarse_level(gdsw_ctx* C, Level& L, hipStream_t s, std::vector<int64_t>& 
   galerkin_local<T>(N, (int64_t)m.pcols.size(), L.int_ptr, L.pc_ptr, L.phi_off, phi, W, z_ptr, z_lc, d_v_off, V,
                     d_c_off, Cm, s);
   coarse_pattern(m, a0_rowptr_h, a0_col_h);
+  int max_row = 0;
+  for (int c = 0; c < m.n_coarse; ++c) max_row = std::max(max_row, (int)(a0_rowptr_h[c + 1] - a0_rowptr_h[c]));
   CsrDev K0;
   K0.n = m.n_coarse;
   K0.nnz = (int64_t)a0_col_h.size();
@@ -318,7 +329,7 @@ CsrDev coarse_level(gdsw_ctx* C, Level& L, hipStream_t s, std::vector<int64_t>& 
   int* cl = upload(A, a0_col_h, s);
   double* val = A.alloc_n<double>((size_t)K0.nnz);
   galerkin_assemble(L.K, L.col_ptr, L.col_dofs, L.dof_gcol, L.cp_ptr, L.cp_part, L.cp_lc, L.pc_ptr, L.pcols, d_c_off,
-                    Cm, rp, cl, val, m.n_coarse, bad, s);
+                    Cm, rp, cl, val, m.n_coarse, max_row, bad, s);
   K0.rowptr = rp;
   K0.col = cl;
   K0.val = val;
@@ -549,7 +560,8 @@ void apply_level(gdsw_ctx* C, int l, const double* r, double* z, hipStream_t s) 
     if (C->ev_used + 2 > 4096) drain_events(C);
     GDSW_HIP(hipEventRecord(next_event(C), s));
   }
-  local_solves<T>(L.nparts, L.max_n, L.dom_ptr, L.gidx, L.blk_off, static_cast<const T*>(L.blocks), r, L.w, s);
+  local_solves<T>(L.nparts, L.max_n, L.order, L.dom_ptr, L.gidx, L.blk_off, static_cast<const T*>(L.blocks), r, L.w,
+                  l == 0, s);
   if (prof) GDSW_HIP(hipEventRecord(next_event(C), s));
   scatter_sum(L.n, L.sc_ptr, L.sc_pos, L.w, z, s);
   if (!L.has_coarse) return;

@@ -65,7 +65,7 @@ void galerkin_local(int nparts, int64_t total_crows, const int64_t* int_ptr, con
 void galerkin_assemble(const CsrDev& K, const int64_t* col_ptr, const int* col_dofs, const int* dof_gcol,
                        const int64_t* cp_ptr, const int* cp_part, const int* cp_lc, const int64_t* pc_ptr,
                        const int* pcols, const int64_t* c_off, const double* C, const int64_t* a0_rowptr, const int* a0_col,
-                       double* a0_val, int n_coarse, int* bad, hipStream_t s);
+                       double* a0_val, int n_coarse, int max_row, int* bad, hipStream_t s);
 // Dense column-major copy of a CSR matrix (pre-zeroed).
 void csr_to_dense(const CsrDev& K, double* D, hipStream_t s);
 template <typename T> void set_identity(T* X, int n, hipStream_t s);
@@ -73,9 +73,11 @@ template <typename S, typename D> void convert(const S* in, D* out, int64_t n, h
 
 // ---- apply ----------------------------------------------------------------
 // w[k] = local solutions: per part, gather r at gidx, forward/backward TRSV with the LU in place.
+// order: part ids, largest block first (the visiting order of the workgroups).
 template <typename T>
-void local_solves(int nparts, int max_n, const int64_t* dom_ptr, const int* gidx, const int64_t* blk_off,
-                  const T* blocks, const double* r, double* w, hipStream_t s);
+void local_solves(int nparts, int max_n, const int* order, const int64_t* dom_ptr, const int* gidx,
+                  const int64_t* blk_off, const T* blocks, const double* r, double* w, bool first_level,
+                  hipStream_t s);
 // z[g] = 0.0 + sum_k w[pos[k]] over sc_ptr[g]..sc_ptr[g+1]
 void scatter_sum(int64_t n, const int64_t* sc_ptr, const int* sc_pos, const double* w, double* z, hipStream_t s);
 // rc = Phi^T r

@@ -9,7 +9,7 @@ namespace gdsw {
 
 namespace {
 
-constexpr int DOT_BLOCK_ROWS = 4096;
+constexpr int DOT_BLOCK_ROWS = 512;
 constexpr int DOT_MAXC = 32;
 
 __global__ __launch_bounds__(256) void k_spmv(CsrDev K, const double* __restrict__ x, double* __restrict__ y) {
@@ -57,12 +57,16 @@ __global__ __launch_bounds__(256) void k_multi_dot_partial(int64_t n, int ncols,
   }
 }
 
-__global__ void k_multi_dot_reduce(int nblocks, int ncols, const double* __restrict__ partial, double* __restrict__ h) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per column: lanes stride over the block partials, then a fixed butterfly.
+__global__ __launch_bounds__(256) void k_multi_dot_reduce(int nblocks, int ncols, const double* __restrict__ partial,
+                                                          double* __restrict__ h) {
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= ncols) return;
+  const int lane = threadIdx.x & 63;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * ncols + c];
-  h[c] = s;
+  for (int b = lane; b < nblocks; b += 64) s += partial[(int64_t)b * ncols + c];
+  s = wave_sum(s);
+  if (lane == 0) h[c] = s;
 }
 
 __global__ __launch_bounds__(256) void k_multi_axpy(int64_t n, int ncols, const double* __restrict__ V, int64_t ldv,
@@ -104,7 +108,7 @@ void multi_dot(int64_t n, int ncols, const double* V, int64_t ldv, const double*
   const int nb = multi_dot_blocks(n);
   hipLaunchKernelGGL(k_multi_dot_partial, dim3(nb), dim3(256), 0, s, n, ncols, V, ldv, w, partial);
   GDSW_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_multi_dot_reduce, dim3(blocks_for(ncols, 64)), dim3(64), 0, s, nb, ncols, partial, h);
+  hipLaunchKernelGGL(k_multi_dot_reduce, dim3(blocks_for(ncols, 4)), dim3(256), 0, s, nb, ncols, partial, h);
   GDSW_LAUNCH_CHECK();
 }
 

@@ -40,6 +40,8 @@ template <> struct Mfma<float> {
 };
 
 constexpr int TILE = 64;
+constexpr int PANEL_REG_R = 3;                       // rows per thread of the register panel
+constexpr int PANEL_REG_ROWS = 512 * PANEL_REG_R;
 
 // C[M x N] -= A[M x K] * B[K x N] on the 64x64 tile (ty, tx); K <= KMAX.
 // Column-major operands.  Four waves, each owning a 32x32 quarter computed as
@@ -105,7 +107,7 @@ __global__ __launch_bounds__(256) void k_lu_panel(T* __restrict__ Ab, const int6
                                                   int k) {
   const int i = blockIdx.x;
   const int n = dim[i];
-  if (k >= n) return;
+  if (k >= n || n - k <= PANEL_REG_ROWS) return;   // short panels go to k_lu_panel_reg
   const int jb = min(NB, n - k);
   T* A = Ab + off[i];
   int* piv = pivb + poff[i];
@@ -177,6 +179,124 @@ __global__ __launch_bounds__(256) void k_lu_panel(T* __restrict__ Ab, const int6
       }
     }
     __syncthreads();
+  }
+}
+
+// Register-resident panel factorization for panels of at most 512 * R rows:
+// thread t keeps rows k + t + 512 q (q < R) of the NB panel columns in
+// registers.  Per column: a block-wide argmax (shuffles, then every thread
+// scans the 8 wave winners, so all agree on the pivot without a second
+// barrier), the pivot row and row j are exchanged through LDS, and every row
+// below is scaled and updated in registers.  Two barriers per column; the
+// panel is read and written once.
+template <typename T, int NB, int R>
+__global__ __launch_bounds__(512) void k_lu_panel_reg(T* __restrict__ Ab, const int64_t* __restrict__ off,
+                                                      const int* __restrict__ dim, int* __restrict__ pivb,
+                                                      const int64_t* __restrict__ poff, int* __restrict__ info,
+                                                      int k) {
+  constexpr int NT = 512;
+  const int i = blockIdx.x;
+  const int n = dim[i];
+  if (k >= n || n - k > NT * R) return;    // taller panels go to k_lu_panel
+  const int jb = min(NB, n - k);
+  T* A = Ab + off[i];
+  int* piv = pivb + poff[i];
+  __shared__ double s_val[NT / 64];
+  __shared__ int s_idx[NT / 64];
+  __shared__ T urow[NB];
+  __shared__ T jrow[NB];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  T v[R][NB];
+#pragma clang loop unroll(full)
+  for (int q = 0; q < R; ++q) {
+    const int row = k + tid + NT * q;
+#pragma clang loop unroll(full)
+    for (int c = 0; c < NB; ++c) v[q][c] = (row < n && c < jb) ? A[row + (int64_t)(k + c) * n] : T(0);
+  }
+#pragma clang loop unroll(full)
+  for (int j = 0; j < NB; ++j) {
+    if (j < jb) {
+      const int gj = k + j;
+      double best = -1.0;
+      int bi = n;
+#pragma clang loop unroll(full)
+      for (int q = 0; q < R; ++q) {
+        const int row = k + tid + NT * q;
+        const double a = fabs((double)v[q][j]);
+        if (row >= gj && row < n && a > best) {
+          best = a;
+          bi = row;
+        }
+      }
+#pragma clang loop unroll(full)
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(best, o, WAVE);
+        const int oi = __shfl_xor(bi, o, WAVE);
+        if (ov > best || (ov == best && oi < bi)) {
+          best = ov;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        s_val[w] = best;
+        s_idx[w] = bi;
+      }
+      __syncthreads();
+      double b = s_val[0];
+      int p = s_idx[0];
+#pragma clang loop unroll(full)
+      for (int q = 1; q < NT / 64; ++q)
+        if (s_val[q] > b || (s_val[q] == b && s_idx[q] < p)) {
+          b = s_val[q];
+          p = s_idx[q];
+        }
+      const bool singular = (p >= n || !(b > 0.0));
+      if (p >= n) p = gj;
+      if (tid == 0) {
+        piv[gj] = p;
+        if (singular && info[i] == 0) info[i] = gj + 1;
+      }
+      // owners publish the pivot row (old row p) and row j
+      const int op = p - k, oj = gj - k;
+#pragma clang loop unroll(full)
+      for (int q = 0; q < R; ++q) {
+        if (op == tid + NT * q) {
+#pragma clang loop unroll(full)
+          for (int c = 0; c < NB; ++c) urow[c] = v[q][c];
+        }
+        if (oj == tid + NT * q) {
+#pragma clang loop unroll(full)
+          for (int c = 0; c < NB; ++c) jrow[c] = v[q][c];
+        }
+      }
+      __syncthreads();
+      const T pv = urow[j];
+#pragma clang loop unroll(full)
+      for (int q = 0; q < R; ++q) {
+        const int lr = tid + NT * q;
+        const int row = k + lr;
+        if (lr == oj) {
+#pragma clang loop unroll(full)
+          for (int c = 0; c < NB; ++c) v[q][c] = urow[c];
+        } else if (lr == op) {
+#pragma clang loop unroll(full)
+          for (int c = 0; c < NB; ++c) v[q][c] = jrow[c];
+        }
+        if (row > gj && row < n) {
+          const T l = (pv != T(0)) ? v[q][j] / pv : v[q][j];
+          v[q][j] = l;
+#pragma clang loop unroll(full)
+          for (int c = j + 1; c < NB; ++c) v[q][c] -= l * urow[c];
+        }
+      }
+    }
+  }
+#pragma clang loop unroll(full)
+  for (int q = 0; q < R; ++q) {
+    const int row = k + tid + NT * q;
+#pragma clang loop unroll(full)
+    for (int c = 0; c < NB; ++c)
+      if (row < n && c < jb) A[row + (int64_t)(k + c) * n] = v[q][c];
   }
 }
 
@@ -366,8 +486,13 @@ void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
   constexpr int NB = LU_NB;
   const unsigned colblocks = blocks_for(b.max_n, 64);
   for (int k = 0; k < b.max_n; k += NB) {
-    hipLaunchKernelGGL((k_lu_panel<T, NB>), dim3(b.count), dim3(256), 0, s, A, b.off, b.dim, b.piv, b.poff,
-                       b.info, k);
+    if (b.max_n - k > PANEL_REG_ROWS) {
+      hipLaunchKernelGGL((k_lu_panel<T, NB>), dim3(b.count), dim3(256), 0, s, A, b.off, b.dim, b.piv, b.poff,
+                         b.info, k);
+      GDSW_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL((k_lu_panel_reg<T, NB, PANEL_REG_R>), dim3(b.count), dim3(512), 0, s, A, b.off, b.dim, b.piv,
+                       b.poff, b.info, k);
     GDSW_LAUNCH_CHECK();
     hipLaunchKernelGGL((k_lu_swap_trsm<T, NB>), dim3(b.count, colblocks), dim3(64), 0, s, A, b.off, b.dim,
                        b.piv, b.poff, k);

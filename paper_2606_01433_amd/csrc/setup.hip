@@ -87,6 +87,9 @@ __global__ void k_gather_index(int nparts, int64_t total, const int64_t* __restr
 }
 
 // W[a, c] = sum_h K[g_a, h] Phi[h, c] over the row of interior dof g_a (one wave per row).
+// The lanes first fetch 64 couplings of the row and classify them (interior row
+// or interface column of this part); the couplings are then applied in row
+// order, lane c accumulating column c.
 template <typename T>
 __global__ __launch_bounds__(256) void k_galerkin_w(CsrDev K, int nparts, int64_t total_rows,
                                                     const int64_t* __restrict__ int_ptr,
@@ -108,25 +111,34 @@ __global__ __launch_bounds__(256) void k_galerkin_w(CsrDev K, int nparts, int64_
   const int* pc = pcols + pc_ptr[i];
   const T* ph = phi + phi_off[i];
   double* Wp = W + phi_off[i];
+  const int64_t e_beg = K.rowptr[g], e_end = K.rowptr[g + 1];
   for (int c0 = 0; c0 < m; c0 += 64) {
     const int c = c0 + lane;
     double acc = 0.0;
-    for (int64_t e = K.rowptr[g]; e < K.rowptr[g + 1]; ++e) {
-      const int h = K.col[e];
-      const double v = K.val[e];
-      if (dof_ipart[h] == i) {
-        if (c < m) acc += v * (double)ph[dof_irow[h] + (int64_t)c * nI];
-      } else {
-        const int gc = dof_gcol[h];
-        if (gc >= 0) {
-          const int lc = lower_bound_i32(pc, m, gc);
-          if (lc < m && pc[lc] == gc) {
-            if (lc == c) acc += v;
-          } else {
-            *bad = 1;
-          }
+    for (int64_t e0 = e_beg; e0 < e_end; e0 += 64) {
+      const int64_t e = e0 + lane;
+      int ir = -1, lc = -1;
+      double v = 0.0;
+      if (e < e_end) {
+        const int h = K.col[e];
+        v = K.val[e];
+        if (dof_ipart[h] == i) {
+          ir = dof_irow[h];
         } else {
-          *bad = 1;
+          const int gc = dof_gcol[h];
+          const int p = gc >= 0 ? lower_bound_i32(pc, m, gc) : m;
+          if (p < m && pc[p] == gc) lc = p;
+          else *bad = 1;            // K couples an interior dof outside its part's closure
+        }
+      }
+      const int cnt = (int)min((int64_t)64, e_end - e0);
+      for (int l = 0; l < cnt; ++l) {
+        const double vl = lane_value(v, l);
+        const int irl = lane_value(ir, l);
+        if (irl >= 0) {
+          if (c < m) acc += vl * (double)ph[irl + (int64_t)c * nI];
+        } else if (lane_value(lc, l) == c) {
+          acc += vl;
         }
       }
     }
@@ -156,12 +168,26 @@ __global__ __launch_bounds__(256) void k_galerkin_v(CsrDev K, int nparts, int64_
   const int m = (int)(pc_ptr[i + 1] - pc_ptr[i]);
   const T* ph = phi + phi_off[i];
   double* Vp = V + v_off[i];
+  const int64_t e_beg = K.rowptr[g], e_end = K.rowptr[g + 1];
   for (int c0 = 0; c0 < m; c0 += 64) {
     const int c = c0 + lane;
     double acc = 0.0;
-    for (int64_t e = K.rowptr[g]; e < K.rowptr[g + 1]; ++e) {
-      const int h = K.col[e];
-      if (dof_ipart[h] == i && c < m) acc += K.val[e] * (double)ph[dof_irow[h] + (int64_t)c * nI];
+    for (int64_t e0 = e_beg; e0 < e_end; e0 += 64) {
+      const int64_t e = e0 + lane;
+      int ir = -1;
+      double v = 0.0;
+      if (e < e_end) {
+        const int h = K.col[e];
+        if (dof_ipart[h] == i) {
+          ir = dof_irow[h];
+          v = K.val[e];
+        }
+      }
+      const int cnt = (int)min((int64_t)64, e_end - e0);
+      for (int l = 0; l < cnt; ++l) {
+        const int irl = lane_value(ir, l);
+        if (irl >= 0 && c < m) acc += lane_value(v, l) * (double)ph[irl + (int64_t)c * nI];
+      }
     }
     if (c < m) Vp[t + (int64_t)c * nZ] = acc;
   }
@@ -204,29 +230,56 @@ __global__ __launch_bounds__(256) void k_galerkin_local(int nparts, int64_t tota
   }
 }
 
-// One thread per coarse row c: interface-interface couplings of K, then the parts' C_i, ascending part id.
-__global__ void k_galerkin_assemble(CsrDev K, const int64_t* __restrict__ col_ptr, const int* __restrict__ col_dofs,
-                                    const int* __restrict__ dof_gcol, const int64_t* __restrict__ cp_ptr,
-                                    const int* __restrict__ cp_part, const int* __restrict__ cp_lc,
-                                    const int64_t* __restrict__ pc_ptr, const int* __restrict__ pcols,
-                                    const int64_t* __restrict__ c_off, const double* __restrict__ C,
-                                    const int64_t* __restrict__ a0_rowptr, const int* __restrict__ a0_col,
-                                    double* __restrict__ a0_val, int n_coarse, int* __restrict__ bad) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per coarse row c, accumulating in wave-private LDS: the
+// interface-interface couplings of K (dof by dof, in row order), then the
+// parts' C_i in ascending part order.  Lanes look up 64 contributions at a
+// time; the additions are applied in that fixed order through readlane.
+__global__ __launch_bounds__(64) void k_galerkin_assemble(CsrDev K, const int64_t* __restrict__ col_ptr,
+                                                          const int* __restrict__ col_dofs,
+                                                          const int* __restrict__ dof_gcol,
+                                                          const int64_t* __restrict__ cp_ptr,
+                                                          const int* __restrict__ cp_part,
+                                                          const int* __restrict__ cp_lc,
+                                                          const int64_t* __restrict__ pc_ptr,
+                                                          const int* __restrict__ pcols,
+                                                          const int64_t* __restrict__ c_off,
+                                                          const double* __restrict__ C,
+                                                          const int64_t* __restrict__ a0_rowptr,
+                                                          const int* __restrict__ a0_col, double* __restrict__ a0_val,
+                                                          int n_coarse, int* __restrict__ bad) {
+  extern __shared__ double rv[];
+  const int c = blockIdx.x;
   if (c >= n_coarse) return;
+  const int lane = threadIdx.x;
   const int64_t rb = a0_rowptr[c];
   const int len = (int)(a0_rowptr[c + 1] - rb);
   const int* rc = a0_col + rb;
-  double* rv = a0_val + rb;
-  for (int k = 0; k < len; ++k) rv[k] = 0.0;
+  for (int k = lane; k < len; k += 64) rv[k] = 0.0;
+  __syncthreads();
   for (int64_t q = col_ptr[c]; q < col_ptr[c + 1]; ++q) {
     const int g = col_dofs[q];
-    for (int64_t e = K.rowptr[g]; e < K.rowptr[g + 1]; ++e) {
-      const int gc = dof_gcol[K.col[e]];
-      if (gc >= 0) {
-        const int pos = lower_bound_i32(rc, len, gc);
-        if (pos < len && rc[pos] == gc) rv[pos] += K.val[e];
-        else *bad = 1;
+    const int64_t e_beg = K.rowptr[g], e_end = K.rowptr[g + 1];
+    for (int64_t e0 = e_beg; e0 < e_end; e0 += 64) {
+      const int64_t e = e0 + lane;
+      int pos = -1;
+      double v = 0.0;
+      if (e < e_end) {
+        const int gc = dof_gcol[K.col[e]];
+        if (gc >= 0) {
+          const int p = lower_bound_i32(rc, len, gc);
+          if (p < len && rc[p] == gc) {
+            pos = p;
+            v = K.val[e];
+          } else {
+            *bad = 1;
+          }
+        }
+      }
+      const int cnt = (int)min((int64_t)64, e_end - e0);
+      for (int l = 0; l < cnt; ++l) {
+        const int pl = lane_value(pos, l);
+        const double vl = lane_value(v, l);
+        if (pl >= 0 && lane == (pl & 63)) rv[pl] += vl;
       }
     }
   }
@@ -236,12 +289,25 @@ __global__ void k_galerkin_assemble(CsrDev K, const int64_t* __restrict__ col_pt
     const int m = (int)(pc_ptr[i + 1] - pc_ptr[i]);
     const int* pc = pcols + pc_ptr[i];
     const double* Ci = C + c_off[i];
-    for (int l2 = 0; l2 < m; ++l2) {
-      const int pos = lower_bound_i32(rc, len, pc[l2]);
-      if (pos < len && rc[pos] == pc[l2]) rv[pos] += Ci[lc + (int64_t)l2 * m];
-      else *bad = 1;
+    for (int l0 = 0; l0 < m; l0 += 64) {
+      const int l2 = l0 + lane;
+      int pos = -1;
+      double v = 0.0;
+      if (l2 < m) {
+        const int p = lower_bound_i32(rc, len, pc[l2]);
+        if (p < len && rc[p] == pc[l2]) {
+          pos = p;
+          v = Ci[lc + (int64_t)l2 * m];
+        } else {
+          *bad = 1;
+        }
+      }
+      // distinct columns of one part land on distinct positions: no ordering conflict
+      if (pos >= 0) rv[pos] += v;
     }
   }
+  __syncthreads();
+  for (int k = lane; k < len; k += 64) a0_val[rb + k] = rv[k];
 }
 
 __global__ void k_csr_to_dense(CsrDev K, double* __restrict__ D) {
@@ -326,11 +392,12 @@ void galerkin_local(int nparts, int64_t total_crows, const int64_t* int_ptr, con
 void galerkin_assemble(const CsrDev& K, const int64_t* col_ptr, const int* col_dofs, const int* dof_gcol,
                        const int64_t* cp_ptr, const int* cp_part, const int* cp_lc, const int64_t* pc_ptr,
                        const int* pcols, const int64_t* c_off, const double* C, const int64_t* a0_rowptr,
-                       const int* a0_col, double* a0_val, int n_coarse, int* bad, hipStream_t s) {
+                       const int* a0_col, double* a0_val, int n_coarse, int max_row, int* bad, hipStream_t s) {
   if (n_coarse == 0) return;
-  hipLaunchKernelGGL(k_galerkin_assemble, dim3(blocks_for(n_coarse, 64)), dim3(64), 0, s, K, col_ptr, col_dofs,
-                     dof_gcol, cp_ptr, cp_part, cp_lc, pc_ptr, pcols, c_off, C, a0_rowptr, a0_col, a0_val, n_coarse,
-                     bad);
+  if ((size_t)max_row * sizeof(double) > 64 * 1024) throw Error(-1, "coarse row too long for the LDS accumulator");
+  hipLaunchKernelGGL(k_galerkin_assemble, dim3(n_coarse), dim3(64), (size_t)max_row * sizeof(double), s, K, col_ptr,
+                     col_dofs, dof_gcol, cp_ptr, cp_part, cp_lc, pc_ptr, pcols, c_off, C, a0_rowptr, a0_col, a0_val,
+                     n_coarse, bad);
   GDSW_LAUNCH_CHECK();
 }
 

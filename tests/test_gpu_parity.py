@@ -178,7 +178,7 @@ def test_singular_local_block_is_reported(gd, cube4):
     P = copy.copy(cube4)
     P.val = cube4.val.copy()
     K = cube4.K()
-    g = int(cube4.node_dof[3 * 40])          # a free velocity dof
+    g = int(cube4.node_dof[cube4.node_dof >= 0][0])     # a free velocity dof
     assert g >= 0
     rows = np.repeat(np.arange(P.n), np.diff(P.rowptr))
     P.val[(rows == g) | (P.col == g)] = 0.0
