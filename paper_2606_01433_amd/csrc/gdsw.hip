@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstdlib>
 #include <cmath>
 #include <cstring>
@@ -136,8 +137,17 @@ struct gdsw_ctx {
   // event pairs around level-1 local-solve launches (profile = 1)
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
+  // the coarse chain of the apply runs on `side`, forked from and joined to the caller's stream
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   ~gdsw_ctx() {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) {
+      (void)hipStreamSynchronize(side);
+      (void)hipStreamDestroy(side);
+    }
   }
 };
 
@@ -338,7 +348,7 @@ CsrDev coarse_level(gdsw_ctx* C, Level& L, hipStream_t s, std::vector<int64_t>& 
   return K0;
 }
 
-void coarsest_inverse(gdsw_ctx* C, const CsrDev& K, hipStream_t s) {
+void coarsest_inverse(gdsw_ctx* C, const CsrDev& K, hipStream_t s, double** dense_out, int** info_out) {
   Arena& A = C->arena;
   const int n = (int)K.n;
   C->nc = n;
@@ -366,19 +376,13 @@ void coarsest_inverse(gdsw_ctx* C, const CsrDev& K, hipStream_t s) {
   lu_solve_batched<double>(b, D, X, d_off, d_dim, n, s);
   C->ainv = X;
   C->gemv_partial = A.alloc_n<double>((size_t)dense_gemv_partials(n));
-  int hinfo = 0;
-  GDSW_HIP(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, s));
-  GDSW_HIP(hipStreamSynchronize(s));
-  A.free_one(D);
-  if (hinfo != 0)
-    throw Error(GDSW_ESINGULAR, "coarsest operator (order " + std::to_string(n) + ") has a zero pivot at column " +
-                                    std::to_string(hinfo - 1));
+  *dense_out = D;
+  *info_out = info;
 }
 
-void check_info(const int* dinfo, int N, const std::string& what, int level, hipStream_t s) {
+void check_info(const int* dinfo, int N, const std::string& what, int level, hipStream_t) {
   std::vector<int> h(N);
-  GDSW_HIP(hipMemcpyAsync(h.data(), dinfo, N * sizeof(int), hipMemcpyDeviceToHost, s));
-  GDSW_HIP(hipStreamSynchronize(s));
+  GDSW_HIP(hipMemcpy(h.data(), dinfo, N * sizeof(int), hipMemcpyDeviceToHost));
   for (int i = 0; i < N; ++i)
     if (h[i] != 0)
       throw Error(GDSW_ESINGULAR, what + " of level " + std::to_string(level) + ", part " + std::to_string(i) +
@@ -403,14 +407,21 @@ void validate_problem(const gdsw_problem* p) {
 Plan plan_levels(const gdsw_problem* p, const gdsw_options& o) {
   validate_problem(p);
   Plan P;
+  const bool dbg = std::getenv("GDSW_DEBUG_PLAN") != nullptr;
+  double tq = now_ms();
+  auto lap = [&](const char* what) {
+    if (dbg) { double t = now_ms(); fprintf(stderr, "plan %s %.2f ms\n", what, t - tq); tq = t; }
+  };
   P.meshes.emplace_back();
   std::string err = build_level1_mesh(p->n, p->n_nodes, p->node_dof, p->n_elem, p->elem_node, p->elem_pdof,
                                       p->elem_part, p->n_parts[0], P.meshes[0]);
   if (!err.empty()) throw Error(GDSW_EINVAL, err);
+  lap("mesh1");
   const int L = p->levels;
   for (int l = 1; l < L; ++l) {
     P.maps.emplace_back();
     build_maps(P.meshes[l - 1], o.overlap, P.maps.back());
+    lap("maps");
     P.schwarz = l;
     const bool last = (l == L - 1);
     if (last) {
@@ -423,6 +434,7 @@ Plan plan_levels(const gdsw_problem* p, const gdsw_options& o) {
     P.meshes.emplace_back();
     err = build_next_mesh(P.meshes[l - 1], P.maps.back(), p->part_parent[l - 1], nxt, P.meshes[l]);
     if (!err.empty()) throw Error(GDSW_EINVAL, err);
+    lap("next");
     if (nxt == 1) {          // a single part: this coarse problem becomes the coarsest
       P.coarsest = true;
       break;
@@ -432,14 +444,27 @@ Plan plan_levels(const gdsw_problem* p, const gdsw_options& o) {
   return P;
 }
 
+// Host maps of level l+1 are built while the GPU works on level l: every
+// launch is asynchronous and the pivot / consistency flags are checked once,
+// after the last level.
 template <typename T>
 void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
   const double t0 = now_ms();
-  Plan P = plan_levels(p, C->opt);
-  const double t1 = now_ms();
   gdsw_stats& st = C->stats;
   std::memset(&st, 0, sizeof(st));
-  st.ms_maps = t1 - t0;
+  validate_problem(p);
+  double host_ms = 0;
+  auto host = [&](auto&& fn) {
+    const double a = now_ms();
+    fn();
+    host_ms += now_ms() - a;
+  };
+  std::vector<LevelMesh> meshes(1);
+  host([&] {
+    std::string err = build_level1_mesh(p->n, p->n_nodes, p->node_dof, p->n_elem, p->elem_node, p->elem_pdof,
+                                        p->elem_part, p->n_parts[0], meshes[0]);
+    if (!err.empty()) throw Error(GDSW_EINVAL, err);
+  });
   // level-1 operator: a private copy of the caller's CSR
   CsrDev K;
   K.n = p->n;
@@ -459,20 +484,30 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
     K.col = cl;
     K.val = vl;
   }
-  C->levels.resize(P.schwarz);
-  hipEvent_t ev[3];
-  for (auto& e : ev) GDSW_HIP(hipEventCreate(&e));
-  GDSW_HIP(hipEventRecord(ev[0], s));
-  float ms_factor = 0, ms_basis = 0;
-  for (int l = 0; l < P.schwarz; ++l) {
-    Level& L = C->levels[l];
+  const int Lp = p->levels;
+  C->levels.reserve(Lp);
+  std::vector<hipEvent_t> evs;
+  auto mark = [&]() {
+    hipEvent_t e;
+    GDSW_HIP(hipEventCreate(&e));
+    GDSW_HIP(hipEventRecord(e, s));
+    evs.push_back(e);
+    return (int)evs.size() - 1;
+  };
+  std::vector<std::pair<int, int>> ev_factor, ev_basis;
+  bool coarsest = false;
+  for (int l = 0; l < Lp - 1; ++l) {
+    C->levels.emplace_back();
+    Level& L = C->levels.back();
     L.index = l + 1;
-    L.nparts = P.meshes[l].n_parts;
+    L.nparts = meshes[l].n_parts;
     L.n = K.n;
     L.K = K;
-    L.maps = std::move(P.maps[l]);
+    host([&] { build_maps(meshes[l], C->opt.overlap, L.maps); });
+    const int e0 = mark();
     factor_level<T>(C, L, s);
-    GDSW_HIP(hipEventRecord(ev[1], s));
+    const int e1 = mark();
+    ev_factor.push_back({e0, e1});
     st.n[l] = L.n;
     st.parts[l] = L.nparts;
     st.sum_ni[l] = L.sum_n;
@@ -482,52 +517,80 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
     double f = 0;
     for (int d : L.dims) f += (2.0 / 3.0) * d * (double)d * d;
     st.factor_flops[l] = f;
-    const bool needs_coarse = (l + 1 < P.schwarz) || P.coarsest;
-    if (needs_coarse) {
-      std::vector<int64_t> rp;
-      std::vector<int> cl;
-      K = coarse_level<T>(C, L, s, rp, cl);
-      st.interior_flops[l] = L.interior_flops;
+    const bool last = (l == Lp - 2);
+    if (last && C->opt.no_coarse) break;
+    if (L.maps.n_coarse == 0) throw Error(GDSW_EINVAL, "coarse space of level " + std::to_string(l + 1) + " is empty");
+    int nxt = 0;
+    if (!last) {
+      nxt = p->n_parts[l + 1];
+      if (nxt <= 0) throw Error(GDSW_EINVAL, "n_parts must be positive");
     }
-    GDSW_HIP(hipEventRecord(ev[2], s));
-    GDSW_HIP(hipEventSynchronize(ev[2]));
-    float a = 0, b = 0;
-    GDSW_HIP(hipEventElapsedTime(&a, ev[0], ev[1]));
-    GDSW_HIP(hipEventElapsedTime(&b, ev[1], ev[2]));
-    ms_factor += a;
-    ms_basis += b;
-    GDSW_HIP(hipEventRecord(ev[0], s));
-    check_info(L.info, L.nparts, "local block", L.index, s);
-    if (L.has_coarse) {
-      check_info(L.iinfo, L.nparts, "interior block", L.index, s);
-      int hb = 0;
-      GDSW_HIP(hipMemcpyAsync(&hb, L.bad, sizeof(int), hipMemcpyDeviceToHost, s));
-      GDSW_HIP(hipStreamSynchronize(s));
-      if (hb)
-        throw Error(GDSW_EINVAL, "level " + std::to_string(L.index) +
-                                     ": K couples dofs that share no element (not an element-assembled operator)");
+    std::vector<int64_t> rp;
+    std::vector<int> cl;
+    K = coarse_level<T>(C, L, s, rp, cl);
+    ev_basis.push_back({e1, mark()});
+    st.interior_flops[l] = L.interior_flops;
+    if (last || nxt == 1) {          // a single coarse part: that coarse problem is the coarsest
+      coarsest = true;
+      break;
     }
+    meshes.emplace_back();
+    host([&] {
+      std::string err = build_next_mesh(meshes[l], L.maps, p->part_parent[l], nxt, meshes[l + 1]);
+      if (!err.empty()) throw Error(GDSW_EINVAL, err);
+    });
   }
-  st.levels = P.schwarz + (P.coarsest ? 1 : 0);
+  const int schwarz = (int)C->levels.size();
+  st.levels = schwarz + (coarsest ? 1 : 0);
   {
     const Level& L1 = C->levels[0];
     double bytes = 0;
     for (int d : L1.dims) bytes += (double)d * d * sizeof(T) + 20.0 * d;
     st.local_solve_bytes = bytes;
   }
-  if (P.coarsest) {
+  int ec0 = -1, ec1 = -1;
+  double* dense = nullptr;
+  int* cinfo = nullptr;
+  if (coarsest) {
     C->has_coarsest = true;
     C->nnz_coarsest = K.nnz;
-    const double tc = now_ms();
-    coarsest_inverse(C, K, s);
-    st.ms_coarse = now_ms() - tc;
-    st.n[P.schwarz] = K.n;
-    st.nnz[P.schwarz] = K.nnz;
-    st.factor_flops[P.schwarz] = (2.0 / 3.0) * K.n * (double)K.n * K.n + 2.0 * K.n * (double)K.n * K.n;
+    ec0 = mark();
+    coarsest_inverse(C, K, s, &dense, &cinfo);
+    ec1 = mark();
+    st.n[schwarz] = K.n;
+    st.nnz[schwarz] = K.nnz;
+    st.factor_flops[schwarz] = (2.0 / 3.0) * K.n * (double)K.n * K.n + 2.0 * K.n * (double)K.n * K.n;
   }
-  for (auto& e : ev) (void)hipEventDestroy(e);
-  st.ms_factor = ms_factor;
-  st.ms_basis = ms_basis;
+  GDSW_HIP(hipStreamSynchronize(s));
+  for (const Level& L : C->levels) {
+    check_info(L.info, L.nparts, "local block", L.index, s);
+    if (L.has_coarse) {
+      check_info(L.iinfo, L.nparts, "interior block", L.index, s);
+      int hb = 0;
+      GDSW_HIP(hipMemcpy(&hb, L.bad, sizeof(int), hipMemcpyDeviceToHost));
+      if (hb)
+        throw Error(GDSW_EINVAL, "level " + std::to_string(L.index) +
+                                     ": K couples dofs that share no element (not an element-assembled operator)");
+    }
+  }
+  if (coarsest) {
+    int hinfo = 0;
+    GDSW_HIP(hipMemcpy(&hinfo, cinfo, sizeof(int), hipMemcpyDeviceToHost));
+    C->arena.free_one(dense);
+    if (hinfo != 0)
+      throw Error(GDSW_ESINGULAR, "coarsest operator (order " + std::to_string(K.n) + ") has a zero pivot at column " +
+                                      std::to_string(hinfo - 1));
+  }
+  auto span = [&](int a, int b) {
+    float ms = 0;
+    GDSW_HIP(hipEventElapsedTime(&ms, evs[a], evs[b]));
+    return (double)ms;
+  };
+  for (auto& pr : ev_factor) st.ms_factor += span(pr.first, pr.second);
+  for (auto& pr : ev_basis) st.ms_basis += span(pr.first, pr.second);
+  if (coarsest) st.ms_coarse = span(ec0, ec1);
+  for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+  st.ms_maps = host_ms;
   st.ms_total = now_ms() - t0;
 }
 
@@ -553,8 +616,31 @@ void drain_events(gdsw_ctx* C) {
 }
 
 template <typename T>
+void apply_level(gdsw_ctx* C, int l, const double* r, double* z, hipStream_t s);
+
+// Coarse correction of level l: Phi^T r, the next level (or the coarsest solve), then L.yc.
+template <typename T>
+void coarse_chain(gdsw_ctx* C, int l, const double* r, hipStream_t s) {
+  Level& L = C->levels[l];
+  const T* phi = static_cast<const T*>(L.phi);
+  restrict_phi<T>(L.n_coarse, L.col_ptr, L.col_dofs, L.cp_ptr, L.cp_part, L.cp_lc, L.int_ptr, L.inter, L.phi_off, phi,
+                  r, L.rc, s);
+  if (l + 1 < (int)C->levels.size()) apply_level<T>(C, l + 1, L.rc, L.yc, s);
+  else dense_gemv(C->nc, C->ainv, L.rc, L.yc, C->gemv_partial, s);
+}
+
+// z = B_l r (eq. (2.2) from level l down).  On level 1 the coarse chain runs on
+// the side stream concurrently with the local solves; both join before z += Phi y.
+template <typename T>
 void apply_level(gdsw_ctx* C, int l, const double* r, double* z, hipStream_t s) {
   Level& L = C->levels[l];
+  const bool fork = (l == 0) && L.has_coarse && C->side;
+  if (fork) {
+    GDSW_HIP(hipEventRecord(C->ev_fork, s));
+    GDSW_HIP(hipStreamWaitEvent(C->side, C->ev_fork, 0));
+    coarse_chain<T>(C, l, r, C->side);
+    GDSW_HIP(hipEventRecord(C->ev_join, C->side));
+  }
   const bool prof = C->opt.profile && l == 0;
   if (prof) {
     if (C->ev_used + 2 > 4096) drain_events(C);
@@ -565,11 +651,9 @@ void apply_level(gdsw_ctx* C, int l, const double* r, double* z, hipStream_t s) 
   if (prof) GDSW_HIP(hipEventRecord(next_event(C), s));
   scatter_sum(L.n, L.sc_ptr, L.sc_pos, L.w, z, s);
   if (!L.has_coarse) return;
+  if (fork) GDSW_HIP(hipStreamWaitEvent(s, C->ev_join, 0));
+  else coarse_chain<T>(C, l, r, s);
   const T* phi = static_cast<const T*>(L.phi);
-  restrict_phi<T>(L.n_coarse, L.col_ptr, L.col_dofs, L.cp_ptr, L.cp_part, L.cp_lc, L.int_ptr, L.inter, L.phi_off, phi,
-                  r, L.rc, s);
-  if (l + 1 < (int)C->levels.size()) apply_level<T>(C, l + 1, L.rc, L.yc, s);
-  else dense_gemv(C->nc, C->ainv, L.rc, L.yc, C->gemv_partial, s);
   prolong_add<T>(L.n, L.dof_gcol, L.dof_ipart, L.dof_irow, L.int_ptr, L.pc_ptr, L.pcols, L.phi_off, phi, L.yc, z, s);
 }
 
@@ -760,6 +844,9 @@ int gdsw_setup(const gdsw_problem* prob, const gdsw_options* opt, void* stream, 
       throw Error(GDSW_EINVAL, "invalid options");
     C->mixed = C->opt.precision == GDSW_MIXED;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    GDSW_HIP(hipStreamCreateWithFlags(&C->side, hipStreamNonBlocking));
+    GDSW_HIP(hipEventCreateWithFlags(&C->ev_fork, hipEventDisableTiming));
+    GDSW_HIP(hipEventCreateWithFlags(&C->ev_join, hipEventDisableTiming));
     if (C->mixed) gdsw::setup_impl<float>(C, prob, s);
     else gdsw::setup_impl<double>(C, prob, s);
     GDSW_HIP(hipStreamSynchronize(s));

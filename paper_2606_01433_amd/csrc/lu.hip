@@ -6,13 +6,15 @@
 // dimension = order.  Pivot rows follow the LAPACK convention (ipiv[j] = row
 // swapped with row j at step j); ties in the pivot search go to the lowest row.
 //
-// Right-looking blocked algorithm over panels of NB columns, one launch per
-// phase and panel for the whole (uneven) batch:
-//   panel : factor A[k:n, k:k+jb] (one workgroup per matrix; wave shuffles
-//           find the pivot);
-//   swap  : apply the panel's interchanges to the other columns and solve
-//           U12 = L11^{-1} A12 (one thread per column);
-//   update: A22 -= L21 U12 with MFMA (16x16x4, FP64 or FP32), 64x64 tiles.
+// Right-looking blocked algorithm with two-level blocking, one launch per
+// phase for the whole (uneven) batch.  Each outer step covers 2*NB columns:
+//   panel  : factor sub-panel 1, A[k:n, k:k+NB] (one workgroup per matrix,
+//            rows held in registers; wave shuffles find the pivot);
+//   inner  : its interchanges and U on sub-panel 2's columns, then the rank-NB
+//            MFMA update of sub-panel 2; factor sub-panel 2;
+//   outer  : the step's interchanges on all other columns, U12 = L11^{-1} A12
+//            (one thread per column), A22 -= L21 U12 with MFMA (16x16x4, FP64
+//            or FP32), 64x64 tiles, inner dimension 2*NB.
 #include "common.h"
 #include "kernels.h"
 
@@ -345,6 +347,138 @@ __global__ __launch_bounds__(64) void k_lu_swap_trsm(T* __restrict__ Ab, const i
     if (r < jb) col[k + r] = x[r];
 }
 
+// ---- two-level blocking: outer width 2 * NB, two NB-wide sub-panels ----------
+
+// Sub-panel 1 of outer step k is factored; bring columns [k+NB, k+2NB) up to
+// date: its interchanges, then U = L11^{-1} A on rows [k, k+NB).
+template <typename T, int NB>
+__global__ __launch_bounds__(64) void k_lu_inner_swap_trsm(T* __restrict__ Ab, const int64_t* __restrict__ off,
+                                                           const int* __restrict__ dim, const int* __restrict__ pivb,
+                                                           const int64_t* __restrict__ poff, int k) {
+  const int i = blockIdx.x;
+  const int n = dim[i];
+  if (k + NB >= n) return;                  // no second sub-panel
+  T* A = Ab + off[i];
+  const int* piv = pivb + poff[i];
+  __shared__ T L11[NB * NB];
+  for (int t = threadIdx.x; t < NB * NB; t += 64) {
+    const int r = t % NB, c = t / NB;
+    L11[t] = A[(k + r) + (int64_t)(k + c) * n];
+  }
+  __syncthreads();
+  const int c = k + NB + (int)threadIdx.x;
+  if (threadIdx.x >= NB || c >= n) return;
+  T* col = A + (int64_t)c * n;
+  for (int j = k; j < k + NB; ++j) {
+    const int p = piv[j];
+    if (p != j) {
+      const T t = col[j];
+      col[j] = col[p];
+      col[p] = t;
+    }
+  }
+  T x[NB];
+#pragma unroll
+  for (int r = 0; r < NB; ++r) x[r] = col[k + r];
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+#pragma unroll
+    for (int r = j + 1; r < NB; ++r) x[r] -= L11[r + j * NB] * x[j];
+#pragma unroll
+  for (int r = 0; r < NB; ++r) col[k + r] = x[r];
+}
+
+// After both sub-panels of outer step k: interchanges on the columns left of
+// sub-panel 2 (all pivots of the step left of k; sub-panel 2's pivots on
+// sub-panel 1).
+template <typename T, int NB>
+__global__ __launch_bounds__(64) void k_lu_outer_swap_left(T* __restrict__ Ab, const int64_t* __restrict__ off,
+                                                           const int* __restrict__ dim, const int* __restrict__ pivb,
+                                                           const int64_t* __restrict__ poff, int k) {
+  const int i = blockIdx.x;
+  const int n = dim[i];
+  if (k >= n) return;
+  const int c = blockIdx.y * 64 + threadIdx.x;
+  if (c >= k + NB || c >= n) return;
+  const int kw = min(2 * NB, n - k);
+  T* col = Ab + off[i] + (int64_t)c * n;
+  const int* piv = pivb + poff[i];
+  for (int j = (c < k ? k : k + NB); j < k + kw; ++j) {
+    const int p = piv[j];
+    if (p != j) {
+      const T t = col[j];
+      col[j] = col[p];
+      col[p] = t;
+    }
+  }
+}
+
+// Columns right of outer step k: all of its interchanges, then
+// U12 = L11^{-1} A12 with the 2NB x 2NB unit lower L11.
+template <typename T, int NB>
+__global__ __launch_bounds__(64) void k_lu_outer_swap_trsm(T* __restrict__ Ab, const int64_t* __restrict__ off,
+                                                           const int* __restrict__ dim, const int* __restrict__ pivb,
+                                                           const int64_t* __restrict__ poff, int k) {
+  constexpr int KW = 2 * NB;
+  const int i = blockIdx.x;
+  const int n = dim[i];
+  if (k + KW >= n) return;                  // no trailing columns
+  T* A = Ab + off[i];
+  const int* piv = pivb + poff[i];
+  __shared__ T L11[KW * KW];
+  for (int t = threadIdx.x; t < KW * KW; t += 64) {
+    const int r = t % KW, c = t / KW;
+    L11[t] = A[(k + r) + (int64_t)(k + c) * n];
+  }
+  __syncthreads();
+  const int c = k + KW + blockIdx.y * 64 + threadIdx.x;
+  if (c >= n) return;
+  T* col = A + (int64_t)c * n;
+  for (int j = k; j < k + KW; ++j) {
+    const int p = piv[j];
+    if (p != j) {
+      const T t = col[j];
+      col[j] = col[p];
+      col[p] = t;
+    }
+  }
+  T x[KW];
+#pragma unroll
+  for (int r = 0; r < KW; ++r) x[r] = col[k + r];
+#pragma unroll
+  for (int j = 0; j < KW; ++j)
+#pragma unroll
+    for (int r = j + 1; r < KW; ++r) x[r] -= L11[r + j * KW] * x[j];
+#pragma unroll
+  for (int r = 0; r < KW; ++r) col[k + r] = x[r];
+}
+
+// A[r0:n, c0:c1) -= A[r0:n, k:k+kw) * A[k:k+kw, c0:c1), r0 = k + kw (64x64 MFMA tiles).
+// inner = 1: kw = NB, c0 = k+NB, c1 = k+2NB (sub-panel 2 before its factorization);
+// inner = 0: kw = 2NB, c0 = k+2NB, c1 = n (trailing matrix).
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void k_lu_update(T* __restrict__ Ab, const int64_t* __restrict__ off,
+                                                   const int* __restrict__ dim, int k, int inner, int tiles_m,
+                                                   int tiles_n) {
+  const int tiles = tiles_m * tiles_n;
+  const int i = blockIdx.x / tiles;
+  const int tl = blockIdx.x - i * tiles;
+  const int n = dim[i];
+  const int kw = inner ? NB : 2 * NB;
+  if (k + kw >= n) return;
+  const int r0 = k + kw;
+  const int c0 = inner ? k + NB : k + 2 * NB;
+  const int c1 = inner ? min(n, k + 2 * NB) : n;
+  const int M = n - r0, N = c1 - c0;
+  const int ty = tl % tiles_m, tx = tl / tiles_m;
+  if (ty * TILE >= M || tx * TILE >= N) return;
+  T* A = Ab + off[i];
+  __shared__ T sA[2 * NB * TILE];
+  __shared__ T sB[2 * NB * TILE];
+  gemm_sub_tile<T, 2 * NB>(A + r0 + (int64_t)c0 * n, n, A + r0 + (int64_t)k * n, n, A + k + (int64_t)c0 * n, n, M, N,
+                           kw, ty, tx, sA, sB);
+}
+
 // mode 0: LU trailing update; 1: forward-solve update of X; 2: backward-solve update of X.
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void k_gemm_update(T* __restrict__ Ab, const int64_t* __restrict__ off,
@@ -484,8 +618,7 @@ __global__ void k_build_perm(const int* __restrict__ dim, const int* __restrict_
 template <typename T>
 void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
   constexpr int NB = LU_NB;
-  const unsigned colblocks = blocks_for(b.max_n, 64);
-  for (int k = 0; k < b.max_n; k += NB) {
+  auto panel = [&](int k) {
     if (b.max_n - k > PANEL_REG_ROWS) {
       hipLaunchKernelGGL((k_lu_panel<T, NB>), dim3(b.count), dim3(256), 0, s, A, b.off, b.dim, b.piv, b.poff,
                          b.info, k);
@@ -494,14 +627,28 @@ void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
     hipLaunchKernelGGL((k_lu_panel_reg<T, NB, PANEL_REG_R>), dim3(b.count), dim3(512), 0, s, A, b.off, b.dim, b.piv,
                        b.poff, b.info, k);
     GDSW_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_lu_swap_trsm<T, NB>), dim3(b.count, colblocks), dim3(64), 0, s, A, b.off, b.dim,
-                       b.piv, b.poff, k);
+  };
+  for (int k = 0; k < b.max_n; k += 2 * NB) {
+    panel(k);
+    if (b.max_n > k + NB) {
+      hipLaunchKernelGGL((k_lu_inner_swap_trsm<T, NB>), dim3(b.count), dim3(64), 0, s, A, b.off, b.dim, b.piv, b.poff,
+                         k);
+      GDSW_LAUNCH_CHECK();
+      const int tm = (int)blocks_for(b.max_n - k - NB, TILE);
+      hipLaunchKernelGGL((k_lu_update<T, NB>), dim3(b.count * tm), dim3(256), 0, s, A, b.off, b.dim, k, 1, tm, 1);
+      GDSW_LAUNCH_CHECK();
+      panel(k + NB);
+    }
+    hipLaunchKernelGGL((k_lu_outer_swap_left<T, NB>), dim3(b.count, blocks_for(k + NB, 64)), dim3(64), 0, s, A, b.off,
+                       b.dim, b.piv, b.poff, k);
     GDSW_LAUNCH_CHECK();
-    const int rest = b.max_n - k - NB;
+    const int rest = b.max_n - k - 2 * NB;
     if (rest > 0) {
+      hipLaunchKernelGGL((k_lu_outer_swap_trsm<T, NB>), dim3(b.count, blocks_for(rest, 64)), dim3(64), 0, s, A, b.off,
+                         b.dim, b.piv, b.poff, k);
+      GDSW_LAUNCH_CHECK();
       const int t = (int)blocks_for(rest, TILE);
-      hipLaunchKernelGGL((k_gemm_update<T, NB>), dim3(b.count * t * t), dim3(256), 0, s, A, b.off, b.dim,
-                         (T*)nullptr, (const int64_t*)nullptr, (const int*)nullptr, k, 0, t);
+      hipLaunchKernelGGL((k_lu_update<T, NB>), dim3(b.count * t * t), dim3(256), 0, s, A, b.off, b.dim, k, 0, t, t);
       GDSW_LAUNCH_CHECK();
     }
   }

@@ -3,12 +3,47 @@
 #include "maps.h"
 
 #include <algorithm>
+#include <atomic>
+#include <cstdlib>
 #include <numeric>
 #include <string>
+#include <thread>
 
 namespace gdsw {
 
 namespace {
+
+int host_threads() {
+  if (const char* e = std::getenv("GDSW_HOST_THREADS")) {
+    const int t = std::atoi(e);
+    if (t >= 1) return t;
+  }
+  const unsigned hw = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(16u, hw));
+}
+
+// f(thread, begin, end) over [0, n) in dynamically scheduled chunks.
+template <typename F>
+void parallel_for(int n, int nthreads, F f) {
+  if (n <= 0) return;
+  if (nthreads <= 1 || n < 64) {
+    f(0, 0, n);
+    return;
+  }
+  std::atomic<int> next(0);
+  const int chunk = std::max(8, n / (nthreads * 8));
+  auto work = [&](int t) {
+    for (;;) {
+      const int b = next.fetch_add(chunk);
+      if (b >= n) break;
+      f(t, b, std::min(n, b + chunk));
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nthreads; ++t) pool.emplace_back(work, t);
+  work(0);
+  for (auto& th : pool) th.join();
+}
 
 // Sort and deduplicate each segment of a CSR list in place, then compact.
 void sort_unique_segments(std::vector<int64_t>& ptr, std::vector<int>& val) {
@@ -92,29 +127,62 @@ std::string build_level1_mesh(int64_t n, int n_nodes, const int* node_dof, int n
   for (int i = 0; i < n_parts; ++i)
     if (!cnt[i]) return "level-1 part " + std::to_string(i) + " has no element";
   // node graph: two nodes of one element whose lattice offsets differ by at most one per axis
-  int pa[27 * 26], pb[27 * 26];
-  int npairs = 0;
-  for (int a = 0; a < 27; ++a)
-    for (int b = 0; b < 27; ++b) {
-      if (a == b) continue;
-      const int dx = a % 3 - b % 3, dy = (a / 3) % 3 - (b / 3) % 3, dz = a / 9 - b / 9;
-      if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) {
-        pa[npairs] = a;
-        pb[npairs] = b;
-        ++npairs;
+  // (at most 26 neighbours per node), built node by node from the elements holding it
+  std::vector<int64_t> ne_ptr(n_nodes + 1, 0);
+  for (int v : out.en) ne_ptr[v + 1]++;
+  for (int v = 0; v < n_nodes; ++v) ne_ptr[v + 1] += ne_ptr[v];
+  std::vector<int> ne_el(ne_ptr[n_nodes]), ne_loc(ne_ptr[n_nodes]);
+  {
+    std::vector<int64_t> fill(ne_ptr.begin(), ne_ptr.end() - 1);
+    for (int e = 0; e < n_elem; ++e)
+      for (int a = 0; a < 27; ++a) {
+        const int v = out.en[(size_t)e * 27 + a];
+        ne_el[fill[v]] = e;
+        ne_loc[fill[v]++] = a;
       }
-    }
-  std::vector<int64_t> cntp(n_nodes + 1, 0);
-  for (int e = 0; e < n_elem; ++e)
-    for (int k = 0; k < npairs; ++k) cntp[out.en[(size_t)e * 27 + pa[k]] + 1]++;
-  for (int v = 0; v < n_nodes; ++v) cntp[v + 1] += cntp[v];
-  std::vector<int> nb(cntp[n_nodes]);
-  std::vector<int64_t> fill(cntp.begin(), cntp.end() - 1);
-  for (int e = 0; e < n_elem; ++e) {
-    const int* nodes = &out.en[(size_t)e * 27];
-    for (int k = 0; k < npairs; ++k) nb[fill[nodes[pa[k]]]++] = nodes[pb[k]];
   }
-  sort_unique_segments(cntp, nb);
+  constexpr int MAXNB = 26;
+  std::vector<int> nbuf((size_t)n_nodes * MAXNB);
+  std::vector<int> ncount(n_nodes, 0);
+  std::atomic<bool> overflow(false);
+  parallel_for(n_nodes, host_threads(), [&](int, int v0, int v1) {
+    int cand[8 * 26];
+    for (int v = v0; v < v1; ++v) {
+      int nc = 0;
+      if (ne_ptr[v + 1] - ne_ptr[v] > 8) {      // a hexahedral lattice node lies in at most 8 elements
+        overflow = true;
+        continue;
+      }
+      for (int64_t q = ne_ptr[v]; q < ne_ptr[v + 1]; ++q) {
+        const int e = ne_el[q], a = ne_loc[q];
+        const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
+        for (int b = 0; b < 27; ++b) {
+          if (b == a) continue;
+          const int dx = ax - b % 3, dy = ay - (b / 3) % 3, dz = az - b / 9;
+          if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) cand[nc++] = out.en[(size_t)e * 27 + b];
+        }
+      }
+      std::sort(cand, cand + nc);
+      int w = 0;
+      for (int k = 0; k < nc; ++k)
+        if (k == 0 || cand[k] != cand[k - 1]) {
+          if (w == MAXNB) {
+            overflow = true;
+            break;
+          }
+          nbuf[(size_t)v * MAXNB + w++] = cand[k];
+        }
+      ncount[v] = w;
+    }
+  });
+  if (overflow) return "elem_node: a node lies in more than 8 elements or has more than 26 lattice neighbours";
+  std::vector<int64_t> cntp(n_nodes + 1, 0);
+  for (int v = 0; v < n_nodes; ++v) cntp[v + 1] = cntp[v] + ncount[v];
+  std::vector<int> nb(cntp[n_nodes]);
+  parallel_for(n_nodes, host_threads(), [&](int, int v0, int v1) {
+    for (int v = v0; v < v1; ++v)
+      std::copy(nbuf.begin() + (size_t)v * MAXNB, nbuf.begin() + (size_t)v * MAXNB + ncount[v], nb.begin() + cntp[v]);
+  });
   out.adj_ptr = std::move(cntp);
   out.adj = std::move(nb);
   return "";
@@ -241,104 +309,114 @@ void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m) {
       m.owner[g] = mesh.elem_part[e];
       if (q == 0) m.dof_gcol[g] = m.part_col[mesh.elem_part[e]];
     }
-  // overlapping and interior sets
-  std::vector<int> stamp(nn, -1), depth(nn, 0);
-  std::vector<int> layer, frontier, next;
-  m.dom_ptr.assign(1, 0);
-  m.dom.clear();
-  m.int_ptr.assign(1, 0);
-  m.inter.clear();
-  m.pc_ptr.assign(1, 0);
-  m.pcols.clear();
-  m.z_ptr.assign(1, 0);
-  m.z_dof.clear();
-  m.z_lc.clear();
-  std::vector<int> dofs, idofs;
-  std::vector<std::pair<int, int>> zs;
-  for (int i = 0; i < N; ++i) {
-    layer.clear();
-    for (int e : part_elems[i])
-      for (int64_t k = mesh.en_ptr[e]; k < mesh.en_ptr[e + 1]; ++k) {
-        const int v = mesh.en[k];
-        if (stamp[v] != i) {
-          stamp[v] = i;
-          depth[v] = 0;
-          layer.push_back(v);
-        }
-      }
-    const size_t n_closure = layer.size();
-    frontier.assign(layer.begin(), layer.end());
-    for (int l = 0; l < delta; ++l) {
-      next.clear();
-      for (int u : frontier)
-        for (int64_t k = mesh.adj_ptr[u]; k < mesh.adj_ptr[u + 1]; ++k) {
-          const int w = mesh.adj[k];
-          if (stamp[w] != i) {
-            stamp[w] = i;
-            depth[w] = l + 1;
-            next.push_back(w);
+  // overlapping and interior sets, part by part (in parallel; concatenated in part order)
+  struct PartOut {
+    std::vector<int> dofs, idofs, pcols, z_lc, z_dof;
+  };
+  std::vector<PartOut> outp(N);
+  const int nthreads = host_threads();
+  std::vector<std::vector<int>> stamps(nthreads);
+  parallel_for(N, nthreads, [&](int t, int i0, int i1) {
+    std::vector<int>& stamp = stamps[t];
+    if (stamp.empty()) stamp.assign(nn, -1);
+    std::vector<int> layer, frontier, next;
+    std::vector<std::pair<int, int>> zs;
+    for (int i = i0; i < i1; ++i) {
+      PartOut& o = outp[i];
+      layer.clear();
+      for (int e : part_elems[i])
+        for (int64_t k = mesh.en_ptr[e]; k < mesh.en_ptr[e + 1]; ++k) {
+          const int v = mesh.en[k];
+          if (stamp[v] != i) {
+            stamp[v] = i;
+            layer.push_back(v);
           }
         }
-      layer.insert(layer.end(), next.begin(), next.end());
-      frontier.swap(next);
-    }
-    dofs.clear();
-    idofs.clear();
-    zs.clear();
-    for (size_t k = 0; k < layer.size(); ++k) {
-      const int v = layer[k];
-      for (int d = 0; d < 3; ++d) {
-        const int g = mesh.node_dof[3 * v + d];
-        if (g >= 0) dofs.push_back(g);
+      const size_t n_closure = layer.size();
+      frontier.assign(layer.begin(), layer.end());
+      for (int l = 0; l < delta; ++l) {
+        next.clear();
+        for (int u : frontier)
+          for (int64_t k = mesh.adj_ptr[u]; k < mesh.adj_ptr[u + 1]; ++k) {
+            const int w = mesh.adj[k];
+            if (stamp[w] != i) {
+              stamp[w] = i;
+              next.push_back(w);
+            }
+          }
+        layer.insert(layer.end(), next.begin(), next.end());
+        frontier.swap(next);
+      }
+      zs.clear();
+      for (size_t k = 0; k < layer.size(); ++k) {
+        const int v = layer[k];
+        for (int d = 0; d < 3; ++d) {
+          const int g = mesh.node_dof[3 * v + d];
+          if (g >= 0) o.dofs.push_back(g);
+        }
+      }
+      for (size_t k = 0; k < n_closure; ++k) {
+        const int v = layer[k];
+        const bool interior = nS(v) == 1 && m.s[m.s_ptr[v]] == i;
+        for (int d = 0; d < 3; ++d) {
+          const int g = mesh.node_dof[3 * v + d];
+          if (g < 0) continue;
+          if (interior) o.idofs.push_back(g);
+          else if (is_gamma[v]) zs.push_back({m.dof_gcol[g], g});
+        }
+      }
+      for (int e : part_elems[i])
+        for (int q = 0; q < 4; ++q) {
+          const int g = mesh.elem_pdof[4 * e + q];
+          if (g < 0) continue;
+          o.dofs.push_back(g);
+          if (q > 0) o.idofs.push_back(g);
+          else zs.push_back({m.dof_gcol[g], g});
+        }
+      std::sort(o.dofs.begin(), o.dofs.end());
+      std::sort(o.idofs.begin(), o.idofs.end());
+      for (size_t a = 0; a < o.idofs.size(); ++a) {   // interior dofs belong to one part only
+        m.dof_ipart[o.idofs[a]] = i;
+        m.dof_irow[o.idofs[a]] = (int)a;
+      }
+      // coarse columns of the part: every column of an interface dof in its closure
+      for (auto& z : zs) o.pcols.push_back(z.first);
+      std::sort(o.pcols.begin(), o.pcols.end());
+      o.pcols.erase(std::unique(o.pcols.begin(), o.pcols.end()), o.pcols.end());
+      // interface dofs of the closure, keyed by their local column
+      for (auto& z : zs) z.first = (int)(std::lower_bound(o.pcols.begin(), o.pcols.end(), z.first) - o.pcols.begin());
+      std::sort(zs.begin(), zs.end());
+      for (auto& z : zs) {
+        o.z_lc.push_back(z.first);
+        o.z_dof.push_back(z.second);
       }
     }
-    for (size_t k = 0; k < n_closure; ++k) {
-      const int v = layer[k];
-      const bool interior = nS(v) == 1 && m.s[m.s_ptr[v]] == i;
-      for (int d = 0; d < 3; ++d) {
-        const int g = mesh.node_dof[3 * v + d];
-        if (g < 0) continue;
-        if (interior) idofs.push_back(g);
-        else if (is_gamma[v]) zs.push_back({m.dof_gcol[g], g});
-      }
-    }
-    for (int e : part_elems[i])
-      for (int q = 0; q < 4; ++q) {
-        const int g = mesh.elem_pdof[4 * e + q];
-        if (g < 0) continue;
-        dofs.push_back(g);
-        if (q > 0) idofs.push_back(g);
-        else zs.push_back({m.dof_gcol[g], g});
-      }
-    std::sort(dofs.begin(), dofs.end());
-    std::sort(idofs.begin(), idofs.end());
-    m.dom.insert(m.dom.end(), dofs.begin(), dofs.end());
-    m.dom_ptr.push_back((int64_t)m.dom.size());
-    for (size_t a = 0; a < idofs.size(); ++a) {
-      m.dof_ipart[idofs[a]] = i;
-      m.dof_irow[idofs[a]] = (int)a;
-    }
-    m.inter.insert(m.inter.end(), idofs.begin(), idofs.end());
-    m.int_ptr.push_back((int64_t)m.inter.size());
-    // coarse columns of the part: every column of an interface dof in its closure
-    const size_t pc0 = m.pcols.size();
-    for (auto& z : zs) m.pcols.push_back(z.first);
-    std::sort(m.pcols.begin() + pc0, m.pcols.end());
-    m.pcols.erase(std::unique(m.pcols.begin() + pc0, m.pcols.end()), m.pcols.end());
-    m.pc_ptr.push_back((int64_t)m.pcols.size());
-    // interface dofs of the closure, keyed by their local column
-    for (auto& z : zs) {
-      const int lc = (int)(std::lower_bound(m.pcols.begin() + pc0, m.pcols.end(), z.first) -
-                           (m.pcols.begin() + pc0));
-      z.first = lc;
-    }
-    std::sort(zs.begin(), zs.end());
-    for (auto& z : zs) {
-      m.z_lc.push_back(z.first);
-      m.z_dof.push_back(z.second);
-    }
-    m.z_ptr.push_back((int64_t)m.z_dof.size());
+  });
+  m.dom_ptr.assign(N + 1, 0);
+  m.int_ptr.assign(N + 1, 0);
+  m.pc_ptr.assign(N + 1, 0);
+  m.z_ptr.assign(N + 1, 0);
+  for (int i = 0; i < N; ++i) {
+    m.dom_ptr[i + 1] = m.dom_ptr[i] + (int64_t)outp[i].dofs.size();
+    m.int_ptr[i + 1] = m.int_ptr[i] + (int64_t)outp[i].idofs.size();
+    m.pc_ptr[i + 1] = m.pc_ptr[i] + (int64_t)outp[i].pcols.size();
+    m.z_ptr[i + 1] = m.z_ptr[i] + (int64_t)outp[i].z_dof.size();
   }
+  m.dom.resize(m.dom_ptr[N]);
+  m.inter.resize(m.int_ptr[N]);
+  m.pcols.resize(m.pc_ptr[N]);
+  m.z_dof.resize(m.z_ptr[N]);
+  m.z_lc.resize(m.z_ptr[N]);
+  parallel_for(N, nthreads, [&](int, int i0, int i1) {
+    for (int i = i0; i < i1; ++i) {
+      const PartOut& o = outp[i];
+      std::copy(o.dofs.begin(), o.dofs.end(), m.dom.begin() + m.dom_ptr[i]);
+      std::copy(o.idofs.begin(), o.idofs.end(), m.inter.begin() + m.int_ptr[i]);
+      std::copy(o.pcols.begin(), o.pcols.end(), m.pcols.begin() + m.pc_ptr[i]);
+      std::copy(o.z_dof.begin(), o.z_dof.end(), m.z_dof.begin() + m.z_ptr[i]);
+      std::copy(o.z_lc.begin(), o.z_lc.end(), m.z_lc.begin() + m.z_ptr[i]);
+    }
+  });
   // per coarse column: the parts that hold it
   std::vector<int64_t> cnt(m.n_coarse + 1, 0);
   for (int i = 0; i < N; ++i)
