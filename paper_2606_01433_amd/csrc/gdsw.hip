@@ -487,15 +487,20 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
   const int Lp = p->levels;
   C->levels.reserve(Lp);
   std::vector<hipEvent_t> evs;
-  auto mark = [&]() {
+  auto mark = [&](hipStream_t st_) {
     hipEvent_t e;
     GDSW_HIP(hipEventCreate(&e));
-    GDSW_HIP(hipEventRecord(e, s));
+    GDSW_HIP(hipEventRecord(e, st_));
     evs.push_back(e);
     return (int)evs.size() - 1;
   };
+  // The local factorizations run on the side stream, concurrently with the
+  // basis / Galerkin / coarser-level chain on the caller's stream; level l's
+  // factorization only waits for its operator K_l.
+  hipStream_t fs = C->side;
   std::vector<std::pair<int, int>> ev_factor, ev_basis;
   bool coarsest = false;
+  int k_ready = mark(s);                      // K_1 copied
   for (int l = 0; l < Lp - 1; ++l) {
     C->levels.emplace_back();
     Level& L = C->levels.back();
@@ -504,10 +509,10 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
     L.n = K.n;
     L.K = K;
     host([&] { build_maps(meshes[l], C->opt.overlap, L.maps); });
-    const int e0 = mark();
-    factor_level<T>(C, L, s);
-    const int e1 = mark();
-    ev_factor.push_back({e0, e1});
+    GDSW_HIP(hipStreamWaitEvent(fs, evs[k_ready], 0));
+    const int e0 = mark(fs);
+    factor_level<T>(C, L, fs);
+    ev_factor.push_back({e0, mark(fs)});
     st.n[l] = L.n;
     st.parts[l] = L.nparts;
     st.sum_ni[l] = L.sum_n;
@@ -527,8 +532,10 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
     }
     std::vector<int64_t> rp;
     std::vector<int> cl;
+    const int b0 = mark(s);
     K = coarse_level<T>(C, L, s, rp, cl);
-    ev_basis.push_back({e1, mark()});
+    k_ready = mark(s);
+    ev_basis.push_back({b0, k_ready});
     st.interior_flops[l] = L.interior_flops;
     if (last || nxt == 1) {          // a single coarse part: that coarse problem is the coarsest
       coarsest = true;
@@ -554,13 +561,14 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
   if (coarsest) {
     C->has_coarsest = true;
     C->nnz_coarsest = K.nnz;
-    ec0 = mark();
+    ec0 = mark(s);
     coarsest_inverse(C, K, s, &dense, &cinfo);
-    ec1 = mark();
+    ec1 = mark(s);
     st.n[schwarz] = K.n;
     st.nnz[schwarz] = K.nnz;
     st.factor_flops[schwarz] = (2.0 / 3.0) * K.n * (double)K.n * K.n + 2.0 * K.n * (double)K.n * K.n;
   }
+  GDSW_HIP(hipStreamSynchronize(fs));
   GDSW_HIP(hipStreamSynchronize(s));
   for (const Level& L : C->levels) {
     check_info(L.info, L.nparts, "local block", L.index, s);

@@ -42,7 +42,7 @@ template <> struct Mfma<float> {
 };
 
 constexpr int TILE = 64;
-constexpr int PANEL_REG_R = 3;                       // rows per thread of the register panel
+constexpr int PANEL_REG_R = 3;                       // rows per thread of the tallest register panel
 constexpr int PANEL_REG_ROWS = 512 * PANEL_REG_R;
 
 // C[M x N] -= A[M x K] * B[K x N] on the 64x64 tile (ty, tx); K <= KMAX.
@@ -99,6 +99,70 @@ __device__ __forceinline__ void gemm_sub_tile(T* __restrict__ C, int64_t ldc, co
         const int gr = r0 + wy * 32 + rb * 16 + li;
         const int gc = c0 + wx * 32 + cb * 16 + Mfma<T>::row(lk, q);
         if (gr < M && gc < N) C[gr + (int64_t)gc * ldc] -= acc[cb][rb][q];
+      }
+}
+
+// C[M x N] -= A[M x K] * B[K x N] on the 64x64 tile (ty, tx), K <= KMAX, without
+// LDS: each wave (32x32 quarter, 2x2 MFMA blocks) loads its operand
+// fragments for all K straight into registers and prefetches its C values,
+// so every load is in flight before the MFMA chain starts.  Same transposed
+// product and C layout as gemm_sub_tile.
+template <typename T, int KMAX>
+__device__ __forceinline__ void gemm_sub_tile_direct(T* __restrict__ C, int64_t ldc, const T* __restrict__ A,
+                                                     int64_t lda, const T* __restrict__ B, int64_t ldb, int M, int N,
+                                                     int K, int ty, int tx) {
+  constexpr int S = KMAX / 4;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wy = w >> 1, wx = w & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  const int rbase = ty * TILE + wy * 32, cbase = tx * TILE + wx * 32;
+  typedef typename Mfma<T>::v4 v4;
+  T av[S][2], bv[S][2];
+#pragma unroll
+  for (int st = 0; st < S; ++st) {
+    const int k = 4 * st + lk;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      const int r = rbase + rb * 16 + li;
+      av[st][rb] = (r < M && k < K) ? A[r + (int64_t)k * lda] : T(0);
+    }
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      const int c = cbase + cb * 16 + li;
+      bv[st][cb] = (c < N && k < K) ? B[k + (int64_t)c * ldb] : T(0);
+    }
+  }
+  T cv[2][2][4];
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gr = rbase + rb * 16 + li;
+        const int gc = cbase + cb * 16 + Mfma<T>::row(lk, q);
+        cv[cb][rb][q] = (gr < M && gc < N) ? C[gr + (int64_t)gc * ldc] : T(0);
+      }
+  v4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4{0, 0, 0, 0};
+#pragma unroll
+  for (int st = 0; st < S; ++st)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) acc[cb][rb] = Mfma<T>::mac(bv[st][cb], av[st][rb], acc[cb][rb]);
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gr = rbase + rb * 16 + li;
+        const int gc = cbase + cb * 16 + Mfma<T>::row(lk, q);
+        if (gr < M && gc < N) C[gr + (int64_t)gc * ldc] = cv[cb][rb][q] - acc[cb][rb][q];
       }
 }
 
@@ -473,10 +537,8 @@ __global__ __launch_bounds__(256) void k_lu_update(T* __restrict__ Ab, const int
   const int ty = tl % tiles_m, tx = tl / tiles_m;
   if (ty * TILE >= M || tx * TILE >= N) return;
   T* A = Ab + off[i];
-  __shared__ T sA[2 * NB * TILE];
-  __shared__ T sB[2 * NB * TILE];
-  gemm_sub_tile<T, 2 * NB>(A + r0 + (int64_t)c0 * n, n, A + r0 + (int64_t)k * n, n, A + k + (int64_t)c0 * n, n, M, N,
-                           kw, ty, tx, sA, sB);
+  gemm_sub_tile_direct<T, 2 * NB>(A + r0 + (int64_t)c0 * n, n, A + r0 + (int64_t)k * n, n, A + k + (int64_t)c0 * n, n,
+                                  M, N, kw, ty, tx);
 }
 
 // mode 0: LU trailing update; 1: forward-solve update of X; 2: backward-solve update of X.
@@ -522,9 +584,7 @@ __global__ __launch_bounds__(256) void k_gemm_update(T* __restrict__ Ab, const i
     }
   }
   if (ty * TILE >= M || tx * TILE >= N) return;
-  __shared__ T sA[NB * TILE];
-  __shared__ T sB[NB * TILE];
-  gemm_sub_tile<T, NB>(C, ldc, Ap, n, Bp, ldb, M, N, jb, ty, tx, sA, sB);
+  gemm_sub_tile_direct<T, NB>(C, ldc, Ap, n, Bp, ldb, M, N, jb, ty, tx);
 }
 
 // Row interchanges of the whole factorization applied to each right-hand side.
