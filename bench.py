@@ -19,6 +19,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM traffic of one level-1 local-solve launch on this workload, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs scaled by a 1 GiB copy (profiles/local_solve_die32x16x16.md), valid only for the
+# local-solve kernel source it was measured on.
+LOCAL_SOLVE_TRAFFIC = {"bytes": 4.348e9, "source_hash": "ed41949a06f3323d", "precision": "fp64"}
+
+
+def local_solve_source_hash():
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2606_01433_amd", "csrc", "apply.hip")).read()
+    a, b = src.index("// Local solves w_i"), src.index("__global__ void k_scatter_sum")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 FP64_MFMA_TFLOPS = 78.6
 FP32_MFMA_TFLOPS = 157.3
 
@@ -108,6 +120,10 @@ def main():
     achieved = bytes_per_launch / (ms_ls / launches * 1e-3) / 1e9 if launches else 0.0
     st0 = stats[0]
     iters = infos[-1]["iterations"]
+    traffic = None
+    if (local_solve_source_hash() == LOCAL_SOLVE_TRAFFIC["source_hash"]
+            and args.precision == LOCAL_SOLVE_TRAFFIC["precision"] and args.seed == 0):
+        traffic = LOCAL_SOLVE_TRAFFIC["bytes"]
     out = {
         "metric": "Stokes solves/s to 1e-8 rel. residual",
         "value": 1.0 / T,
@@ -131,7 +147,7 @@ def main():
                                        "basis_galerkin": st0["ms_basis"], "coarsest": st0["ms_coarse"]}},
         "roofline": {"kernel": "k_local_solve (level-1 batched pivoted LU forward/backward substitution)",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": bytes_per_launch, "launches": launches,
                      "avg_launch_us": ms_ls / launches * 1e3 if launches else None},
         "factor": {"flops_level1": st0["factor_flops"][0], "ms_factor_all_levels": st0["ms_factor"],

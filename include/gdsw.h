@@ -100,7 +100,8 @@ typedef struct gdsw_problem {
  * no_coarse : 1 = omit the coarsest correction (one-level Schwarz for L = 2).
  * panel     : LU panel width, 0 = built-in default.
  * profile   : 1 = time every launch of the level-1 local-solve kernel with
- *             HIP events on the caller's stream (reported by gdsw_get_stats).
+ *             HIP events recorded by the dispatch itself on the caller's stream
+ *             (reported by gdsw_get_stats).
  */
 typedef struct gdsw_options {
   int32_t overlap;

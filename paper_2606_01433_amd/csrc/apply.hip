@@ -1,6 +1,8 @@
 // Preconditioner apply, eq. (2.2): local solves R_i^T A_i^{-1} R_i, the
 // ordered combination of overlapping values, the coarse restriction Phi^T r,
 // the prolongation Phi y and the coarsest direct solve.
+#include <hip/hip_ext.h>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -186,14 +188,21 @@ __global__ void k_gemv_reduce(int n, int chunks, const double* __restrict__ part
 template <typename T>
 void local_solves(int nparts, int max_n, const int* order, const int64_t* dom_ptr, const int* gidx,
                   const int64_t* blk_off, const T* blocks, const double* r, double* w, bool first_level,
-                  hipStream_t s) {
+                  hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (nparts == 0) return;
   const size_t lds = (size_t)max_n * sizeof(T);
   if (lds > 64 * 1024) throw Error(-1, "local block too large for the LDS-resident right-hand side");
   const bool big = nparts >= BIG_BATCH;
-#define GDSW_LS(F, NW)                                                                                        \
-  hipLaunchKernelGGL((k_local_solve_wg<T, F, NW>), dim3(nparts), dim3(64 * NW), lds, s, order, dom_ptr, gidx, \
-                     blk_off, blocks, r, w)
+  // with events, the dispatch itself records its start and end (exact kernel duration)
+#define GDSW_LS(F, NW)                                                                                          \
+  do {                                                                                                          \
+    if (ev_start)                                                                                               \
+      hipExtLaunchKernelGGL((k_local_solve_wg<T, F, NW>), dim3(nparts), dim3(64 * NW), lds, s, ev_start, ev_stop, \
+                            0, order, dom_ptr, gidx, blk_off, blocks, r, w);                                    \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_local_solve_wg<T, F, NW>), dim3(nparts), dim3(64 * NW), lds, s, order, dom_ptr,     \
+                         gidx, blk_off, blocks, r, w);                                                          \
+  } while (0)
   if (big) {
     if (first_level) GDSW_LS(true, 2);
     else GDSW_LS(false, 2);
@@ -239,9 +248,9 @@ void dense_gemv(int n, const double* Ainv, const double* x, double* y, double* p
 }
 
 template void local_solves<double>(int, int, const int*, const int64_t*, const int*, const int64_t*,
-                                   const double*, const double*, double*, bool, hipStream_t);
+                                   const double*, const double*, double*, bool, hipStream_t, hipEvent_t, hipEvent_t);
 template void local_solves<float>(int, int, const int*, const int64_t*, const int*, const int64_t*, const float*,
-                                  const double*, double*, bool, hipStream_t);
+                                  const double*, double*, bool, hipStream_t, hipEvent_t, hipEvent_t);
 template void restrict_phi<double>(int, const int64_t*, const int*, const int64_t*, const int*, const int*,
                                    const int64_t*, const int*, const int64_t*, const double*, const double*, double*,
                                    hipStream_t);

@@ -650,13 +650,14 @@ void apply_level(gdsw_ctx* C, int l, const double* r, double* z, hipStream_t s) 
     GDSW_HIP(hipEventRecord(C->ev_join, C->side));
   }
   const bool prof = C->opt.profile && l == 0;
+  hipEvent_t e_start = nullptr, e_stop = nullptr;
   if (prof) {
     if (C->ev_used + 2 > 4096) drain_events(C);
-    GDSW_HIP(hipEventRecord(next_event(C), s));
+    e_start = next_event(C);
+    e_stop = next_event(C);
   }
   local_solves<T>(L.nparts, L.max_n, L.order, L.dom_ptr, L.gidx, L.blk_off, static_cast<const T*>(L.blocks), r, L.w,
-                  l == 0, s);
-  if (prof) GDSW_HIP(hipEventRecord(next_event(C), s));
+                  l == 0, s, e_start, e_stop);
   scatter_sum(L.n, L.sc_ptr, L.sc_pos, L.w, z, s);
   if (!L.has_coarse) return;
   if (fork) GDSW_HIP(hipStreamWaitEvent(s, C->ev_join, 0));
