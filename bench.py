@@ -59,6 +59,57 @@ def cpu_baseline(P, gpu_iterations, budget_its=4):
                        f"iterations ({per_it:.2f} s each), extrapolated to the GPU's {gpu_iterations} iterations")}
 
 
+def serving_bench(seed=0, n_requests=24):
+    """Poisson stream of Picard-step solves over a pool of seeded dies: FP32-factor serving with
+    concurrent slots vs. plain FP64 one at a time on the same arrival times."""
+    import numpy as np
+    from harness import die_problem
+    from paper_2606_01433_amd.serving import Server, Request, summarize
+    rng = np.random.Generator(np.random.PCG64(seed + 7))
+    pool = []
+    for nx, ny, nz in [(16, 8, 8), (24, 12, 12), (32, 16, 16)]:
+        for q in range(2):
+            n_exp = float(rng.uniform(0.3, 0.9))
+            lam = float(10.0 ** rng.uniform(-1.0, 1.0))
+            pool.append(die_problem(nx, ny, nz, seed=seed + q, nu0=1.0, lam=lam, n_exp=n_exp, levels=3))
+    picks = rng.integers(0, len(pool), n_requests)
+    # service time of the plain FP64 path, one request at a time (also warms every size up)
+    srv = Server(max_active=1)
+    t0 = time.perf_counter()
+    for k, P in enumerate(pool):
+        srv.submit(Request(-1 - k, P, tol=1e-8)).wait()
+    t_mean = (time.perf_counter() - t0) / len(pool)
+    srv.close()
+    rate = 1.5 / t_mean
+    gaps = rng.exponential(1.0 / rate, n_requests)
+
+    def stream(server, **opts):
+        reqs = []
+        t_start = time.perf_counter()
+        t_next = t_start
+        for k in range(n_requests):
+            delay = t_next - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            reqs.append(server.submit(Request(k, pool[int(picks[k])], arrival=time.perf_counter(), **opts)))
+            t_next += gaps[k]
+        server.drain(reqs)
+        t_end = time.perf_counter()
+        server.close()
+        return reqs, summarize(reqs, t_start, t_end)
+
+    base_reqs, base = stream(Server(max_active=1), tol=1e-8)
+    srv = Server(budget_bytes=200 * 2 ** 30, max_active=4)
+    mix_reqs, mixed = stream(srv, tol=1e-8, precision="mixed")
+    mixed["peak_active"] = srv.peak_active
+    err = max(float(np.linalg.norm(m.x - b_.x) / np.linalg.norm(b_.x)) for m, b_ in zip(mix_reqs, base_reqs))
+    return {"requests": n_requests, "arrival_rate_hz": rate,
+            "pool": "seeded dies 16x8x8, 24x12x12, 32x16x16; Carreau n ~ U[0.3,0.9], lambda = 10^U[-1,1]; "
+                    "three levels; FGMRES(30) to 1e-8",
+            "serving_fp32_factors_4_slots": mixed, "fp64_one_at_a_time": base,
+            "max_rel_diff_fp32_vs_fp64_solution": err}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +118,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -154,6 +206,8 @@ def main():
                    "tflops_level1_lower_bound": st0["factor_flops"][0] / (st0["ms_factor"] * 1e-3) / 1e12,
                    "peak_tflops": FP64_MFMA_TFLOPS if args.precision == "fp64" else FP32_MFMA_TFLOPS},
     }
+    if not args.no_serving:
+        out["serving"] = serving_bench(args.seed)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, iters)
     print(json.dumps(out), flush=True)
