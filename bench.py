@@ -110,6 +110,24 @@ def serving_bench(seed=0, n_requests=24):
             "max_rel_diff_fp32_vs_fp64_solution": err}
 
 
+def solve_only_bench(P, Kdev, b, precision, n_solves=5):
+    """Setup amortized: several solves on one context, eager applies vs captured hipGraph applies."""
+    import torch
+    from paper_2606_01433_amd import gdsw
+    out = {}
+    for graph in (False, True):
+        with gdsw.Context(P, K=Kdev, tol=1e-8, precision=precision, graph=graph) as ctx:
+            ctx.solve(b)                     # warm-up (captures the graphs in graph mode)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(n_solves):
+                x, info = ctx.solve(b)
+            torch.cuda.synchronize()
+            out["graph" if graph else "eager"] = {"ms_per_solve": (time.perf_counter() - t0) / n_solves * 1e3,
+                                                  "solves_per_s": n_solves / (time.perf_counter() - t0)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,6 +224,7 @@ def main():
                    "tflops_level1_lower_bound": st0["factor_flops"][0] / (st0["ms_factor"] * 1e-3) / 1e12,
                    "peak_tflops": FP64_MFMA_TFLOPS if args.precision == "fp64" else FP32_MFMA_TFLOPS},
     }
+    out["solve_only"] = solve_only_bench(P, Kdev, b, args.precision)
     if not args.no_serving:
         out["serving"] = serving_bench(args.seed)
     if not args.no_cpu_baseline:

@@ -101,7 +101,11 @@ typedef struct gdsw_problem {
  * panel     : LU panel width, 0 = built-in default.
  * profile   : 1 = time every launch of the level-1 local-solve kernel with
  *             HIP events recorded by the dispatch itself on the caller's stream
- *             (reported by gdsw_get_stats).
+ *             (reported by gdsw_get_stats); eager applies only.
+ * graph     : 1 = inside gdsw_solve, each apply runs as a captured hipGraph
+ *             (one per Krylov column, captured on first use and replayed by
+ *             later solves on the same context); the solve then runs on a
+ *             stream of the context, ordered after and before `stream`.
  */
 typedef struct gdsw_options {
   int32_t overlap;
@@ -113,6 +117,7 @@ typedef struct gdsw_options {
   int32_t no_coarse;
   int32_t panel;
   int32_t profile;
+  int32_t graph;
 } gdsw_options;
 
 typedef struct gdsw_solve_info {

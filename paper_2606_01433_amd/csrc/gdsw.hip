@@ -140,7 +140,18 @@ struct gdsw_ctx {
   // the coarse chain of the apply runs on `side`, forked from and joined to the caller's stream
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // graph mode: the solve runs on `own`; apply graphs per Krylov column
+  hipStream_t own = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::vector<hipGraphExec_t> apply_exec;
+  bool capturing = false;
   ~gdsw_ctx() {
+    if (own) (void)hipStreamSynchronize(own);
+    for (hipGraphExec_t g : apply_exec)
+      if (g) (void)hipGraphExecDestroy(g);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (own) (void)hipStreamDestroy(own);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
@@ -649,7 +660,7 @@ void apply_level(gdsw_ctx* C, int l, const double* r, double* z, hipStream_t s) 
     coarse_chain<T>(C, l, r, C->side);
     GDSW_HIP(hipEventRecord(C->ev_join, C->side));
   }
-  const bool prof = C->opt.profile && l == 0;
+  const bool prof = C->opt.profile && l == 0 && !C->capturing;
   hipEvent_t e_start = nullptr, e_stop = nullptr;
   if (prof) {
     if (C->ev_used + 2 > 4096) drain_events(C);
@@ -686,9 +697,59 @@ void ensure_workspace(gdsw_ctx* C) {
   C->ws_m = m;
 }
 
-int solve_impl(gdsw_ctx* C, const double* b, double* x, hipStream_t s, gdsw_solve_info* info) {
+// Apply of Krylov column j: eager, or replay of the graph captured for that column.
+void column_apply(gdsw_ctx* C, int j, const double* v, double* z, hipStream_t s) {
+  if (!C->opt.graph) {
+    apply_any(C, v, z, s);
+    return;
+  }
+  if ((int)C->apply_exec.size() <= j) C->apply_exec.resize(j + 1, nullptr);
+  if (!C->apply_exec[j]) {
+    hipGraph_t g = nullptr;
+    C->capturing = true;
+    GDSW_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+      apply_any(C, v, z, s);
+    } catch (...) {
+      (void)hipStreamEndCapture(s, &g);
+      if (g) (void)hipGraphDestroy(g);
+      C->capturing = false;
+      throw;
+    }
+    GDSW_HIP(hipStreamEndCapture(s, &g));
+    C->capturing = false;
+    hipGraphExec_t exec = nullptr;
+    GDSW_HIP(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(g);
+    C->apply_exec[j] = exec;
+  }
+  GDSW_HIP(hipGraphLaunch(C->apply_exec[j], s));
+}
+
+int solve_impl(gdsw_ctx* C, const double* b, double* x, hipStream_t caller, gdsw_solve_info* info) {
   const double t0 = now_ms();
   ensure_workspace(C);
+  hipStream_t s = caller;
+  if (C->opt.graph) {            // captured work needs a stream of its own (not the legacy default stream)
+    if (!C->own) {
+      GDSW_HIP(hipStreamCreateWithFlags(&C->own, hipStreamNonBlocking));
+      GDSW_HIP(hipEventCreateWithFlags(&C->ev_in, hipEventDisableTiming));
+      GDSW_HIP(hipEventCreateWithFlags(&C->ev_out, hipEventDisableTiming));
+    }
+    GDSW_HIP(hipEventRecord(C->ev_in, caller));
+    GDSW_HIP(hipStreamWaitEvent(C->own, C->ev_in, 0));
+    s = C->own;
+  }
+  struct Rejoin {
+    gdsw_ctx* C;
+    hipStream_t caller;
+    ~Rejoin() {
+      if (C->opt.graph && C->own) {
+        (void)hipEventRecord(C->ev_out, C->own);
+        (void)hipStreamWaitEvent(caller, C->ev_out, 0);
+      }
+    }
+  } rejoin{C, caller};
   const int m = C->opt.restart;
   const int64_t n = C->levels[0].n;
   const CsrDev& K = C->levels[0].K;
@@ -752,7 +813,7 @@ int solve_impl(gdsw_ctx* C, const double* b, double* x, hipStream_t s, gdsw_solv
       }
       double* vj = V + (int64_t)j * n;
       double* zj = Z + (int64_t)j * n;
-      apply_any(C, vj, zj, s);
+      column_apply(C, j, vj, zj, s);
       tick(ms_apply, last);
       spmv(K, zj, w, s);
       tick(ms_spmv, last);
@@ -829,6 +890,7 @@ void gdsw_default_options(gdsw_options* o) {
   o->no_coarse = 0;
   o->panel = 0;
   o->profile = 0;
+  o->graph = 0;
 }
 
 const char* gdsw_last_error(void) { return gdsw::g_last_error.c_str(); }

@@ -26,7 +26,8 @@ class Problem(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("overlap", c_i32), ("combine", c_i32), ("precision", c_i32), ("restart", c_i32),
-                ("max_it", c_i32), ("tol", c_dbl), ("no_coarse", c_i32), ("panel", c_i32), ("profile", c_i32)]
+                ("max_it", c_i32), ("tol", c_dbl), ("no_coarse", c_i32), ("panel", c_i32), ("profile", c_i32),
+                ("graph", c_i32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -101,7 +102,7 @@ def _check(code):
 
 
 def make_options(overlap=1, combine="restricted", precision="fp64", restart=30, max_it=1000, tol=1e-8,
-                 no_coarse=False, panel=0, profile=False):
+                 no_coarse=False, panel=0, profile=False, graph=False):
     o = Options()
     load_library().gdsw_default_options(ctypes.byref(o))
     o.overlap = overlap
@@ -113,6 +114,7 @@ def make_options(overlap=1, combine="restricted", precision="fp64", restart=30, 
     o.no_coarse = int(bool(no_coarse))
     o.panel = panel
     o.profile = int(bool(profile))
+    o.graph = int(bool(graph))
     return o
 
 

@@ -197,3 +197,24 @@ def test_repeat_runs_bitwise(gd):
     with gd.Context(P) as ctx2:
         z3 = ctx2.apply(r).cpu().numpy()
     assert np.array_equal(z1, z2) and np.array_equal(z1, z3)
+
+
+def test_graph_solves_match_eager(gd):
+    """Applies replayed from captured hipGraphs give bit-identical solves, across several solves on
+    one context with eager work and synchronizations in between."""
+    P = _problem("die16_L3")
+    rng = np.random.Generator(np.random.PCG64(21))
+    bs = [P.b] + [rng.standard_normal(P.n) for _ in range(2)]
+    _say("graph vs eager solves")
+    with gd.Context(P) as eager:
+        ref = [eager.solve(_dev(b))[0].cpu().numpy() for b in bs]
+    with gd.Context(P, graph=True) as g:
+        for rep in range(2):
+            for b, xr in zip(bs, ref):
+                x, info = g.solve(_dev(b))
+                torch.cuda.synchronize()
+                z = g.apply(_dev(b))            # eager work between replays
+                torch.cuda.synchronize()
+                assert info["converged"]
+                assert np.array_equal(x.cpu().numpy(), xr), rep
+                assert np.isfinite(z.cpu().numpy()).all()
