@@ -211,6 +211,7 @@ def main():
                                "(~20% masked), Q2-P1disc, Carreau nu0=1 lambda=1 n=0.5, 2^3-voxel parts, overlap 1",
                    "n_dofs": int(P.n), "nnz": int(len(P.col)), "parts": st0["parts"][:st0["levels"]],
                    "level_dofs": st0["n"][:st0["levels"]], "iterations": iters,
+                   "local_solve_waves_per_matrix": st0["ls_waves"][:st0["levels"] - 1],
                    "true_rel_residual": res, "precision": args.precision,
                    "ms_setup": st0["ms_total"], "ms_solve": infos[-1]["ms_total"],
                    "ms_setup_phases": {"host_maps": st0["ms_maps"], "factor": st0["ms_factor"],

@@ -106,6 +106,9 @@ typedef struct gdsw_problem {
  *             (one per Krylov column, captured on first use and replayed by
  *             later solves on the same context); the solve then runs on a
  *             stream of the context, ordered after and before `stream`.
+ * tune      : 1 = at the end of setup, time the local solves of every level
+ *             with 2, 4 and 8 wavefronts per matrix and keep the fastest
+ *             (reported in gdsw_stats.ls_waves); 0 = 4 wavefronts.
  */
 typedef struct gdsw_options {
   int32_t overlap;
@@ -118,6 +121,7 @@ typedef struct gdsw_options {
   int32_t panel;
   int32_t profile;
   int32_t graph;
+  int32_t tune;
 } gdsw_options;
 
 typedef struct gdsw_solve_info {
@@ -144,6 +148,7 @@ typedef struct gdsw_stats {
   int64_t local_solve_launches;
   double ms_local_solve;          /* summed kernel time                         */
   double local_solve_bytes;       /* algorithmic bytes of one launch: sum_i n_i^2 s + 20 n_i */
+  int32_t ls_waves[8];            /* wavefronts per matrix used by the local solves of level l */
 } gdsw_stats;
 
 /* Index maps of one level, host copies owned by the context (valid until

@@ -11,7 +11,6 @@ namespace gdsw {
 namespace {
 
 constexpr int PW = 64;   // triangle / panel width of the blocked substitution
-constexpr int BIG_BATCH = 512;   // batches this large use two wavefronts per matrix
 
 // ---------------------------------------------------------------------------
 // Local solves w_i = A_i^{-1} R_i r with the pivoted LU stored in place.
@@ -22,9 +21,9 @@ constexpr int BIG_BATCH = 512;   // batches this large use two wavefronts per ma
 // thread streams its row's 64 panel entries with all loads in flight).  The
 // gathered right-hand side lives in LDS.
 //
-// NW wavefronts per matrix share the GEMV rows: two for batches that fill the
-// chip (all matrices resident at once), four for small batches.  Matrices are
-// visited largest first (`order`), so the big ones do not form the tail.
+// NW wavefronts per matrix share the GEMV rows (4 by default; the autotuner
+// may pick 2 or 8).  Matrices are visited largest first (`order`), so the big
+// ones do not form the tail.
 // FIRST only separates the level-1 launch from deeper levels in profiles.
 // ---------------------------------------------------------------------------
 template <typename T, bool FIRST, int NW>
@@ -188,11 +187,11 @@ __global__ void k_gemv_reduce(int n, int chunks, const double* __restrict__ part
 template <typename T>
 void local_solves(int nparts, int max_n, const int* order, const int64_t* dom_ptr, const int* gidx,
                   const int64_t* blk_off, const T* blocks, const double* r, double* w, bool first_level,
-                  hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+                  int waves, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (nparts == 0) return;
   const size_t lds = (size_t)max_n * sizeof(T);
   if (lds > 64 * 1024) throw Error(-1, "local block too large for the LDS-resident right-hand side");
-  const bool big = nparts >= BIG_BATCH;
+  if (waves != 2 && waves != 4 && waves != 8) throw Error(-1, "local solves: waves per matrix must be 2, 4 or 8");
   // with events, the dispatch itself records its start and end (exact kernel duration)
 #define GDSW_LS(F, NW)                                                                                          \
   do {                                                                                                          \
@@ -203,12 +202,14 @@ void local_solves(int nparts, int max_n, const int* order, const int64_t* dom_pt
       hipLaunchKernelGGL((k_local_solve_wg<T, F, NW>), dim3(nparts), dim3(64 * NW), lds, s, order, dom_ptr,     \
                          gidx, blk_off, blocks, r, w);                                                          \
   } while (0)
-  if (big) {
-    if (first_level) GDSW_LS(true, 2);
-    else GDSW_LS(false, 2);
+  if (first_level) {
+    if (waves == 2) GDSW_LS(true, 2);
+    else if (waves == 4) GDSW_LS(true, 4);
+    else GDSW_LS(true, 8);
   } else {
-    if (first_level) GDSW_LS(true, 4);
-    else GDSW_LS(false, 4);
+    if (waves == 2) GDSW_LS(false, 2);
+    else if (waves == 4) GDSW_LS(false, 4);
+    else GDSW_LS(false, 8);
   }
 #undef GDSW_LS
   GDSW_LAUNCH_CHECK();
@@ -248,9 +249,10 @@ void dense_gemv(int n, const double* Ainv, const double* x, double* y, double* p
 }
 
 template void local_solves<double>(int, int, const int*, const int64_t*, const int*, const int64_t*,
-                                   const double*, const double*, double*, bool, hipStream_t, hipEvent_t, hipEvent_t);
+                                   const double*, const double*, double*, bool, int, hipStream_t, hipEvent_t,
+                                   hipEvent_t);
 template void local_solves<float>(int, int, const int*, const int64_t*, const int*, const int64_t*, const float*,
-                                  const double*, double*, bool, hipStream_t, hipEvent_t, hipEvent_t);
+                                  const double*, double*, bool, int, hipStream_t, hipEvent_t, hipEvent_t);
 template void restrict_phi<double>(int, const int64_t*, const int*, const int64_t*, const int*, const int*,
                                    const int64_t*, const int*, const int64_t*, const double*, const double*, double*,
                                    hipStream_t);

@@ -87,6 +87,7 @@ struct Level {
   int* gidx = nullptr;
   int* info = nullptr;
   int* order = nullptr;          // parts by decreasing block size (apply visiting order)
+  int ls_waves = 4;              // wavefronts per matrix of the local solves (autotuned with tune = 1)
   int64_t* sc_ptr = nullptr;
   int* sc_pos = nullptr;
   double* w = nullptr;           // local solutions, sum_n
@@ -634,6 +635,42 @@ void drain_events(gdsw_ctx* C) {
   C->ev_used = 0;
 }
 
+// Autotuner: for every level, time the local solves with 2, 4 and 8 wavefronts
+// per matrix (two runs each on a zero right-hand side) and keep the fastest.
+template <typename T>
+void tune_local_solves(gdsw_ctx* C, hipStream_t s) {
+  hipEvent_t e0, e1;
+  GDSW_HIP(hipEventCreate(&e0));
+  GDSW_HIP(hipEventCreate(&e1));
+  for (size_t l = 0; l < C->levels.size(); ++l) {
+    Level& L = C->levels[l];
+    double* r0 = C->arena.alloc_n<double>((size_t)L.n);
+    GDSW_HIP(hipMemsetAsync(r0, 0, (size_t)L.n * sizeof(double), s));
+    float best = 1e30f;
+    int best_w = L.ls_waves;
+    for (int wv : {2, 4, 8}) {
+      for (int rep = 0; rep < 2; ++rep) {
+        GDSW_HIP(hipEventRecord(e0, s));
+        local_solves<T>(L.nparts, L.max_n, L.order, L.dom_ptr, L.gidx, L.blk_off, static_cast<const T*>(L.blocks), r0,
+                        L.w, l == 0, wv, s);
+        GDSW_HIP(hipEventRecord(e1, s));
+        GDSW_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        GDSW_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (rep == 1 && ms < best) {
+          best = ms;
+          best_w = wv;
+        }
+      }
+    }
+    L.ls_waves = best_w;
+    if (l < 8) C->stats.ls_waves[l] = best_w;
+    C->arena.free_one(r0);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
 template <typename T>
 void apply_level(gdsw_ctx* C, int l, const double* r, double* z, hipStream_t s);
 
@@ -668,7 +705,7 @@ void apply_level(gdsw_ctx* C, int l, const double* r, double* z, hipStream_t s) 
     e_stop = next_event(C);
   }
   local_solves<T>(L.nparts, L.max_n, L.order, L.dom_ptr, L.gidx, L.blk_off, static_cast<const T*>(L.blocks), r, L.w,
-                  l == 0, s, e_start, e_stop);
+                  l == 0, L.ls_waves, s, e_start, e_stop);
   scatter_sum(L.n, L.sc_ptr, L.sc_pos, L.w, z, s);
   if (!L.has_coarse) return;
   if (fork) GDSW_HIP(hipStreamWaitEvent(s, C->ev_join, 0));
@@ -891,6 +928,7 @@ void gdsw_default_options(gdsw_options* o) {
   o->panel = 0;
   o->profile = 0;
   o->graph = 0;
+  o->tune = 0;
 }
 
 const char* gdsw_last_error(void) { return gdsw::g_last_error.c_str(); }
@@ -920,6 +958,11 @@ int gdsw_setup(const gdsw_problem* prob, const gdsw_options* opt, void* stream, 
     GDSW_HIP(hipEventCreateWithFlags(&C->ev_join, hipEventDisableTiming));
     if (C->mixed) gdsw::setup_impl<float>(C, prob, s);
     else gdsw::setup_impl<double>(C, prob, s);
+    for (size_t l = 0; l < C->levels.size() && l < 8; ++l) C->stats.ls_waves[l] = C->levels[l].ls_waves;
+    if (C->opt.tune) {
+      if (C->mixed) gdsw::tune_local_solves<float>(C, s);
+      else gdsw::tune_local_solves<double>(C, s);
+    }
     GDSW_HIP(hipStreamSynchronize(s));
   } catch (const Error& e) {
     delete C;

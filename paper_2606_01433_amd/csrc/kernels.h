@@ -73,11 +73,12 @@ template <typename S, typename D> void convert(const S* in, D* out, int64_t n, h
 
 // ---- apply ----------------------------------------------------------------
 // w[k] = local solutions: per part, gather r at gidx, forward/backward TRSV with the LU in place.
-// order: part ids, largest block first (the visiting order of the workgroups).
+// order: part ids, largest block first (the visiting order of the workgroups);
+// waves: wavefronts per matrix (2, 4 or 8).
 template <typename T>
 void local_solves(int nparts, int max_n, const int* order, const int64_t* dom_ptr, const int* gidx,
                   const int64_t* blk_off, const T* blocks, const double* r, double* w, bool first_level,
-                  hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+                  int waves, hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // z[g] = 0.0 + sum_k w[pos[k]] over sc_ptr[g]..sc_ptr[g+1]
 void scatter_sum(int64_t n, const int64_t* sc_ptr, const int* sc_pos, const double* w, double* z, hipStream_t s);
 // rc = Phi^T r

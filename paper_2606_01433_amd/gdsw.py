@@ -27,7 +27,7 @@ class Problem(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("overlap", c_i32), ("combine", c_i32), ("precision", c_i32), ("restart", c_i32),
                 ("max_it", c_i32), ("tol", c_dbl), ("no_coarse", c_i32), ("panel", c_i32), ("profile", c_i32),
-                ("graph", c_i32)]
+                ("graph", c_i32), ("tune", c_i32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -41,7 +41,7 @@ class Stats(ctypes.Structure):
                 ("interior_flops", c_dbl * 8), ("nnz", c_i64 * 8), ("ms_maps", c_dbl), ("ms_extract", c_dbl),
                 ("ms_factor", c_dbl), ("ms_basis", c_dbl), ("ms_galerkin", c_dbl), ("ms_coarse", c_dbl),
                 ("ms_total", c_dbl), ("local_solve_launches", c_i64), ("ms_local_solve", c_dbl),
-                ("local_solve_bytes", c_dbl)]
+                ("local_solve_bytes", c_dbl), ("ls_waves", c_i32 * 8)]
 
 
 class MapsView(ctypes.Structure):
@@ -102,7 +102,7 @@ def _check(code):
 
 
 def make_options(overlap=1, combine="restricted", precision="fp64", restart=30, max_it=1000, tol=1e-8,
-                 no_coarse=False, panel=0, profile=False, graph=False):
+                 no_coarse=False, panel=0, profile=False, graph=False, tune=False):
     o = Options()
     load_library().gdsw_default_options(ctypes.byref(o))
     o.overlap = overlap
@@ -115,6 +115,7 @@ def make_options(overlap=1, combine="restricted", precision="fp64", restart=30, 
     o.panel = panel
     o.profile = int(bool(profile))
     o.graph = int(bool(graph))
+    o.tune = int(bool(tune))
     return o
 
 

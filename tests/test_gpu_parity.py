@@ -218,3 +218,17 @@ def test_graph_solves_match_eager(gd):
                 assert info["converged"]
                 assert np.array_equal(x.cpu().numpy(), xr), rep
                 assert np.isfinite(z.cpu().numpy()).all()
+
+
+def test_autotuned_local_solves_are_bit_identical(gd):
+    """The waves-per-matrix choice changes scheduling only: every row keeps its summation order."""
+    P = _problem("die16_L4_uneven")
+    r = _dev(random_vector(P.n, 8))
+    _say("autotune")
+    with gd.Context(P) as a:
+        za = a.apply(r).cpu().numpy()
+    with gd.Context(P, tune=True) as t:
+        zt = t.apply(r).cpu().numpy()
+        waves = t.stats()["ls_waves"][:3]
+    assert all(w in (2, 4, 8) for w in waves), waves
+    assert np.array_equal(za, zt)
