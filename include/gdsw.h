@@ -143,6 +143,9 @@ typedef struct gdsw_stats {
   double factor_flops[8];         /* sum (2/3) n_i^3 on level l                */
   double interior_flops[8];       /* interior LU + extension solves on level l */
   int64_t nnz[8];                 /* nonzeros of the level-l operator          */
+  /* ms_maps: host map building; ms_extract: other host preparation (lists, patterns, uploads);
+   * ms_factor / ms_basis / ms_coarse: GPU time of the local LU, basis + Galerkin and coarsest
+   * phases (they overlap); ms_total: wall clock of gdsw_setup; ms_galerkin: unused (0). */
   double ms_maps, ms_extract, ms_factor, ms_basis, ms_galerkin, ms_coarse, ms_total;
   /* profile = 1 only: event-timed level-1 local-solve launches since setup */
   int64_t local_solve_launches;

@@ -135,51 +135,66 @@ __global__ __launch_bounds__(256) void k_restrict(int n_coarse, const int64_t* _
   if (lane == 0) rc[c] = s;
 }
 
+// z[g] += y[col(g)] for the interface dofs (Phi_Gamma has a single one per row).
+__global__ void k_prolong_gamma(int64_t count, const int* __restrict__ gdofs, const int* __restrict__ dof_gcol,
+                                const double* __restrict__ y, double* __restrict__ z) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const int g = gdofs[k];
+  z[g] += y[dof_gcol[g]];
+}
+
+// z[I_i[a]] += sum_c Phi_I[a, c] y[col_i(c)], one workgroup per part, the part's
+// coarse values staged in LDS (interior dofs belong to one part only).
 template <typename T>
-__global__ void k_prolong_add(int64_t n, const int* __restrict__ dof_gcol, const int* __restrict__ dof_ipart,
-                              const int* __restrict__ dof_irow, const int64_t* __restrict__ int_ptr,
-                              const int64_t* __restrict__ pc_ptr, const int* __restrict__ pcols,
-                              const int64_t* __restrict__ phi_off, const T* __restrict__ phi,
-                              const double* __restrict__ y, double* __restrict__ z) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  const int gc = dof_gcol[g];
-  double p = 0.0;
-  if (gc >= 0) {
-    p = y[gc];
-  } else {
-    const int i = dof_ipart[g];
-    if (i >= 0) {
-      const int a = dof_irow[g];
-      const int nI = (int)(int_ptr[i + 1] - int_ptr[i]);
-      const int m = (int)(pc_ptr[i + 1] - pc_ptr[i]);
-      const T* ph = phi + phi_off[i] + a;
-      const int* pc = pcols + pc_ptr[i];
-      for (int c = 0; c < m; ++c) p += (double)ph[(int64_t)c * nI] * y[pc[c]];
-    }
+__global__ __launch_bounds__(128) void k_prolong_interior(const int64_t* __restrict__ int_ptr,
+                                                          const int* __restrict__ inter,
+                                                          const int64_t* __restrict__ pc_ptr,
+                                                          const int* __restrict__ pcols,
+                                                          const int64_t* __restrict__ phi_off,
+                                                          const T* __restrict__ phi, const double* __restrict__ y,
+                                                          double* __restrict__ z) {
+  extern __shared__ double ys[];
+  const int i = blockIdx.x;
+  const int64_t ib = int_ptr[i];
+  const int nI = (int)(int_ptr[i + 1] - ib);
+  const int m = (int)(pc_ptr[i + 1] - pc_ptr[i]);
+  const int* pc = pcols + pc_ptr[i];
+  for (int c = threadIdx.x; c < m; c += blockDim.x) ys[c] = y[pc[c]];
+  __syncthreads();
+  const T* ph = phi + phi_off[i];
+  for (int a = threadIdx.x; a < nI; a += blockDim.x) {
+    double p = 0.0;
+    for (int c = 0; c < m; ++c) p += (double)ph[a + (int64_t)c * nI] * ys[c];
+    z[inter[ib + a]] += p;
   }
-  z[g] += p;
 }
 
-constexpr int GEMV_CHUNK = 64;
-
-__global__ __launch_bounds__(256) void k_gemv_partial(int n, const double* __restrict__ A,
-                                                      const double* __restrict__ x, double* __restrict__ partial) {
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  const int c0 = blockIdx.y * GEMV_CHUNK;
+// y[r] = sum_c Ainv[r, c] x[c] with the inverse stored transposed (row r contiguous): one wave per row.
+__global__ __launch_bounds__(256) void k_gemv_rows(int n, const double* __restrict__ AT, const double* __restrict__ x,
+                                                   double* __restrict__ y) {
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= n) return;
-  const int c1 = min(n, c0 + GEMV_CHUNK);
-  double acc = 0.0;
-  for (int c = c0; c < c1; ++c) acc += A[r + (int64_t)c * n] * x[c];
-  partial[(int64_t)blockIdx.y * n + r] = acc;
-}
-
-__global__ void k_gemv_reduce(int n, int chunks, const double* __restrict__ partial, double* __restrict__ y) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
+  const int lane = threadIdx.x & 63;
+  const double* row = AT + (int64_t)r * n;
   double s = 0.0;
-  for (int q = 0; q < chunks; ++q) s += partial[(int64_t)q * n + r];
-  y[r] = s;
+  for (int c = lane; c < n; c += 64) s += row[c] * x[c];
+  s = wave_sum(s);
+  if (lane == 0) y[r] = s;
+}
+
+__global__ void k_transpose(int n, const double* __restrict__ A, double* __restrict__ AT) {
+  __shared__ double t[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    const int r = bx + threadIdx.x, c = by + k;
+    if (r < n && c < n) t[k][threadIdx.x] = A[r + (int64_t)c * n];
+  }
+  __syncthreads();
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    const int r = by + threadIdx.x, c = bx + k;       // AT[r + c n] = A[c + r n]
+    if (r < n && c < n) AT[r + (int64_t)c * n] = t[threadIdx.x][k];
+  }
 }
 
 }  // namespace
@@ -230,21 +245,28 @@ void restrict_phi(int n_coarse, const int64_t* col_ptr, const int* col_dofs, con
 }
 
 template <typename T>
-void prolong_add(int64_t n, const int* dof_gcol, const int* dof_ipart, const int* dof_irow, const int64_t* int_ptr,
-                 const int64_t* pc_ptr, const int* pcols, const int64_t* phi_off, const T* phi, const double* y,
-                 double* z, hipStream_t s) {
-  hipLaunchKernelGGL((k_prolong_add<T>), dim3(blocks_for(n, 256)), dim3(256), 0, s, n, dof_gcol, dof_ipart, dof_irow,
-                     int_ptr, pc_ptr, pcols, phi_off, phi, y, z);
+void prolong_add(int nparts, int max_m, int64_t n_gamma, const int* gdofs, const int* dof_gcol,
+                 const int64_t* int_ptr, const int* inter, const int64_t* pc_ptr, const int* pcols,
+                 const int64_t* phi_off, const T* phi, const double* y, double* z, hipStream_t s) {
+  if (n_gamma > 0) {
+    hipLaunchKernelGGL(k_prolong_gamma, dim3(blocks_for(n_gamma, 256)), dim3(256), 0, s, n_gamma, gdofs, dof_gcol, y,
+                       z);
+    GDSW_LAUNCH_CHECK();
+  }
+  if (nparts > 0) {
+    hipLaunchKernelGGL((k_prolong_interior<T>), dim3(nparts), dim3(128), (size_t)max_m * sizeof(double), s, int_ptr,
+                       inter, pc_ptr, pcols, phi_off, phi, y, z);
+    GDSW_LAUNCH_CHECK();
+  }
+}
+
+void transpose_square(int n, const double* A, double* AT, hipStream_t s) {
+  hipLaunchKernelGGL(k_transpose, dim3(blocks_for(n, 32), blocks_for(n, 32)), dim3(32, 8), 0, s, n, A, AT);
   GDSW_LAUNCH_CHECK();
 }
 
-int dense_gemv_partials(int n) { return (int)blocks_for(n, GEMV_CHUNK) * n; }
-
-void dense_gemv(int n, const double* Ainv, const double* x, double* y, double* partial, hipStream_t s) {
-  const int chunks = (int)blocks_for(n, GEMV_CHUNK);
-  hipLaunchKernelGGL(k_gemv_partial, dim3(blocks_for(n, 256), chunks), dim3(256), 0, s, n, Ainv, x, partial);
-  GDSW_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_gemv_reduce, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, chunks, partial, y);
+void dense_gemv_rows(int n, const double* AT, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemv_rows, dim3(blocks_for(n, 4)), dim3(256), 0, s, n, AT, x, y);
   GDSW_LAUNCH_CHECK();
 }
 
@@ -259,9 +281,11 @@ template void restrict_phi<double>(int, const int64_t*, const int*, const int64_
 template void restrict_phi<float>(int, const int64_t*, const int*, const int64_t*, const int*, const int*,
                                   const int64_t*, const int*, const int64_t*, const float*, const double*, double*,
                                   hipStream_t);
-template void prolong_add<double>(int64_t, const int*, const int*, const int*, const int64_t*, const int64_t*,
-                                  const int*, const int64_t*, const double*, const double*, double*, hipStream_t);
-template void prolong_add<float>(int64_t, const int*, const int*, const int*, const int64_t*, const int64_t*,
-                                 const int*, const int64_t*, const float*, const double*, double*, hipStream_t);
+template void prolong_add<double>(int, int, int64_t, const int*, const int*, const int64_t*, const int*,
+                                  const int64_t*, const int*, const int64_t*, const double*, const double*, double*,
+                                  hipStream_t);
+template void prolong_add<float>(int, int, int64_t, const int*, const int*, const int64_t*, const int*,
+                                 const int64_t*, const int*, const int64_t*, const float*, const double*, double*,
+                                 hipStream_t);
 
 }  // namespace gdsw

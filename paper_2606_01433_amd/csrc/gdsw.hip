@@ -109,6 +109,9 @@ struct Level {
   int64_t* phi_off = nullptr;
   void* phi = nullptr;           // double or float, |I_i| x m_i column-major per part
   int* iinfo = nullptr;
+  int* gdofs = nullptr;          // interface dofs (rows of Phi_Gamma)
+  int64_t n_gdofs = 0;
+  int max_m = 0;                 // largest number of coarse columns of a part
   int* bad = nullptr;            // set by the basis/Galerkin kernels on non-element-local couplings
   int max_ni = 0;
   double* rc = nullptr;          // restricted residual (n_coarse)
@@ -141,6 +144,9 @@ struct gdsw_ctx {
   // the coarse chain of the apply runs on `side`, forked from and joined to the caller's stream
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // host-to-device uploads run on `up`, which never holds compute work
+  hipStream_t up = nullptr;
+  hipEvent_t ev_up = nullptr;
   // graph mode: the solve runs on `own`; apply graphs per Krylov column
   hipStream_t own = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -160,11 +166,22 @@ struct gdsw_ctx {
       (void)hipStreamSynchronize(side);
       (void)hipStreamDestroy(side);
     }
+    if (up) {
+      (void)hipStreamSynchronize(up);
+      (void)hipStreamDestroy(up);
+    }
+    if (ev_up) (void)hipEventDestroy(ev_up);
   }
 };
 
 namespace gdsw {
 namespace {
+
+// Make stream s wait for every upload issued so far.
+void wait_uploads(gdsw_ctx* C, hipStream_t s) {
+  GDSW_HIP(hipEventRecord(C->ev_up, C->up));
+  GDSW_HIP(hipStreamWaitEvent(s, C->ev_up, 0));
+}
 
 int64_t checked_i32(int64_t v, const char* what) {
   if (v > INT32_MAX) throw Error(GDSW_EINVAL, std::string(what) + " exceeds the int32 index range");
@@ -173,6 +190,7 @@ int64_t checked_i32(int64_t v, const char* what) {
 
 template <typename T>
 void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
+  const double th = now_ms();
   Arena& A = C->arena;
   const LevelMaps& m = L.maps;
   const int N = L.nparts;
@@ -189,37 +207,9 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
     L.sum_n += ni;
     L.max_n = std::max(L.max_n, ni);
   }
-  L.dom_ptr = upload(A, m.dom_ptr, s);
-  L.dom = upload(A, m.dom, s);
-  L.blk_off = upload(A, L.blk_off_h, s);
-  {
-    std::vector<int> ord(N);
-    for (int i = 0; i < N; ++i) ord[i] = i;
-    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return L.dims[a] > L.dims[b]; });
-    L.order_h = ord;
-    L.order = upload(A, L.order_h, s);
-  }
-  L.dim = upload(A, L.dims, s);
-  T* blocks = A.alloc_n<T>((size_t)L.sum_n2);
-  L.blocks = blocks;
-  GDSW_HIP(hipMemsetAsync(blocks, 0, (size_t)L.sum_n2 * sizeof(T), s));
-  extract_blocks<T>(L.K, N, L.sum_n, L.dom_ptr, L.dom, L.blk_off, blocks, s);
-  L.piv = A.alloc_n<int>((size_t)L.sum_n);
-  L.info = A.alloc_n<int>(N);
-  GDSW_HIP(hipMemsetAsync(L.info, 0, N * sizeof(int), s));
-  LuBatch b;
-  b.count = N;
-  b.max_n = L.max_n;
-  b.off = L.blk_off;
-  b.dim = L.dim;
-  b.piv = L.piv;
-  b.poff = L.dom_ptr;
-  b.info = L.info;
-  lu_batched<T>(b, blocks, s);
-  L.perm = A.alloc_n<int>((size_t)L.sum_n);
-  lu_build_perm(b, L.perm, s);
-  L.gidx = A.alloc_n<int>((size_t)L.sum_n);
-  make_gather_index(N, L.sum_n, L.dom_ptr, L.dom, L.perm, L.gidx, s);
+  L.order_h.resize(N);
+  for (int i = 0; i < N; ++i) L.order_h[i] = i;
+  std::stable_sort(L.order_h.begin(), L.order_h.end(), [&](int a, int b) { return L.dims[a] > L.dims[b]; });
   // ordered combination lists: every position holding g (additive) or the owner's only (restricted)
   std::vector<int64_t> sc_ptr(L.n + 1, 0);
   std::vector<int> sc_pos;
@@ -242,8 +232,37 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
       sc_ptr[g + 1] = g + 1;
     }
   }
-  L.sc_ptr = upload(A, sc_ptr, s);
-  L.sc_pos = upload(A, sc_pos, s);
+  // all uploads first, on the upload stream (never queued behind compute work)
+  hipStream_t up = C->up;
+  L.dom_ptr = upload(A, m.dom_ptr, up);
+  L.dom = upload(A, m.dom, up);
+  L.blk_off = upload(A, L.blk_off_h, up);
+  L.order = upload(A, L.order_h, up);
+  L.dim = upload(A, L.dims, up);
+  L.sc_ptr = upload(A, sc_ptr, up);
+  L.sc_pos = upload(A, sc_pos, up);
+  wait_uploads(C, s);
+  C->stats.ms_extract += now_ms() - th;     // host-side preparation of the level (lists and uploads)
+  T* blocks = A.alloc_n<T>((size_t)L.sum_n2);
+  L.blocks = blocks;
+  GDSW_HIP(hipMemsetAsync(blocks, 0, (size_t)L.sum_n2 * sizeof(T), s));
+  extract_blocks<T>(L.K, N, L.sum_n, L.dom_ptr, L.dom, L.blk_off, blocks, s);
+  L.piv = A.alloc_n<int>((size_t)L.sum_n);
+  L.info = A.alloc_n<int>(N);
+  GDSW_HIP(hipMemsetAsync(L.info, 0, N * sizeof(int), s));
+  LuBatch b;
+  b.count = N;
+  b.max_n = L.max_n;
+  b.off = L.blk_off;
+  b.dim = L.dim;
+  b.piv = L.piv;
+  b.poff = L.dom_ptr;
+  b.info = L.info;
+  lu_batched<T>(b, blocks, s);
+  L.perm = A.alloc_n<int>((size_t)L.sum_n);
+  lu_build_perm(b, L.perm, s);
+  L.gidx = A.alloc_n<int>((size_t)L.sum_n);
+  make_gather_index(N, L.sum_n, L.dom_ptr, L.dom, L.perm, L.gidx, s);
   L.w = A.alloc_n<double>((size_t)L.sum_n);
 }
 
@@ -251,26 +270,27 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
 template <typename T>
 CsrDev coarse_level(gdsw_ctx* C, Level& L, hipStream_t s, std::vector<int64_t>& a0_rowptr_h,
                     std::vector<int>& a0_col_h) {
+  const double th = now_ms();
   Arena& A = C->arena;
   const LevelMaps& m = L.maps;
   const int N = L.nparts;
   L.has_coarse = true;
   L.n_coarse = m.n_coarse;
-  L.int_ptr = upload(A, m.int_ptr, s);
-  L.inter = upload(A, m.inter, s);
-  L.dof_gcol = upload(A, m.dof_gcol, s);
-  L.dof_ipart = upload(A, m.dof_ipart, s);
-  L.dof_irow = upload(A, m.dof_irow, s);
-  L.pc_ptr = upload(A, m.pc_ptr, s);
-  L.pcols = upload(A, m.pcols, s);
-  L.cp_ptr = upload(A, m.cp_ptr, s);
-  L.cp_part = upload(A, m.cp_part, s);
-  L.cp_lc = upload(A, m.cp_lc, s);
-  L.col_ptr = upload(A, m.col_ptr, s);
-  L.col_dofs = upload(A, m.col_dofs, s);
-  int64_t* z_ptr = upload(A, m.z_ptr, s);
-  int* z_dof = upload(A, m.z_dof, s);
-  int* z_lc = upload(A, m.z_lc, s);
+  L.int_ptr = upload(A, m.int_ptr, C->up);
+  L.inter = upload(A, m.inter, C->up);
+  L.dof_gcol = upload(A, m.dof_gcol, C->up);
+  L.dof_ipart = upload(A, m.dof_ipart, C->up);
+  L.dof_irow = upload(A, m.dof_irow, C->up);
+  L.pc_ptr = upload(A, m.pc_ptr, C->up);
+  L.pcols = upload(A, m.pcols, C->up);
+  L.cp_ptr = upload(A, m.cp_ptr, C->up);
+  L.cp_part = upload(A, m.cp_part, C->up);
+  L.cp_lc = upload(A, m.cp_lc, C->up);
+  L.col_ptr = upload(A, m.col_ptr, C->up);
+  L.col_dofs = upload(A, m.col_dofs, C->up);
+  int64_t* z_ptr = upload(A, m.z_ptr, C->up);
+  int* z_dof = upload(A, m.z_dof, C->up);
+  int* z_lc = upload(A, m.z_lc, C->up);
   std::vector<int64_t> aii_off(N), phi_off(N + 1), v_off(N), c_off(N);
   std::vector<int> ni(N), mi(N);
   int64_t aii_tot = 0, phi_tot = 0, v_tot = 0, c_tot = 0;
@@ -296,13 +316,28 @@ CsrDev coarse_level(gdsw_ctx* C, Level& L, hipStream_t s, std::vector<int64_t>& 
   }
   phi_off[N] = phi_tot;
   L.max_ni = max_ni;
+  L.max_m = max_m;
   L.interior_flops = iflops;
-  int64_t* d_aii_off = upload(A, aii_off, s);
-  L.phi_off = upload(A, phi_off, s);
-  int64_t* d_v_off = upload(A, v_off, s);
-  int64_t* d_c_off = upload(A, c_off, s);
-  int* d_ni = upload(A, ni, s);
-  int* d_mi = upload(A, mi, s);
+  {
+    std::vector<int> gd;
+    for (int64_t g = 0; g < L.n; ++g)
+      if (m.dof_gcol[g] >= 0) gd.push_back((int)g);
+    L.n_gdofs = (int64_t)gd.size();
+    L.gdofs = upload(A, gd, C->up);
+  }
+  int64_t* d_aii_off = upload(A, aii_off, C->up);
+  L.phi_off = upload(A, phi_off, C->up);
+  int64_t* d_v_off = upload(A, v_off, C->up);
+  int64_t* d_c_off = upload(A, c_off, C->up);
+  int* d_ni = upload(A, ni, C->up);
+  int* d_mi = upload(A, mi, C->up);
+  coarse_pattern(m, a0_rowptr_h, a0_col_h);
+  int max_row = 0;
+  for (int c = 0; c < m.n_coarse; ++c) max_row = std::max(max_row, (int)(a0_rowptr_h[c + 1] - a0_rowptr_h[c]));
+  int64_t* rp = upload(A, a0_rowptr_h, C->up);
+  int* cl = upload(A, a0_col_h, C->up);
+  wait_uploads(C, s);
+  C->stats.ms_extract += now_ms() - th;
   T* aii = A.alloc_n<T>((size_t)aii_tot);
   GDSW_HIP(hipMemsetAsync(aii, 0, (size_t)aii_tot * sizeof(T), s));
   double* rhs = A.alloc_n<double>((size_t)phi_tot);
@@ -341,14 +376,11 @@ CsrDev coarse_level(gdsw_ctx* C, Level& L, hipStream_t s, std::vector<int64_t>& 
                  L.dof_irow, L.dof_gcol, L.pc_ptr, L.pcols, L.phi_off, phi, z_ptr, z_dof, d_v_off, W, V, bad, s);
   galerkin_local<T>(N, (int64_t)m.pcols.size(), L.int_ptr, L.pc_ptr, L.phi_off, phi, W, z_ptr, z_lc, d_v_off, V,
                     d_c_off, Cm, s);
-  coarse_pattern(m, a0_rowptr_h, a0_col_h);
-  int max_row = 0;
-  for (int c = 0; c < m.n_coarse; ++c) max_row = std::max(max_row, (int)(a0_rowptr_h[c + 1] - a0_rowptr_h[c]));
+
   CsrDev K0;
   K0.n = m.n_coarse;
   K0.nnz = (int64_t)a0_col_h.size();
-  int64_t* rp = upload(A, a0_rowptr_h, s);
-  int* cl = upload(A, a0_col_h, s);
+
   double* val = A.alloc_n<double>((size_t)K0.nnz);
   galerkin_assemble(L.K, L.col_ptr, L.col_dofs, L.dof_gcol, L.cp_ptr, L.cp_part, L.cp_lc, L.pc_ptr, L.pcols, d_c_off,
                     Cm, rp, cl, val, m.n_coarse, max_row, bad, s);
@@ -369,8 +401,9 @@ void coarsest_inverse(gdsw_ctx* C, const CsrDev& K, hipStream_t s, double** dens
   csr_to_dense(K, D, s);
   std::vector<int64_t> off0 = {0};
   std::vector<int> dim0 = {n};
-  int64_t* d_off = upload(A, off0, s);
-  int* d_dim = upload(A, dim0, s);
+  int64_t* d_off = upload(A, off0, C->up);
+  int* d_dim = upload(A, dim0, C->up);
+  wait_uploads(C, s);
   int* piv = A.alloc_n<int>(n);
   int* info = A.alloc_n<int>(1);
   GDSW_HIP(hipMemsetAsync(info, 0, sizeof(int), s));
@@ -386,8 +419,10 @@ void coarsest_inverse(gdsw_ctx* C, const CsrDev& K, hipStream_t s, double** dens
   double* X = A.alloc_n<double>((size_t)n * n);
   set_identity<double>(X, n, s);
   lu_solve_batched<double>(b, D, X, d_off, d_dim, n, s);
-  C->ainv = X;
-  C->gemv_partial = A.alloc_n<double>((size_t)dense_gemv_partials(n));
+  // keep the inverse transposed, so the per-apply GEMV reads rows contiguously (X becomes scratch)
+  transpose_square(n, X, D, s);
+  C->ainv = D;
+  D = X;
   *dense_out = D;
   *info_out = info;
 }
@@ -419,21 +454,14 @@ void validate_problem(const gdsw_problem* p) {
 Plan plan_levels(const gdsw_problem* p, const gdsw_options& o) {
   validate_problem(p);
   Plan P;
-  const bool dbg = std::getenv("GDSW_DEBUG_PLAN") != nullptr;
-  double tq = now_ms();
-  auto lap = [&](const char* what) {
-    if (dbg) { double t = now_ms(); fprintf(stderr, "plan %s %.2f ms\n", what, t - tq); tq = t; }
-  };
   P.meshes.emplace_back();
   std::string err = build_level1_mesh(p->n, p->n_nodes, p->node_dof, p->n_elem, p->elem_node, p->elem_pdof,
                                       p->elem_part, p->n_parts[0], P.meshes[0]);
   if (!err.empty()) throw Error(GDSW_EINVAL, err);
-  lap("mesh1");
   const int L = p->levels;
   for (int l = 1; l < L; ++l) {
     P.maps.emplace_back();
     build_maps(P.meshes[l - 1], o.overlap, P.maps.back());
-    lap("maps");
     P.schwarz = l;
     const bool last = (l == L - 1);
     if (last) {
@@ -446,7 +474,6 @@ Plan plan_levels(const gdsw_problem* p, const gdsw_options& o) {
     P.meshes.emplace_back();
     err = build_next_mesh(P.meshes[l - 1], P.maps.back(), p->part_parent[l - 1], nxt, P.meshes[l]);
     if (!err.empty()) throw Error(GDSW_EINVAL, err);
-    lap("next");
     if (nxt == 1) {          // a single part: this coarse problem becomes the coarsest
       P.coarsest = true;
       break;
@@ -682,7 +709,7 @@ void coarse_chain(gdsw_ctx* C, int l, const double* r, hipStream_t s) {
   restrict_phi<T>(L.n_coarse, L.col_ptr, L.col_dofs, L.cp_ptr, L.cp_part, L.cp_lc, L.int_ptr, L.inter, L.phi_off, phi,
                   r, L.rc, s);
   if (l + 1 < (int)C->levels.size()) apply_level<T>(C, l + 1, L.rc, L.yc, s);
-  else dense_gemv(C->nc, C->ainv, L.rc, L.yc, C->gemv_partial, s);
+  else dense_gemv_rows(C->nc, C->ainv, L.rc, L.yc, s);
 }
 
 // z = B_l r (eq. (2.2) from level l down).  On level 1 the coarse chain runs on
@@ -711,7 +738,8 @@ void apply_level(gdsw_ctx* C, int l, const double* r, double* z, hipStream_t s) 
   if (fork) GDSW_HIP(hipStreamWaitEvent(s, C->ev_join, 0));
   else coarse_chain<T>(C, l, r, s);
   const T* phi = static_cast<const T*>(L.phi);
-  prolong_add<T>(L.n, L.dof_gcol, L.dof_ipart, L.dof_irow, L.int_ptr, L.pc_ptr, L.pcols, L.phi_off, phi, L.yc, z, s);
+  prolong_add<T>(L.nparts, L.max_m, L.n_gdofs, L.gdofs, L.dof_gcol, L.int_ptr, L.inter, L.pc_ptr, L.pcols, L.phi_off,
+                 phi, L.yc, z, s);
 }
 
 void apply_any(gdsw_ctx* C, const double* r, double* z, hipStream_t s) {
@@ -854,11 +882,17 @@ int solve_impl(gdsw_ctx* C, const double* b, double* x, hipStream_t caller, gdsw
       tick(ms_apply, last);
       spmv(K, zj, w, s);
       tick(ms_spmv, last);
+      // classical Gram-Schmidt with one reorthogonalisation (two fused axpy + dot passes)
       multi_dot(n, j + 1, V, n, w, C->dpart, h1, s);
-      multi_axpy(n, j + 1, V, n, h1, w, s);
-      multi_dot(n, j + 1, V, n, w, C->dpart, h2, s);
-      multi_axpy(n, j + 1, V, n, h2, w, s);
-      multi_dot(n, 1, w, n, w, C->dpart, nr, s);
+      if (j + 1 <= fused_gs_max_cols()) {
+        axpy_dot(n, j + 1, V, n, h1, w, C->dpart, h2, false, s);
+        axpy_dot(n, j + 1, V, n, h2, w, C->dpart, nr, true, s);
+      } else {
+        multi_axpy(n, j + 1, V, n, h1, w, s);
+        multi_dot(n, j + 1, V, n, w, C->dpart, h2, s);
+        multi_axpy(n, j + 1, V, n, h2, w, s);
+        multi_dot(n, 1, w, n, w, C->dpart, nr, s);
+      }
       scale_by_inv_norm(n, w, nr, V + (int64_t)(j + 1) * n, s);
       fetch(2 * (m + 1) + 1);
       tick(ms_orth, last);
@@ -954,6 +988,8 @@ int gdsw_setup(const gdsw_problem* prob, const gdsw_options* opt, void* stream, 
     C->mixed = C->opt.precision == GDSW_MIXED;
     hipStream_t s = static_cast<hipStream_t>(stream);
     GDSW_HIP(hipStreamCreateWithFlags(&C->side, hipStreamNonBlocking));
+    GDSW_HIP(hipStreamCreateWithFlags(&C->up, hipStreamNonBlocking));
+    GDSW_HIP(hipEventCreateWithFlags(&C->ev_up, hipEventDisableTiming));
     GDSW_HIP(hipEventCreateWithFlags(&C->ev_fork, hipEventDisableTiming));
     GDSW_HIP(hipEventCreateWithFlags(&C->ev_join, hipEventDisableTiming));
     if (C->mixed) gdsw::setup_impl<float>(C, prob, s);

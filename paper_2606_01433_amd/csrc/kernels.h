@@ -86,14 +86,16 @@ template <typename T>
 void restrict_phi(int n_coarse, const int64_t* col_ptr, const int* col_dofs, const int64_t* cp_ptr,
                   const int* cp_part, const int* cp_lc, const int64_t* int_ptr, const int* inter,
                   const int64_t* phi_off, const T* phi, const double* r, double* rc, hipStream_t s);
-// z += Phi y
+// z += Phi y: interface dofs (gdofs, n_gamma of them) take y at their column; interior dofs of
+// part i take Phi_I y restricted to the part's columns (max_m = largest column count).
 template <typename T>
-void prolong_add(int64_t n, const int* dof_gcol, const int* dof_ipart, const int* dof_irow, const int64_t* int_ptr,
-                 const int64_t* pc_ptr, const int* pcols, const int64_t* phi_off, const T* phi, const double* y,
-                 double* z, hipStream_t s);
-// y = Ainv x for a dense n x n column-major matrix (two passes, deterministic).
-void dense_gemv(int n, const double* Ainv, const double* x, double* y, double* partial, hipStream_t s);
-int dense_gemv_partials(int n);
+void prolong_add(int nparts, int max_m, int64_t n_gamma, const int* gdofs, const int* dof_gcol,
+                 const int64_t* int_ptr, const int* inter, const int64_t* pc_ptr, const int* pcols,
+                 const int64_t* phi_off, const T* phi, const double* y, double* z, hipStream_t s);
+// AT = A^T for a dense n x n column-major matrix.
+void transpose_square(int n, const double* A, double* AT, hipStream_t s);
+// y = Ainv x given AT = Ainv^T (rows of Ainv contiguous); one wave per row, deterministic.
+void dense_gemv_rows(int n, const double* AT, const double* x, double* y, hipStream_t s);
 
 // ---- Krylov ---------------------------------------------------------------
 void spmv(const CsrDev& K, const double* x, double* y, hipStream_t s);
@@ -101,6 +103,11 @@ void spmv(const CsrDev& K, const double* x, double* y, hipStream_t s);
 void multi_dot(int64_t n, int ncols, const double* V, int64_t ldv, const double* w, double* partial, double* h,
                hipStream_t s);
 int multi_dot_blocks(int64_t n);
+// Fused Gram-Schmidt pass: w -= V[:, 0..ncols) h, then out = V[:, 0..ncols)^T w (norm = false)
+// or out[0] = w . w (norm = true); ncols <= fused_gs_max_cols().
+void axpy_dot(int64_t n, int ncols, const double* V, int64_t ldv, const double* h, double* w, double* partial,
+              double* out, bool norm, hipStream_t s);
+int fused_gs_max_cols();
 // w -= V[:, 0..ncols) h
 void multi_axpy(int64_t n, int ncols, const double* V, int64_t ldv, const double* h, double* w, hipStream_t s);
 // y = alpha * x   (alpha read from device: 1 / sqrt(*nrm2))

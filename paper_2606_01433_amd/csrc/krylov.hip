@@ -69,6 +69,56 @@ __global__ __launch_bounds__(256) void k_multi_dot_reduce(int nblocks, int ncols
   if (lane == 0) h[c] = s;
 }
 
+// Fused pass of classical Gram-Schmidt: w -= V[:, :ncols] h, then per-block
+// partial dots of the updated w with V's columns (norm = 0) or with itself
+// (norm = 1).  Same row blocking and reduction tree as k_multi_dot_partial.
+__global__ __launch_bounds__(256) void k_axpy_dot_partial(int64_t n, int ncols, const double* __restrict__ V,
+                                                          int64_t ldv, const double* __restrict__ h,
+                                                          double* __restrict__ w, double* __restrict__ partial,
+                                                          int norm) {
+  __shared__ double hs[DOT_MAXC];
+  __shared__ double red[4][DOT_MAXC];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (threadIdx.x < ncols) hs[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
+  const int64_t r0 = (int64_t)blockIdx.x * DOT_BLOCK_ROWS;
+  const int64_t r1 = min(n, r0 + DOT_BLOCK_ROWS);
+  const int nout = norm ? 1 : ncols;
+  double acc[DOT_MAXC];
+#pragma unroll
+  for (int c = 0; c < DOT_MAXC; ++c) acc[c] = 0.0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+    double v[DOT_MAXC];
+    double t = 0.0;
+#pragma unroll
+    for (int c = 0; c < DOT_MAXC; ++c) {
+      v[c] = (c < ncols) ? V[r + (int64_t)c * ldv] : 0.0;
+      t += v[c] * hs[min(c, ncols - 1)] * (c < ncols ? 1.0 : 0.0);
+    }
+    const double wr = w[r] - t;
+    w[r] = wr;
+    if (norm) {
+      acc[0] += wr * wr;
+    } else {
+#pragma unroll
+      for (int c = 0; c < DOT_MAXC; ++c)
+        if (c < ncols) acc[c] += v[c] * wr;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < DOT_MAXC; ++c) {
+    if (c < nout) {
+      const double t = wave_sum(acc[c]);
+      if (lane == 0) red[wid][c] = t;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < nout) {
+    const int c = threadIdx.x;
+    partial[(int64_t)blockIdx.x * nout + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_multi_axpy(int64_t n, int ncols, const double* __restrict__ V, int64_t ldv,
                                                     const double* __restrict__ h, double* __restrict__ w) {
   __shared__ double hs[256];
@@ -109,6 +159,19 @@ void multi_dot(int64_t n, int ncols, const double* V, int64_t ldv, const double*
   hipLaunchKernelGGL(k_multi_dot_partial, dim3(nb), dim3(256), 0, s, n, ncols, V, ldv, w, partial);
   GDSW_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_multi_dot_reduce, dim3(blocks_for(ncols, 4)), dim3(256), 0, s, nb, ncols, partial, h);
+  GDSW_LAUNCH_CHECK();
+}
+
+int fused_gs_max_cols() { return DOT_MAXC; }
+
+void axpy_dot(int64_t n, int ncols, const double* V, int64_t ldv, const double* h, double* w, double* partial,
+              double* out, bool norm, hipStream_t s) {
+  if (ncols > DOT_MAXC) throw Error(-1, "axpy_dot: too many columns");
+  const int nb = multi_dot_blocks(n);
+  hipLaunchKernelGGL(k_axpy_dot_partial, dim3(nb), dim3(256), 0, s, n, ncols, V, ldv, h, w, partial, norm ? 1 : 0);
+  GDSW_LAUNCH_CHECK();
+  const int nout = norm ? 1 : ncols;
+  hipLaunchKernelGGL(k_multi_dot_reduce, dim3(blocks_for(nout, 4)), dim3(256), 0, s, nb, nout, partial, out);
   GDSW_LAUNCH_CHECK();
 }
 

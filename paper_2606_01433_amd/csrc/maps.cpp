@@ -492,20 +492,25 @@ std::string build_next_mesh(const LevelMesh& mesh, const LevelMaps& m, const int
 }
 
 void coarse_pattern(const LevelMaps& m, std::vector<int64_t>& rowptr, std::vector<int>& col) {
-  rowptr.assign(m.n_coarse + 1, 0);
-  col.clear();
-  std::vector<int> row;
-  for (int c = 0; c < m.n_coarse; ++c) {
-    row.clear();
-    for (int64_t k = m.cp_ptr[c]; k < m.cp_ptr[c + 1]; ++k) {
-      const int i = m.cp_part[k];
-      row.insert(row.end(), m.pcols.begin() + m.pc_ptr[i], m.pcols.begin() + m.pc_ptr[i + 1]);
+  const int nc = m.n_coarse;
+  std::vector<std::vector<int>> rows(nc);
+  parallel_for(nc, host_threads(), [&](int, int c0, int c1) {
+    for (int c = c0; c < c1; ++c) {
+      std::vector<int>& row = rows[c];
+      for (int64_t k = m.cp_ptr[c]; k < m.cp_ptr[c + 1]; ++k) {
+        const int i = m.cp_part[k];
+        row.insert(row.end(), m.pcols.begin() + m.pc_ptr[i], m.pcols.begin() + m.pc_ptr[i + 1]);
+      }
+      std::sort(row.begin(), row.end());
+      row.erase(std::unique(row.begin(), row.end()), row.end());
     }
-    std::sort(row.begin(), row.end());
-    row.erase(std::unique(row.begin(), row.end()), row.end());
-    col.insert(col.end(), row.begin(), row.end());
-    rowptr[c + 1] = (int64_t)col.size();
-  }
+  });
+  rowptr.assign(nc + 1, 0);
+  for (int c = 0; c < nc; ++c) rowptr[c + 1] = rowptr[c] + (int64_t)rows[c].size();
+  col.resize(rowptr[nc]);
+  parallel_for(nc, host_threads(), [&](int, int c0, int c1) {
+    for (int c = c0; c < c1; ++c) std::copy(rows[c].begin(), rows[c].end(), col.begin() + rowptr[c]);
+  });
 }
 
 }  // namespace gdsw
