@@ -152,6 +152,12 @@ typedef struct gdsw_stats {
   double ms_local_solve;          /* summed kernel time                         */
   double local_solve_bytes;       /* algorithmic bytes of one launch: sum_i n_i^2 s + 20 n_i */
   int32_t ls_waves[8];            /* wavefronts per matrix used by the local solves of level l */
+  /* setup timeline from GPU events, in ms after the setup's first event on the caller's stream:
+   * [l][0] begin and [l][1] end of level l+1's local factorization (side stream) and of its
+   * basis + Galerkin phase (caller's stream); tl_coarsest: the coarsest factorization. */
+  double tl_factor[8][2];
+  double tl_basis[8][2];
+  double tl_coarsest[2];
 } gdsw_stats;
 
 /* Index maps of one level, host copies owned by the context (valid until

@@ -105,6 +105,10 @@ __global__ void k_scatter_sum(int64_t n, const int64_t* __restrict__ sc_ptr, con
                               const double* __restrict__ w, double* __restrict__ z) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
+  if (!sc_ptr) {                       // restricted: one position per dof (still a sum into zero)
+    z[g] = 0.0 + w[sc_pos[g]];
+    return;
+  }
   double s = 0.0;
   for (int64_t k = sc_ptr[g]; k < sc_ptr[g + 1]; ++k) s += w[sc_pos[k]];
   z[g] = s;

@@ -51,6 +51,17 @@ __device__ __forceinline__ float lane_value(float v, int l) {
 }
 __device__ __forceinline__ int lane_value(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
+// Workgroups of a 1-D grid are dispatched round-robin over the 8 XCDs (each
+// with its own L2).  xcd_remap(b, G) maps hardware workgroup b to a logical
+// index so that every XCD receives one contiguous range of logical indices:
+// neighbouring tiles (same matrix, shared operand panels) then share an L2.
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned G) {
+  const unsigned x = b % NUM_XCD, j = b / NUM_XCD;
+  const unsigned q = G / NUM_XCD, r = G % NUM_XCD;
+  return x * q + (x < r ? x : r) + j;
+}
+
 // Lower bound of `key` in the sorted array a[0..n).
 __device__ __forceinline__ int lower_bound_i32(const int* a, int n, int key) {
   int lo = 0, hi = n;

@@ -4,7 +4,11 @@
 #include "../../include/gdsw.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <map>
+#include <mutex>
+#include <thread>
 #include <cstdio>
 #include <cstdlib>
 #include <cmath>
@@ -58,11 +62,58 @@ class Arena {
   size_t bytes_ = 0;
 };
 
-template <typename T>
-T* upload(Arena& a, const std::vector<T>& v, hipStream_t s) {
-  T* d = a.alloc_n<T>(v.size());
-  if (!v.empty()) GDSW_HIP(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
-  return d;
+
+// Page-locked host buffers shared by all contexts of the process; a context
+// takes them while it uploads and gives them back at the end of its setup
+// (held until the process exits).
+std::mutex g_pin_mu;
+std::multimap<size_t, void*> g_pin_free;
+
+void* pinned_take(size_t bytes, size_t& cap) {
+  {
+    std::lock_guard<std::mutex> g(g_pin_mu);
+    auto it = g_pin_free.lower_bound(bytes);
+    if (it != g_pin_free.end()) {
+      cap = it->first;
+      void* p = it->second;
+      g_pin_free.erase(it);
+      return p;
+    }
+  }
+  cap = std::max<size_t>(bytes, size_t(4) << 20);
+  cap = (cap + (size_t(1) << 20) - 1) & ~((size_t(1) << 20) - 1);
+  void* p = nullptr;
+  GDSW_HIP(hipHostMalloc(&p, cap, hipHostMallocDefault));
+  return p;
+}
+
+void pinned_give(void* p, size_t cap) {
+  std::lock_guard<std::mutex> g(g_pin_mu);
+  g_pin_free.emplace(cap, p);
+}
+
+// Copy n bytes with up to 16 host threads (large packs only).
+void parallel_copy(char* dst, const char* src, size_t n) {
+  constexpr size_t PIECE = size_t(1) << 20;
+  if (n <= 2 * PIECE) {
+    std::memcpy(dst, src, n);
+    return;
+  }
+  const size_t pieces = (n + PIECE - 1) / PIECE;
+  const int nt = (int)std::min<size_t>(pieces, std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
+  std::atomic<size_t> next(0);
+  auto work = [&] {
+    for (;;) {
+      const size_t k = next.fetch_add(1);
+      if (k >= pieces) break;
+      const size_t o = k * PIECE;
+      std::memcpy(dst + o, src + o, std::min(PIECE, n - o));
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+  work();
+  for (auto& th : pool) th.join();
 }
 
 struct Level {
@@ -152,6 +203,12 @@ struct gdsw_ctx {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::vector<hipGraphExec_t> apply_exec;
   bool capturing = false;
+  // page-locked staging buffers held while uploads may be in flight
+  std::vector<std::pair<void*, size_t>> pinned;
+  void release_pinned() {
+    for (auto& pc : pinned) gdsw::pinned_give(pc.first, pc.second);
+    pinned.clear();
+  }
   ~gdsw_ctx() {
     if (own) (void)hipStreamSynchronize(own);
     for (hipGraphExec_t g : apply_exec)
@@ -170,6 +227,7 @@ struct gdsw_ctx {
       (void)hipStreamSynchronize(up);
       (void)hipStreamDestroy(up);
     }
+    release_pinned();
     if (ev_up) (void)hipEventDestroy(ev_up);
   }
 };
@@ -182,6 +240,45 @@ void wait_uploads(gdsw_ctx* C, hipStream_t s) {
   GDSW_HIP(hipEventRecord(C->ev_up, C->up));
   GDSW_HIP(hipStreamWaitEvent(s, C->ev_up, 0));
 }
+
+// Uploads of one setup phase: the host arrays are packed into one page-locked
+// buffer and moved with a single asynchronous copy on the upload stream into
+// one device allocation; each destination pointer is set to its slice.
+class UploadBatch {
+ public:
+  template <typename T>
+  void add(T** dst, const std::vector<T>& v) {
+    entries_.push_back({reinterpret_cast<void**>(dst), v.data(), v.size() * sizeof(T), total_});
+    total_ += (v.size() * sizeof(T) + 255) & ~size_t(255);
+  }
+  // Pack, copy and point the destinations at the device slices; stream s then
+  // waits for the copy.
+  void flush(gdsw_ctx* C, hipStream_t s) {
+    if (entries_.empty()) return;
+    const size_t total = std::max<size_t>(total_, 256);
+    char* d = static_cast<char*>(C->arena.alloc(total));
+    size_t cap = 0;
+    char* h = static_cast<char*>(pinned_take(total, cap));
+    C->pinned.push_back({h, cap});
+    for (const Entry& e : entries_) {
+      if (e.bytes) parallel_copy(h + e.off, static_cast<const char*>(e.src), e.bytes);
+      *e.dst = d + e.off;
+    }
+    GDSW_HIP(hipMemcpyAsync(d, h, total_, hipMemcpyHostToDevice, C->up));
+    wait_uploads(C, s);
+    entries_.clear();
+    total_ = 0;
+  }
+
+ private:
+  struct Entry {
+    void** dst;
+    const void* src;
+    size_t bytes, off;
+  };
+  std::vector<Entry> entries_;
+  size_t total_ = 0;
+};
 
 int64_t checked_i32(int64_t v, const char* what) {
   if (v > INT32_MAX) throw Error(GDSW_EINVAL, std::string(what) + " exceeds the int32 index range");
@@ -211,37 +308,19 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
   for (int i = 0; i < N; ++i) L.order_h[i] = i;
   std::stable_sort(L.order_h.begin(), L.order_h.end(), [&](int a, int b) { return L.dims[a] > L.dims[b]; });
   // ordered combination lists: every position holding g (additive) or the owner's only (restricted)
-  std::vector<int64_t> sc_ptr(L.n + 1, 0);
+  std::vector<int64_t> sc_ptr;
   std::vector<int> sc_pos;
-  const bool additive = C->opt.combine == GDSW_COMBINE_ADDITIVE;
-  if (additive) {
-    for (int64_t k = 0; k < L.sum_n; ++k) sc_ptr[m.dom[k] + 1]++;
-    for (int64_t g = 0; g < L.n; ++g) sc_ptr[g + 1] += sc_ptr[g];
-    sc_pos.resize(L.sum_n);
-    std::vector<int64_t> fill(sc_ptr.begin(), sc_ptr.end() - 1);
-    for (int64_t k = 0; k < L.sum_n; ++k) sc_pos[fill[m.dom[k]]++] = (int)k;
-  } else {
-    sc_pos.resize(L.n);
-    for (int64_t g = 0; g < L.n; ++g) {
-      const int i = m.owner[g];
-      const int* D = m.dom.data() + m.dom_ptr[i];
-      const int ni = L.dims[i];
-      const int a = (int)(std::lower_bound(D, D + ni, (int)g) - D);
-      if (a >= ni || D[a] != g) throw Error(GDSW_EINVAL, "owner part does not hold its dof");
-      sc_pos[g] = (int)(m.dom_ptr[i] + a);
-      sc_ptr[g + 1] = g + 1;
-    }
-  }
-  // all uploads first, on the upload stream (never queued behind compute work)
-  hipStream_t up = C->up;
-  L.dom_ptr = upload(A, m.dom_ptr, up);
-  L.dom = upload(A, m.dom, up);
-  L.blk_off = upload(A, L.blk_off_h, up);
-  L.order = upload(A, L.order_h, up);
-  L.dim = upload(A, L.dims, up);
-  L.sc_ptr = upload(A, sc_ptr, up);
-  L.sc_pos = upload(A, sc_pos, up);
-  wait_uploads(C, s);
+  const std::string err = scatter_lists(m, L.n, C->opt.combine == GDSW_COMBINE_ADDITIVE, sc_ptr, sc_pos);
+  if (!err.empty()) throw Error(GDSW_EINVAL, err);
+  UploadBatch B;
+  B.add(&L.dom_ptr, m.dom_ptr);
+  B.add(&L.dom, m.dom);
+  B.add(&L.blk_off, L.blk_off_h);
+  B.add(&L.order, L.order_h);
+  B.add(&L.dim, L.dims);
+  if (!sc_ptr.empty()) B.add(&L.sc_ptr, sc_ptr);
+  B.add(&L.sc_pos, sc_pos);
+  B.flush(C, s);
   C->stats.ms_extract += now_ms() - th;     // host-side preparation of the level (lists and uploads)
   T* blocks = A.alloc_n<T>((size_t)L.sum_n2);
   L.blocks = blocks;
@@ -276,21 +355,24 @@ CsrDev coarse_level(gdsw_ctx* C, Level& L, hipStream_t s, std::vector<int64_t>& 
   const int N = L.nparts;
   L.has_coarse = true;
   L.n_coarse = m.n_coarse;
-  L.int_ptr = upload(A, m.int_ptr, C->up);
-  L.inter = upload(A, m.inter, C->up);
-  L.dof_gcol = upload(A, m.dof_gcol, C->up);
-  L.dof_ipart = upload(A, m.dof_ipart, C->up);
-  L.dof_irow = upload(A, m.dof_irow, C->up);
-  L.pc_ptr = upload(A, m.pc_ptr, C->up);
-  L.pcols = upload(A, m.pcols, C->up);
-  L.cp_ptr = upload(A, m.cp_ptr, C->up);
-  L.cp_part = upload(A, m.cp_part, C->up);
-  L.cp_lc = upload(A, m.cp_lc, C->up);
-  L.col_ptr = upload(A, m.col_ptr, C->up);
-  L.col_dofs = upload(A, m.col_dofs, C->up);
-  int64_t* z_ptr = upload(A, m.z_ptr, C->up);
-  int* z_dof = upload(A, m.z_dof, C->up);
-  int* z_lc = upload(A, m.z_lc, C->up);
+  int64_t *z_ptr, *d_aii_off, *d_v_off, *d_c_off;
+  int *z_dof, *z_lc, *d_ni, *d_mi;
+  UploadBatch B;
+  B.add(&L.int_ptr, m.int_ptr);
+  B.add(&L.inter, m.inter);
+  B.add(&L.dof_gcol, m.dof_gcol);
+  B.add(&L.dof_ipart, m.dof_ipart);
+  B.add(&L.dof_irow, m.dof_irow);
+  B.add(&L.pc_ptr, m.pc_ptr);
+  B.add(&L.pcols, m.pcols);
+  B.add(&L.cp_ptr, m.cp_ptr);
+  B.add(&L.cp_part, m.cp_part);
+  B.add(&L.cp_lc, m.cp_lc);
+  B.add(&L.col_ptr, m.col_ptr);
+  B.add(&L.col_dofs, m.col_dofs);
+  B.add(&z_ptr, m.z_ptr);
+  B.add(&z_dof, m.z_dof);
+  B.add(&z_lc, m.z_lc);
   std::vector<int64_t> aii_off(N), phi_off(N + 1), v_off(N), c_off(N);
   std::vector<int> ni(N), mi(N);
   int64_t aii_tot = 0, phi_tot = 0, v_tot = 0, c_tot = 0;
@@ -318,25 +400,18 @@ CsrDev coarse_level(gdsw_ctx* C, Level& L, hipStream_t s, std::vector<int64_t>& 
   L.max_ni = max_ni;
   L.max_m = max_m;
   L.interior_flops = iflops;
-  {
-    std::vector<int> gd;
-    for (int64_t g = 0; g < L.n; ++g)
-      if (m.dof_gcol[g] >= 0) gd.push_back((int)g);
-    L.n_gdofs = (int64_t)gd.size();
-    L.gdofs = upload(A, gd, C->up);
-  }
-  int64_t* d_aii_off = upload(A, aii_off, C->up);
-  L.phi_off = upload(A, phi_off, C->up);
-  int64_t* d_v_off = upload(A, v_off, C->up);
-  int64_t* d_c_off = upload(A, c_off, C->up);
-  int* d_ni = upload(A, ni, C->up);
-  int* d_mi = upload(A, mi, C->up);
-  coarse_pattern(m, a0_rowptr_h, a0_col_h);
-  int max_row = 0;
-  for (int c = 0; c < m.n_coarse; ++c) max_row = std::max(max_row, (int)(a0_rowptr_h[c + 1] - a0_rowptr_h[c]));
-  int64_t* rp = upload(A, a0_rowptr_h, C->up);
-  int* cl = upload(A, a0_col_h, C->up);
-  wait_uploads(C, s);
+  std::vector<int> gd;
+  for (int64_t g = 0; g < L.n; ++g)
+    if (m.dof_gcol[g] >= 0) gd.push_back((int)g);
+  L.n_gdofs = (int64_t)gd.size();
+  B.add(&L.gdofs, gd);
+  B.add(&d_aii_off, aii_off);
+  B.add(&L.phi_off, phi_off);
+  B.add(&d_v_off, v_off);
+  B.add(&d_c_off, c_off);
+  B.add(&d_ni, ni);
+  B.add(&d_mi, mi);
+  B.flush(C, s);
   C->stats.ms_extract += now_ms() - th;
   T* aii = A.alloc_n<T>((size_t)aii_tot);
   GDSW_HIP(hipMemsetAsync(aii, 0, (size_t)aii_tot * sizeof(T), s));
@@ -376,6 +451,17 @@ CsrDev coarse_level(gdsw_ctx* C, Level& L, hipStream_t s, std::vector<int64_t>& 
                  L.dof_irow, L.dof_gcol, L.pc_ptr, L.pcols, L.phi_off, phi, z_ptr, z_dof, d_v_off, W, V, bad, s);
   galerkin_local<T>(N, (int64_t)m.pcols.size(), L.int_ptr, L.pc_ptr, L.phi_off, phi, W, z_ptr, z_lc, d_v_off, V,
                     d_c_off, Cm, s);
+  // sparsity of the coarse operator, built on the host while the kernels above run
+  const double tp = now_ms();
+  coarse_pattern(m, a0_rowptr_h, a0_col_h);
+  int max_row = 0;
+  for (int c = 0; c < m.n_coarse; ++c) max_row = std::max(max_row, (int)(a0_rowptr_h[c + 1] - a0_rowptr_h[c]));
+  int64_t* rp;
+  int* cl;
+  B.add(&rp, a0_rowptr_h);
+  B.add(&cl, a0_col_h);
+  B.flush(C, s);
+  C->stats.ms_extract += now_ms() - tp;
 
   CsrDev K0;
   K0.n = m.n_coarse;
@@ -401,9 +487,12 @@ void coarsest_inverse(gdsw_ctx* C, const CsrDev& K, hipStream_t s, double** dens
   csr_to_dense(K, D, s);
   std::vector<int64_t> off0 = {0};
   std::vector<int> dim0 = {n};
-  int64_t* d_off = upload(A, off0, C->up);
-  int* d_dim = upload(A, dim0, C->up);
-  wait_uploads(C, s);
+  int64_t* d_off;
+  int* d_dim;
+  UploadBatch B;
+  B.add(&d_off, off0);
+  B.add(&d_dim, dim0);
+  B.flush(C, s);
   int* piv = A.alloc_n<int>(n);
   int* info = A.alloc_n<int>(1);
   GDSW_HIP(hipMemsetAsync(info, 0, sizeof(int), s));
@@ -533,6 +622,7 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
     evs.push_back(e);
     return (int)evs.size() - 1;
   };
+  const int e_setup = mark(s);
   // The local factorizations run on the side stream, concurrently with the
   // basis / Galerkin / coarser-level chain on the caller's stream; level l's
   // factorization only waits for its operator K_l.
@@ -609,6 +699,8 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
   }
   GDSW_HIP(hipStreamSynchronize(fs));
   GDSW_HIP(hipStreamSynchronize(s));
+  GDSW_HIP(hipStreamSynchronize(C->up));
+  C->release_pinned();
   for (const Level& L : C->levels) {
     check_info(L.info, L.nparts, "local block", L.index, s);
     if (L.has_coarse) {
@@ -636,6 +728,18 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
   for (auto& pr : ev_factor) st.ms_factor += span(pr.first, pr.second);
   for (auto& pr : ev_basis) st.ms_basis += span(pr.first, pr.second);
   if (coarsest) st.ms_coarse = span(ec0, ec1);
+  for (size_t l = 0; l < ev_factor.size() && l < 8; ++l) {
+    st.tl_factor[l][0] = span(e_setup, ev_factor[l].first);
+    st.tl_factor[l][1] = span(e_setup, ev_factor[l].second);
+  }
+  for (size_t l = 0; l < ev_basis.size() && l < 8; ++l) {
+    st.tl_basis[l][0] = span(e_setup, ev_basis[l].first);
+    st.tl_basis[l][1] = span(e_setup, ev_basis[l].second);
+  }
+  if (coarsest) {
+    st.tl_coarsest[0] = span(e_setup, ec0);
+    st.tl_coarsest[1] = span(e_setup, ec1);
+  }
   for (hipEvent_t e : evs) (void)hipEventDestroy(e);
   st.ms_maps = host_ms;
   st.ms_total = now_ms() - t0;

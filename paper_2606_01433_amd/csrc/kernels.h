@@ -79,7 +79,7 @@ template <typename T>
 void local_solves(int nparts, int max_n, const int* order, const int64_t* dom_ptr, const int* gidx,
                   const int64_t* blk_off, const T* blocks, const double* r, double* w, bool first_level,
                   int waves, hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
-// z[g] = 0.0 + sum_k w[pos[k]] over sc_ptr[g]..sc_ptr[g+1]
+// z[g] = 0.0 + sum_k w[pos[k]] over sc_ptr[g]..sc_ptr[g+1]; with sc_ptr == nullptr, z[g] = 0.0 + w[pos[g]]
 void scatter_sum(int64_t n, const int64_t* sc_ptr, const int* sc_pos, const double* w, double* z, hipStream_t s);
 // rc = Phi^T r
 template <typename T>

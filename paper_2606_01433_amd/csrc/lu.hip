@@ -9,7 +9,8 @@
 // Right-looking blocked algorithm with two-level blocking, one launch per
 // phase for the whole (uneven) batch.  Each outer step covers 2*NB columns:
 //   panel  : factor sub-panel 1, A[k:n, k:k+NB] (one workgroup per matrix,
-//            rows held in registers; wave shuffles find the pivot);
+//            rows held in registers and labelled with their interchanged
+//            position; DPP wave reductions find the pivot);
 //   inner  : its interchanges and U on sub-panel 2's columns, then the rank-NB
 //            MFMA update of sub-panel 2; factor sub-panel 2;
 //   outer  : the step's interchanges on all other columns, U12 = L11^{-1} A12
@@ -42,8 +43,8 @@ template <> struct Mfma<float> {
 };
 
 constexpr int TILE = 64;
-constexpr int PANEL_REG_R = 3;                       // rows per thread of the tallest register panel
-constexpr int PANEL_REG_ROWS = 512 * PANEL_REG_R;
+// Tallest panel held in registers: 512 threads x 3 rows (FP64) or x 6 rows (FP32).
+template <typename T> constexpr int panel_reg_rows() { return sizeof(T) == 8 ? 512 * 3 : 512 * 6; }
 
 // C[M x N] -= A[M x K] * B[K x N] on the 64x64 tile (ty, tx); K <= KMAX.
 // Column-major operands.  Four waves, each owning a 32x32 quarter computed as
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(256) void k_lu_panel(T* __restrict__ Ab, const int6
                                                   int k) {
   const int i = blockIdx.x;
   const int n = dim[i];
-  if (k >= n || n - k <= PANEL_REG_ROWS) return;   // short panels go to k_lu_panel_reg
+  if (k >= n || n - k <= panel_reg_rows<T>()) return;   // shorter panels go to k_lu_panel_rot
   const int jb = min(NB, n - k);
   T* A = Ab + off[i];
   int* piv = pivb + poff[i];
@@ -248,122 +249,209 @@ __global__ __launch_bounds__(256) void k_lu_panel(T* __restrict__ Ab, const int6
   }
 }
 
-// Register-resident panel factorization for panels of at most 512 * R rows:
-// thread t keeps rows k + t + 512 q (q < R) of the NB panel columns in
-// registers.  Per column: a block-wide argmax (shuffles, then every thread
-// scans the 8 wave winners, so all agree on the pivot without a second
-// barrier), the pivot row and row j are exchanged through LDS, and every row
-// below is scaled and updated in registers.  Two barriers per column; the
-// panel is read and written once.
-template <typename T, int NB, int R>
-__global__ __launch_bounds__(512) void k_lu_panel_reg(T* __restrict__ Ab, const int64_t* __restrict__ off,
-                                                      const int* __restrict__ dim, int* __restrict__ pivb,
-                                                      const int64_t* __restrict__ poff, int* __restrict__ info,
-                                                      int k) {
-  constexpr int NT = 512;
+// (ov, ol) beats (val, lab): larger value, equal values to the smaller label.
+// Evaluated without short-circuit so it compiles to compares and selects.
+__device__ __forceinline__ bool argmax_beats(double ov, int ol, double val, int lab) {
+  return (ov > val) | ((ov == val) & (ol < lab));
+}
+
+// One DPP step of the pivot search: combine (val, lab) with the lane selected
+// by CTRL (a permutation inside each row of 16 lanes).
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp_step(double& val, int& lab) {
+  const long long bits = __builtin_bit_cast(long long, val);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(bits & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(bits >> 32), CTRL, 0xf, 0xf, false);
+  const int ol = __builtin_amdgcn_mov_dpp(lab, CTRL, 0xf, 0xf, false);
+  const double ov = __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+  const bool t = argmax_beats(ov, ol, val, lab);
+  val = t ? ov : val;
+  lab = t ? ol : lab;
+}
+
+// Wave-wide argmax of (val, lab); every lane receives the winner.  Butterflies
+// inside each 16-lane row (quad_perm [1,0,3,2], [2,3,0,1], half mirror,
+// mirror), then the four row winners are combined from lanes 0, 16, 32, 48.
+__device__ __forceinline__ void wave_argmax(double& val, int& lab) {
+  argmax_dpp_step<0xB1>(val, lab);
+  argmax_dpp_step<0x4E>(val, lab);
+  argmax_dpp_step<0x141>(val, lab);
+  argmax_dpp_step<0x140>(val, lab);
+  double rv[4];
+  int rl[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    rv[r] = lane_value(val, 16 * r);
+    rl[r] = lane_value(lab, 16 * r);
+  }
+  double b = rv[0];
+  int l = rl[0];
+#pragma unroll
+  for (int r = 1; r < 4; ++r) {
+    const bool t = argmax_beats(rv[r], rl[r], b, l);
+    b = t ? rv[r] : b;
+    l = t ? rl[r] : l;
+  }
+  val = b;
+  lab = l;
+}
+
+constexpr int NO_ROW = 0x7fffffff;
+
+// Register-resident panel factorization of A[k:n, k:k+NB] for panels of at most
+// NT * R rows, one workgroup per matrix.  Thread t holds panel rows t + NT q
+// (q < R).  Rows never move while the panel is factored: each carries a label,
+// its position in the interchanged order, and an interchange swaps two labels;
+// at the end every row is stored at its label.
+//
+// Columns are processed in chunks of 8 with the 8 steps of a chunk unrolled
+// (static register indices); the loop over chunks is not unrolled, so the
+// code stays small.  After a chunk the registers of each row rotate by 8:
+// the current chunk is always registers 0..7, the columns still to factor
+// follow, and finished chunks collect at the top (after NB / 8 chunks the
+// original order is back).  Blocks of 8 finished columns are skipped by the
+// rank-1 update with a wavefront-uniform branch.
+//
+// Per column: every thread proposes its best candidate (largest |a| among rows
+// at or below the diagonal, ties to the smallest label), waves reduce with DPP,
+// each wave's winner writes value, label and its row to a double-buffered LDS
+// slot, one barrier, and every thread picks the winning wave and applies the
+// rank-1 update from that slot.  Nothing is stored to global memory inside the
+// column loop (pivot indices and the singularity flag are written after it),
+// so the barriers never wait on global stores.
+template <typename T, int NB, int NT, int R>
+__global__ __launch_bounds__(NT) void k_lu_panel_rot(T* __restrict__ Ab, const int64_t* __restrict__ off,
+                                                     const int* __restrict__ dim, int* __restrict__ pivb,
+                                                     const int64_t* __restrict__ poff, int* __restrict__ info,
+                                                     int k) {
+  static_assert(NB % 8 == 0, "panel width must be a multiple of 8");
+  constexpr int NW = NT / 64;
+  constexpr int CH = 8;
   const int i = blockIdx.x;
   const int n = dim[i];
-  if (k >= n || n - k > NT * R) return;    // taller panels go to k_lu_panel
-  const int jb = min(NB, n - k);
-  T* A = Ab + off[i];
-  int* piv = pivb + poff[i];
-  __shared__ double s_val[NT / 64];
-  __shared__ int s_idx[NT / 64];
-  __shared__ T urow[NB];
-  __shared__ T jrow[NB];
+  const int m = n - k;
+  if (m <= 0 || m > NT * R) return;         // taller panels go to k_lu_panel
+  const int jb = min(NB, m);
+  T* A = Ab + off[i] + k + (int64_t)k * n;  // panel origin
+  int* piv = pivb + poff[i] + k;
+  __shared__ double s_val[2][NW];
+  __shared__ int s_lab[2][NW];
+  __shared__ T s_row[2 * NW * NB];          // [buffer][wave][column]
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   T v[R][NB];
-#pragma clang loop unroll(full)
+  int lab[R];
+  int piv_r = 0;                            // lane j of wave 0 keeps pivot j
+  int first_zero = 0;                       // 1 + first column without a nonzero pivot
+#pragma unroll
   for (int q = 0; q < R; ++q) {
-    const int row = k + tid + NT * q;
-#pragma clang loop unroll(full)
-    for (int c = 0; c < NB; ++c) v[q][c] = (row < n && c < jb) ? A[row + (int64_t)(k + c) * n] : T(0);
+    const int r = tid + NT * q;
+    lab[q] = r < m ? r : NO_ROW;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) v[q][c] = (r < m && c < jb) ? A[r + (int64_t)c * n] : T(0);
   }
-#pragma clang loop unroll(full)
-  for (int j = 0; j < NB; ++j) {
-    if (j < jb) {
-      const int gj = k + j;
+#pragma clang loop unroll(disable)
+  for (int g = 0; g < NB / CH; ++g) {
+    const int live = NB / CH - g;           // 8-column blocks not yet finished (block 0 = this chunk)
+#pragma unroll
+    for (int jj = 0; jj < CH; ++jj) {
+      const int j = CH * g + jj;
+      if (j >= jb) break;
+      const int buf = j & 1;
       double best = -1.0;
-      int bi = n;
-#pragma clang loop unroll(full)
+      int bl = NO_ROW, bq = -1;
+#pragma unroll
       for (int q = 0; q < R; ++q) {
-        const int row = k + tid + NT * q;
-        const double a = fabs((double)v[q][j]);
-        if (row >= gj && row < n && a > best) {
-          best = a;
-          bi = row;
-        }
+        const double a = fabs((double)v[q][jj]);
+        const bool t = (lab[q] >= j) & (lab[q] != NO_ROW) & argmax_beats(a, lab[q], best, bl);
+        best = t ? a : best;
+        bl = t ? lab[q] : bl;
+        bq = t ? q : bq;
       }
-#pragma clang loop unroll(full)
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(best, o, WAVE);
-        const int oi = __shfl_xor(bi, o, WAVE);
-        if (ov > best || (ov == best && oi < bi)) {
-          best = ov;
-          bi = oi;
-        }
-      }
+      double wb = best;
+      int wl = bl;
+      wave_argmax(wb, wl);
       if (lane == 0) {
-        s_val[w] = best;
-        s_idx[w] = bi;
+        s_val[buf][w] = wb;
+        s_lab[buf][w] = wl;
+      }
+      if (wl != NO_ROW && bl == wl) {        // this wave's winner publishes its row
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+          if (bq == q) {
+#pragma unroll
+            for (int c = jj; c < NB; ++c) s_row[(buf * NW + w) * NB + c] = v[q][c];
+          }
       }
       __syncthreads();
-      double b = s_val[0];
-      int p = s_idx[0];
-#pragma clang loop unroll(full)
-      for (int q = 1; q < NT / 64; ++q)
-        if (s_val[q] > b || (s_val[q] == b && s_idx[q] < p)) {
-          b = s_val[q];
-          p = s_idx[q];
-        }
-      const bool singular = (p >= n || !(b > 0.0));
-      if (p >= n) p = gj;
-      if (tid == 0) {
-        piv[gj] = p;
-        if (singular && info[i] == 0) info[i] = gj + 1;
+      double wv[NW];
+      int wlab[NW];
+#pragma unroll
+      for (int x = 0; x < NW; ++x) {
+        wv[x] = s_val[buf][x];
+        wlab[x] = s_lab[buf][x];
       }
-      // owners publish the pivot row (old row p) and row j
-      const int op = p - k, oj = gj - k;
-#pragma clang loop unroll(full)
+      double b = wv[0];
+      int p = wlab[0], pw = 0;
+#pragma unroll
+      for (int x = 1; x < NW; ++x) {
+        const bool t = argmax_beats(wv[x], wlab[x], b, p);
+        b = t ? wv[x] : b;
+        p = t ? wlab[x] : p;
+        pw = t ? x : pw;
+      }
+      const bool have = (p != NO_ROW);       // false only when every candidate is NaN
+      if (tid == j) piv_r = k + (have ? p : j);
+      if ((!have || !(b > 0.0)) && first_zero == 0) first_zero = j + 1;
+      if (!have) continue;
+#pragma unroll
+      for (int q = 0; q < R; ++q) lab[q] = (lab[q] == j) ? p : (lab[q] == p ? j : lab[q]);
+      const int src = (buf * NW + pw) * NB;
+      const T pv = s_row[src + jj];
+      T l[R];
+#pragma unroll
       for (int q = 0; q < R; ++q) {
-        if (op == tid + NT * q) {
-#pragma clang loop unroll(full)
-          for (int c = 0; c < NB; ++c) urow[c] = v[q][c];
-        }
-        if (oj == tid + NT * q) {
-#pragma clang loop unroll(full)
-          for (int c = 0; c < NB; ++c) jrow[c] = v[q][c];
-        }
+        const bool below = lab[q] > j && lab[q] != NO_ROW;
+        l[q] = below ? ((pv != T(0)) ? v[q][jj] / pv : v[q][jj]) : T(0);
+        v[q][jj] = below ? l[q] : v[q][jj];
       }
-      __syncthreads();
-      const T pv = urow[j];
-#pragma clang loop unroll(full)
-      for (int q = 0; q < R; ++q) {
-        const int lr = tid + NT * q;
-        const int row = k + lr;
-        if (lr == oj) {
-#pragma clang loop unroll(full)
-          for (int c = 0; c < NB; ++c) v[q][c] = urow[c];
-        } else if (lr == op) {
-#pragma clang loop unroll(full)
-          for (int c = 0; c < NB; ++c) v[q][c] = jrow[c];
-        }
-        if (row > gj && row < n) {
-          const T l = (pv != T(0)) ? v[q][j] / pv : v[q][j];
-          v[q][j] = l;
-#pragma clang loop unroll(full)
-          for (int c = j + 1; c < NB; ++c) v[q][c] -= l * urow[c];
-        }
+#pragma unroll
+      for (int c = jj + 1; c < CH; ++c) {
+        const T uc = s_row[src + c];
+#pragma unroll
+        for (int q = 0; q < R; ++q) v[q][c] -= l[q] * uc;
       }
+#pragma unroll
+      for (int bk = 1; bk < NB / CH; ++bk)
+        if (bk < live) {
+#pragma unroll
+          for (int c = CH * bk; c < CH * bk + CH; ++c) {
+            const T uc = s_row[src + c];
+#pragma unroll
+            for (int q = 0; q < R; ++q) v[q][c] -= l[q] * uc;
+          }
+        }
+    }
+    // rotate each row by one chunk
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      T t[CH];
+#pragma unroll
+      for (int x = 0; x < CH; ++x) t[x] = v[q][x];
+#pragma unroll
+      for (int c = 0; c < NB - CH; ++c) v[q][c] = v[q][c + CH];
+#pragma unroll
+      for (int x = 0; x < CH; ++x) v[q][NB - CH + x] = t[x];
     }
   }
-#pragma clang loop unroll(full)
-  for (int q = 0; q < R; ++q) {
-    const int row = k + tid + NT * q;
-#pragma clang loop unroll(full)
-    for (int c = 0; c < NB; ++c)
-      if (row < n && c < jb) A[row + (int64_t)(k + c) * n] = v[q][c];
-  }
+  if (tid < jb) piv[tid] = piv_r;
+  if (tid == 0 && first_zero && info[i] == 0) info[i] = k + first_zero;
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+    if (lab[q] != NO_ROW) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c < jb) A[lab[q] + (int64_t)c * n] = v[q][c];
+    }
 }
 
 // Interchanges of panel k on every non-panel column; U12 = L11^{-1} A12 right of the panel.
@@ -525,8 +613,9 @@ __global__ __launch_bounds__(256) void k_lu_update(T* __restrict__ Ab, const int
                                                    const int* __restrict__ dim, int k, int inner, int tiles_m,
                                                    int tiles_n) {
   const int tiles = tiles_m * tiles_n;
-  const int i = blockIdx.x / tiles;
-  const int tl = blockIdx.x - i * tiles;
+  const int w = (int)xcd_remap(blockIdx.x, gridDim.x);
+  const int i = w / tiles;
+  const int tl = w - i * tiles;
   const int n = dim[i];
   const int kw = inner ? NB : 2 * NB;
   if (k + kw >= n) return;
@@ -547,10 +636,11 @@ __global__ __launch_bounds__(256) void k_gemm_update(T* __restrict__ Ab, const i
                                                      const int* __restrict__ dim, T* __restrict__ Xb,
                                                      const int64_t* __restrict__ xoff, const int* __restrict__ nrhs,
                                                      int k, int mode, int tiles_n) {
-  // blockIdx.x = tile + tiles_n^2 * matrix; tiles are (ty, tx) with ty fastest
+  // logical index = tile + tiles_n^2 * matrix; tiles are (ty, tx) with ty fastest
   const int tiles = tiles_n * tiles_n;
-  const int i = blockIdx.x / tiles;
-  const int tl = blockIdx.x - i * tiles;
+  const int w = (int)xcd_remap(blockIdx.x, gridDim.x);
+  const int i = w / tiles;
+  const int tl = w - i * tiles;
   const int n = dim[i];
   if (k >= n) return;
   const int jb = min(NB, n - k);
@@ -675,18 +765,42 @@ __global__ void k_build_perm(const int* __restrict__ dim, const int* __restrict_
 
 }  // namespace
 
+// Register panel for the tallest panel of the launch: the smallest workgroup
+// shape (threads x rows per thread) that holds min(rows, register limit) rows.
+template <typename T>
+void launch_panel_rot(const LuBatch& b, T* A, int k, int rows, hipStream_t s) {
+  constexpr int NB = LU_NB;
+#define GDSW_PANEL(NT, R)                                                                                       \
+  if (rows <= NT * R) {                                                                                         \
+    hipLaunchKernelGGL((k_lu_panel_rot<T, NB, NT, R>), dim3(b.count), dim3(NT), 0, s, A, b.off, b.dim, b.piv, \
+                       b.poff, b.info, k);                                                                      \
+    GDSW_LAUNCH_CHECK();                                                                                        \
+    return;                                                                                                     \
+  }
+  GDSW_PANEL(256, 1)
+  GDSW_PANEL(256, 2)
+  GDSW_PANEL(256, 3)
+  GDSW_PANEL(512, 2)
+  GDSW_PANEL(512, 3)
+  if constexpr (sizeof(T) == 4) {
+    GDSW_PANEL(512, 4)
+    GDSW_PANEL(512, 6)
+  }
+#undef GDSW_PANEL
+  throw Error(-1, "panel taller than the register panel");
+}
+
 template <typename T>
 void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
   constexpr int NB = LU_NB;
   auto panel = [&](int k) {
-    if (b.max_n - k > PANEL_REG_ROWS) {
+    const int rows = b.max_n - k;
+    if (rows > panel_reg_rows<T>()) {
       hipLaunchKernelGGL((k_lu_panel<T, NB>), dim3(b.count), dim3(256), 0, s, A, b.off, b.dim, b.piv, b.poff,
                          b.info, k);
       GDSW_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL((k_lu_panel_reg<T, NB, PANEL_REG_R>), dim3(b.count), dim3(512), 0, s, A, b.off, b.dim, b.piv,
-                       b.poff, b.info, k);
-    GDSW_LAUNCH_CHECK();
+    launch_panel_rot<T>(b, A, k, std::min(rows, panel_reg_rows<T>()), s);
   };
   for (int k = 0; k < b.max_n; k += 2 * NB) {
     panel(k);

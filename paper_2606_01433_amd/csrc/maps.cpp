@@ -493,24 +493,76 @@ std::string build_next_mesh(const LevelMesh& mesh, const LevelMaps& m, const int
 
 void coarse_pattern(const LevelMaps& m, std::vector<int64_t>& rowptr, std::vector<int>& col) {
   const int nc = m.n_coarse;
-  std::vector<std::vector<int>> rows(nc);
-  parallel_for(nc, host_threads(), [&](int, int c0, int c1) {
-    for (int c = c0; c < c1; ++c) {
-      std::vector<int>& row = rows[c];
-      for (int64_t k = m.cp_ptr[c]; k < m.cp_ptr[c + 1]; ++k) {
-        const int i = m.cp_part[k];
-        row.insert(row.end(), m.pcols.begin() + m.pc_ptr[i], m.pcols.begin() + m.pc_ptr[i + 1]);
+  const int nthreads = host_threads();
+  // per-thread stamps: column j is already in row c when stamp[j] == c
+  std::vector<std::vector<int>> stamps(nthreads);
+  auto row_walk = [&](int t, int c, auto&& emit) {
+    std::vector<int>& stamp = stamps[t];
+    if (stamp.size() != (size_t)nc) stamp.assign(nc, -1);
+    for (int64_t k = m.cp_ptr[c]; k < m.cp_ptr[c + 1]; ++k) {
+      const int i = m.cp_part[k];
+      for (int64_t q = m.pc_ptr[i]; q < m.pc_ptr[i + 1]; ++q) {
+        const int j = m.pcols[q];
+        if (stamp[j] != c) {
+          stamp[j] = c;
+          emit(j);
+        }
       }
-      std::sort(row.begin(), row.end());
-      row.erase(std::unique(row.begin(), row.end()), row.end());
+    }
+  };
+  rowptr.assign(nc + 1, 0);
+  parallel_for(nc, nthreads, [&](int t, int c0, int c1) {
+    for (int c = c0; c < c1; ++c) {
+      int64_t cnt = 0;
+      row_walk(t, c, [&](int) { ++cnt; });
+      rowptr[c + 1] = cnt;
     }
   });
-  rowptr.assign(nc + 1, 0);
-  for (int c = 0; c < nc; ++c) rowptr[c + 1] = rowptr[c] + (int64_t)rows[c].size();
+  for (int c = 0; c < nc; ++c) rowptr[c + 1] += rowptr[c];
   col.resize(rowptr[nc]);
-  parallel_for(nc, host_threads(), [&](int, int c0, int c1) {
-    for (int c = c0; c < c1; ++c) std::copy(rows[c].begin(), rows[c].end(), col.begin() + rowptr[c]);
+  for (auto& st : stamps) std::fill(st.begin(), st.end(), -1);
+  parallel_for(nc, nthreads, [&](int t, int c0, int c1) {
+    for (int c = c0; c < c1; ++c) {
+      int* out = col.data() + rowptr[c];
+      int64_t q = 0;
+      row_walk(t, c, [&](int j) { out[q++] = j; });
+      std::sort(out, out + q);
+    }
   });
+}
+
+std::string scatter_lists(const LevelMaps& m, int64_t n, bool additive, std::vector<int64_t>& sc_ptr,
+                          std::vector<int>& sc_pos) {
+  const int N = (int)m.dom_ptr.size() - 1;
+  const int64_t total = m.dom_ptr[N];
+  if (additive) {
+    sc_ptr.assign(n + 1, 0);
+    for (int64_t k = 0; k < total; ++k) sc_ptr[m.dom[k] + 1]++;
+    for (int64_t g = 0; g < n; ++g) sc_ptr[g + 1] += sc_ptr[g];
+    sc_pos.resize(total);
+    std::vector<int64_t> fill(sc_ptr.begin(), sc_ptr.end() - 1);
+    for (int64_t k = 0; k < total; ++k) sc_pos[fill[m.dom[k]]++] = (int)k;
+    return "";
+  }
+  // restricted: the one position of g inside its owner's domain
+  sc_ptr.clear();
+  sc_pos.assign(n, -1);
+  const int nthreads = host_threads();
+  std::vector<int64_t> found(nthreads, 0);
+  parallel_for(N, nthreads, [&](int t, int i0, int i1) {
+    for (int i = i0; i < i1; ++i)
+      for (int64_t k = m.dom_ptr[i]; k < m.dom_ptr[i + 1]; ++k) {
+        const int g = m.dom[k];
+        if (m.owner[g] == i) {
+          sc_pos[g] = (int)k;
+          ++found[t];
+        }
+      }
+  });
+  int64_t f = 0;
+  for (int64_t c : found) f += c;
+  if (f != n) return "some dof is not held by its owning part";
+  return "";
 }
 
 }  // namespace gdsw

@@ -85,4 +85,11 @@ std::string build_next_mesh(const LevelMesh& mesh, const LevelMaps& m, const int
 // of the parts that hold column c.
 void coarse_pattern(const LevelMaps& m, std::vector<int64_t>& rowptr, std::vector<int>& col);
 
+// Combination lists of the local solutions: additive lists every position of
+// dof g over all domains (sc_ptr / sc_pos, ascending position); restricted
+// lists only the position inside the owner's domain (sc_pos[g], sc_ptr left
+// empty).  Returns "" or an error text.
+std::string scatter_lists(const LevelMaps& m, int64_t n, bool additive, std::vector<int64_t>& sc_ptr,
+                          std::vector<int>& sc_pos);
+
 }  // namespace gdsw

@@ -41,7 +41,8 @@ class Stats(ctypes.Structure):
                 ("interior_flops", c_dbl * 8), ("nnz", c_i64 * 8), ("ms_maps", c_dbl), ("ms_extract", c_dbl),
                 ("ms_factor", c_dbl), ("ms_basis", c_dbl), ("ms_galerkin", c_dbl), ("ms_coarse", c_dbl),
                 ("ms_total", c_dbl), ("local_solve_launches", c_i64), ("ms_local_solve", c_dbl),
-                ("local_solve_bytes", c_dbl), ("ls_waves", c_i32 * 8)]
+                ("local_solve_bytes", c_dbl), ("ls_waves", c_i32 * 8), ("tl_factor", (c_dbl * 2) * 8),
+                ("tl_basis", (c_dbl * 2) * 8), ("tl_coarsest", c_dbl * 2)]
 
 
 class MapsView(ctypes.Structure):
@@ -285,7 +286,9 @@ class Context:
         out = {}
         for k, t in Stats._fields_:
             v = getattr(s, k)
-            out[k] = list(v) if hasattr(t, "_length_") else v
+            if hasattr(t, "_length_"):
+                v = [list(x) if hasattr(x, "_length_") else x for x in v]
+            out[k] = v
         return out
 
     def close(self):
