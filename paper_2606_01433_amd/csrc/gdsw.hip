@@ -192,8 +192,9 @@ struct gdsw_ctx {
   // event pairs around level-1 local-solve launches (profile = 1)
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  // the coarse chain of the apply runs on `side`, forked from and joined to the caller's stream
-  hipStream_t side = nullptr;
+  // the coarse chain of the apply runs on `side`, forked from and joined to the caller's stream;
+  // during setup `side` factors level 1 and `side2` the deeper levels
+  hipStream_t side = nullptr, side2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // host-to-device uploads run on `up`, which never holds compute work
   hipStream_t up = nullptr;
@@ -222,6 +223,10 @@ struct gdsw_ctx {
     if (side) {
       (void)hipStreamSynchronize(side);
       (void)hipStreamDestroy(side);
+    }
+    if (side2) {
+      (void)hipStreamSynchronize(side2);
+      (void)hipStreamDestroy(side2);
     }
     if (up) {
       (void)hipStreamSynchronize(up);
@@ -485,14 +490,11 @@ void coarsest_inverse(gdsw_ctx* C, const CsrDev& K, hipStream_t s, double** dens
   double* D = A.alloc_n<double>((size_t)n * n);
   GDSW_HIP(hipMemsetAsync(D, 0, (size_t)n * n * sizeof(double), s));
   csr_to_dense(K, D, s);
-  std::vector<int64_t> off0 = {0};
-  std::vector<int> dim0 = {n};
-  int64_t* d_off;
-  int* d_dim;
-  UploadBatch B;
-  B.add(&d_off, off0);
-  B.add(&d_dim, dim0);
-  B.flush(C, s);
+  // a batch of one: offset 0, order n (set on the device, nothing to upload)
+  int64_t* d_off = A.alloc_n<int64_t>(1);
+  int* d_dim = A.alloc_n<int>(1);
+  GDSW_HIP(hipMemsetAsync(d_off, 0, sizeof(int64_t), s));
+  GDSW_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(d_dim), n, 1, s));
   int* piv = A.alloc_n<int>(n);
   int* info = A.alloc_n<int>(1);
   GDSW_HIP(hipMemsetAsync(info, 0, sizeof(int), s));
@@ -623,10 +625,10 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
     return (int)evs.size() - 1;
   };
   const int e_setup = mark(s);
-  // The local factorizations run on the side stream, concurrently with the
-  // basis / Galerkin / coarser-level chain on the caller's stream; level l's
-  // factorization only waits for its operator K_l.
-  hipStream_t fs = C->side;
+  // The local factorizations run on side streams (level 1 on one, deeper
+  // levels on another), concurrently with the basis / Galerkin / coarser-level
+  // chain on the caller's stream; level l's factorization only waits for its
+  // operator K_l.
   std::vector<std::pair<int, int>> ev_factor, ev_basis;
   bool coarsest = false;
   int k_ready = mark(s);                      // K_1 copied
@@ -637,11 +639,15 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
     L.nparts = meshes[l].n_parts;
     L.n = K.n;
     L.K = K;
-    host([&] { build_maps(meshes[l], C->opt.overlap, L.maps); });
+    // the overlapping sets first: the local factorizations start while the
+    // host builds the rest of the level's maps
+    host([&] { build_domains(meshes[l], C->opt.overlap, L.maps); });
+    hipStream_t fs = (l == 0) ? C->side : C->side2;
     GDSW_HIP(hipStreamWaitEvent(fs, evs[k_ready], 0));
     const int e0 = mark(fs);
     factor_level<T>(C, L, fs);
     ev_factor.push_back({e0, mark(fs)});
+    host([&] { build_maps(meshes[l], C->opt.overlap, L.maps); });
     st.n[l] = L.n;
     st.parts[l] = L.nparts;
     st.sum_ni[l] = L.sum_n;
@@ -697,7 +703,8 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
     st.nnz[schwarz] = K.nnz;
     st.factor_flops[schwarz] = (2.0 / 3.0) * K.n * (double)K.n * K.n + 2.0 * K.n * (double)K.n * K.n;
   }
-  GDSW_HIP(hipStreamSynchronize(fs));
+  GDSW_HIP(hipStreamSynchronize(C->side));
+  GDSW_HIP(hipStreamSynchronize(C->side2));
   GDSW_HIP(hipStreamSynchronize(s));
   GDSW_HIP(hipStreamSynchronize(C->up));
   C->release_pinned();
@@ -1092,6 +1099,7 @@ int gdsw_setup(const gdsw_problem* prob, const gdsw_options* opt, void* stream, 
     C->mixed = C->opt.precision == GDSW_MIXED;
     hipStream_t s = static_cast<hipStream_t>(stream);
     GDSW_HIP(hipStreamCreateWithFlags(&C->side, hipStreamNonBlocking));
+    GDSW_HIP(hipStreamCreateWithFlags(&C->side2, hipStreamNonBlocking));
     GDSW_HIP(hipStreamCreateWithFlags(&C->up, hipStreamNonBlocking));
     GDSW_HIP(hipEventCreateWithFlags(&C->ev_up, hipEventDisableTiming));
     GDSW_HIP(hipEventCreateWithFlags(&C->ev_fork, hipEventDisableTiming));

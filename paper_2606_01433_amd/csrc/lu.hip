@@ -566,31 +566,38 @@ __global__ __launch_bounds__(64) void k_lu_outer_swap_left(T* __restrict__ Ab, c
 }
 
 // Columns right of outer step k: all of its interchanges, then
-// U12 = L11^{-1} A12 with the 2NB x 2NB unit lower L11.
+// U12 = L11^{-1} A12 with the 2NB x 2NB unit lower L11.  One thread per
+// column, TRSM_COLS columns per workgroup; L11 and the step's pivots are staged
+// in LDS once per workgroup.
+constexpr int TRSM_COLS = 128;
 template <typename T, int NB>
-__global__ __launch_bounds__(64) void k_lu_outer_swap_trsm(T* __restrict__ Ab, const int64_t* __restrict__ off,
-                                                           const int* __restrict__ dim, const int* __restrict__ pivb,
-                                                           const int64_t* __restrict__ poff, int k) {
+__global__ __launch_bounds__(TRSM_COLS) void k_lu_outer_swap_trsm(T* __restrict__ Ab, const int64_t* __restrict__ off,
+                                                                  const int* __restrict__ dim,
+                                                                  const int* __restrict__ pivb,
+                                                                  const int64_t* __restrict__ poff, int k) {
   constexpr int KW = 2 * NB;
   const int i = blockIdx.x;
   const int n = dim[i];
-  if (k + KW >= n) return;                  // no trailing columns
+  const int cfirst = k + KW + blockIdx.y * TRSM_COLS;
+  if (cfirst >= n) return;                  // no trailing columns in this block
   T* A = Ab + off[i];
   const int* piv = pivb + poff[i];
   __shared__ T L11[KW * KW];
-  for (int t = threadIdx.x; t < KW * KW; t += 64) {
+  __shared__ int sp[KW];
+  for (int t = threadIdx.x; t < KW * KW; t += TRSM_COLS) {
     const int r = t % KW, c = t / KW;
     L11[t] = A[(k + r) + (int64_t)(k + c) * n];
   }
+  if (threadIdx.x < KW) sp[threadIdx.x] = piv[k + threadIdx.x];
   __syncthreads();
-  const int c = k + KW + blockIdx.y * 64 + threadIdx.x;
+  const int c = cfirst + (int)threadIdx.x;
   if (c >= n) return;
   T* col = A + (int64_t)c * n;
-  for (int j = k; j < k + KW; ++j) {
-    const int p = piv[j];
-    if (p != j) {
-      const T t = col[j];
-      col[j] = col[p];
+  for (int j = 0; j < KW; ++j) {
+    const int p = sp[j];
+    if (p != k + j) {
+      const T t = col[k + j];
+      col[k + j] = col[p];
       col[p] = t;
     }
   }
@@ -818,8 +825,8 @@ void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
     GDSW_LAUNCH_CHECK();
     const int rest = b.max_n - k - 2 * NB;
     if (rest > 0) {
-      hipLaunchKernelGGL((k_lu_outer_swap_trsm<T, NB>), dim3(b.count, blocks_for(rest, 64)), dim3(64), 0, s, A, b.off,
-                         b.dim, b.piv, b.poff, k);
+      hipLaunchKernelGGL((k_lu_outer_swap_trsm<T, NB>), dim3(b.count, blocks_for(rest, TRSM_COLS)), dim3(TRSM_COLS), 0,
+                         s, A, b.off, b.dim, b.piv, b.poff, k);
       GDSW_LAUNCH_CHECK();
       const int t = (int)blocks_for(rest, TILE);
       hipLaunchKernelGGL((k_lu_update<T, NB>), dim3(b.count * t * t), dim3(256), 0, s, A, b.off, b.dim, k, 0, t, t);

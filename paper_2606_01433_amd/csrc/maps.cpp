@@ -188,7 +188,7 @@ std::string build_level1_mesh(int64_t n, int n_nodes, const int* node_dof, int n
   return "";
 }
 
-void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m) {
+void build_domains(const LevelMesh& mesh, int delta, LevelMaps& m) {
   const int N = mesh.n_parts;
   const int nn = mesh.n_nodes;
   std::vector<int64_t> ne_ptr;
@@ -199,6 +199,81 @@ void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m) {
   m.s.resize(ne.size());
   for (size_t k = 0; k < ne.size(); ++k) m.s[k] = mesh.elem_part[ne[k]];
   sort_unique_segments(m.s_ptr, m.s);
+  // owning part of every dof (restricted combination): first part of S(v), the element's part for pressure
+  m.owner.assign(mesh.n_dof, -1);
+  for (int v = 0; v < nn; ++v) {
+    if (m.s_ptr[v + 1] == m.s_ptr[v]) continue;
+    const int own = m.s[m.s_ptr[v]];
+    for (int d = 0; d < 3; ++d) {
+      const int g = mesh.node_dof[3 * v + d];
+      if (g >= 0) m.owner[g] = own;
+    }
+  }
+  for (int e = 0; e < mesh.n_elem; ++e)
+    for (int q = 0; q < 4; ++q) {
+      const int g = mesh.elem_pdof[4 * e + q];
+      if (g >= 0) m.owner[g] = mesh.elem_part[e];
+    }
+  // D_i: nodes of the part's elements grown by delta node-graph layers, plus its pressure dofs
+  std::vector<std::vector<int>> part_elems(N);
+  for (int e = 0; e < mesh.n_elem; ++e) part_elems[mesh.elem_part[e]].push_back(e);
+  std::vector<std::vector<int>> dofs(N);
+  const int nthreads = host_threads();
+  std::vector<std::vector<int>> stamps(nthreads);
+  parallel_for(N, nthreads, [&](int t, int i0, int i1) {
+    std::vector<int>& stamp = stamps[t];
+    if (stamp.empty()) stamp.assign(nn, -1);
+    std::vector<int> layer, frontier, next;
+    for (int i = i0; i < i1; ++i) {
+      std::vector<int>& o = dofs[i];
+      layer.clear();
+      for (int e : part_elems[i])
+        for (int64_t k = mesh.en_ptr[e]; k < mesh.en_ptr[e + 1]; ++k) {
+          const int v = mesh.en[k];
+          if (stamp[v] != i) {
+            stamp[v] = i;
+            layer.push_back(v);
+          }
+        }
+      frontier.assign(layer.begin(), layer.end());
+      for (int l = 0; l < delta; ++l) {
+        next.clear();
+        for (int u : frontier)
+          for (int64_t k = mesh.adj_ptr[u]; k < mesh.adj_ptr[u + 1]; ++k) {
+            const int w = mesh.adj[k];
+            if (stamp[w] != i) {
+              stamp[w] = i;
+              next.push_back(w);
+            }
+          }
+        layer.insert(layer.end(), next.begin(), next.end());
+        frontier.swap(next);
+      }
+      for (int v : layer)
+        for (int d = 0; d < 3; ++d) {
+          const int g = mesh.node_dof[3 * v + d];
+          if (g >= 0) o.push_back(g);
+        }
+      for (int e : part_elems[i])
+        for (int q = 0; q < 4; ++q) {
+          const int g = mesh.elem_pdof[4 * e + q];
+          if (g >= 0) o.push_back(g);
+        }
+      std::sort(o.begin(), o.end());
+    }
+  });
+  m.dom_ptr.assign(N + 1, 0);
+  for (int i = 0; i < N; ++i) m.dom_ptr[i + 1] = m.dom_ptr[i] + (int64_t)dofs[i].size();
+  m.dom.resize(m.dom_ptr[N]);
+  parallel_for(N, nthreads, [&](int, int i0, int i1) {
+    for (int i = i0; i < i1; ++i) std::copy(dofs[i].begin(), dofs[i].end(), m.dom.begin() + m.dom_ptr[i]);
+  });
+}
+
+void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m) {
+  const int N = mesh.n_parts;
+  const int nn = mesh.n_nodes;
+  if ((int)m.dom_ptr.size() != N + 1) build_domains(mesh, delta, m);
   auto nS = [&](int v) { return m.s_ptr[v + 1] - m.s_ptr[v]; };
   auto has_free = [&](int v) {
     return mesh.node_dof[3 * v] >= 0 || mesh.node_dof[3 * v + 1] >= 0 || mesh.node_dof[3 * v + 2] >= 0;
@@ -288,30 +363,21 @@ void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m) {
   m.n_coarse = (int)m.col_entity.size();
   // per-dof tables
   const int n = mesh.n_dof;
-  m.owner.assign(n, -1);
   m.dof_gcol.assign(n, -1);
   m.dof_ipart.assign(n, -1);
   m.dof_irow.assign(n, -1);
-  for (int v = 0; v < nn; ++v) {
-    if (nS(v) == 0) continue;
-    const int own = m.s[m.s_ptr[v]];
+  for (int v : m.gamma_nodes)
     for (int d = 0; d < 3; ++d) {
       const int g = mesh.node_dof[3 * v + d];
-      if (g < 0) continue;
-      m.owner[g] = own;
-      if (is_gamma[v]) m.dof_gcol[g] = m.ent_col[(size_t)m.node_ent[v] * 3 + d];
+      if (g >= 0) m.dof_gcol[g] = m.ent_col[(size_t)m.node_ent[v] * 3 + d];
     }
+  for (int e = 0; e < mesh.n_elem; ++e) {
+    const int g = mesh.elem_pdof[4 * e];
+    if (g >= 0) m.dof_gcol[g] = m.part_col[mesh.elem_part[e]];
   }
-  for (int e = 0; e < mesh.n_elem; ++e)
-    for (int q = 0; q < 4; ++q) {
-      const int g = mesh.elem_pdof[4 * e + q];
-      if (g < 0) continue;
-      m.owner[g] = mesh.elem_part[e];
-      if (q == 0) m.dof_gcol[g] = m.part_col[mesh.elem_part[e]];
-    }
-  // overlapping and interior sets, part by part (in parallel; concatenated in part order)
+  // interior sets and coarse columns, part by part (in parallel; concatenated in part order)
   struct PartOut {
-    std::vector<int> dofs, idofs, pcols, z_lc, z_dof;
+    std::vector<int> idofs, pcols, z_lc, z_dof;
   };
   std::vector<PartOut> outp(N);
   const int nthreads = host_threads();
@@ -319,7 +385,7 @@ void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m) {
   parallel_for(N, nthreads, [&](int t, int i0, int i1) {
     std::vector<int>& stamp = stamps[t];
     if (stamp.empty()) stamp.assign(nn, -1);
-    std::vector<int> layer, frontier, next;
+    std::vector<int> layer;
     std::vector<std::pair<int, int>> zs;
     for (int i = i0; i < i1; ++i) {
       PartOut& o = outp[i];
@@ -333,28 +399,7 @@ void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m) {
           }
         }
       const size_t n_closure = layer.size();
-      frontier.assign(layer.begin(), layer.end());
-      for (int l = 0; l < delta; ++l) {
-        next.clear();
-        for (int u : frontier)
-          for (int64_t k = mesh.adj_ptr[u]; k < mesh.adj_ptr[u + 1]; ++k) {
-            const int w = mesh.adj[k];
-            if (stamp[w] != i) {
-              stamp[w] = i;
-              next.push_back(w);
-            }
-          }
-        layer.insert(layer.end(), next.begin(), next.end());
-        frontier.swap(next);
-      }
       zs.clear();
-      for (size_t k = 0; k < layer.size(); ++k) {
-        const int v = layer[k];
-        for (int d = 0; d < 3; ++d) {
-          const int g = mesh.node_dof[3 * v + d];
-          if (g >= 0) o.dofs.push_back(g);
-        }
-      }
       for (size_t k = 0; k < n_closure; ++k) {
         const int v = layer[k];
         const bool interior = nS(v) == 1 && m.s[m.s_ptr[v]] == i;
@@ -369,11 +414,9 @@ void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m) {
         for (int q = 0; q < 4; ++q) {
           const int g = mesh.elem_pdof[4 * e + q];
           if (g < 0) continue;
-          o.dofs.push_back(g);
           if (q > 0) o.idofs.push_back(g);
           else zs.push_back({m.dof_gcol[g], g});
         }
-      std::sort(o.dofs.begin(), o.dofs.end());
       std::sort(o.idofs.begin(), o.idofs.end());
       for (size_t a = 0; a < o.idofs.size(); ++a) {   // interior dofs belong to one part only
         m.dof_ipart[o.idofs[a]] = i;
@@ -392,17 +435,14 @@ void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m) {
       }
     }
   });
-  m.dom_ptr.assign(N + 1, 0);
   m.int_ptr.assign(N + 1, 0);
   m.pc_ptr.assign(N + 1, 0);
   m.z_ptr.assign(N + 1, 0);
   for (int i = 0; i < N; ++i) {
-    m.dom_ptr[i + 1] = m.dom_ptr[i] + (int64_t)outp[i].dofs.size();
     m.int_ptr[i + 1] = m.int_ptr[i] + (int64_t)outp[i].idofs.size();
     m.pc_ptr[i + 1] = m.pc_ptr[i] + (int64_t)outp[i].pcols.size();
     m.z_ptr[i + 1] = m.z_ptr[i] + (int64_t)outp[i].z_dof.size();
   }
-  m.dom.resize(m.dom_ptr[N]);
   m.inter.resize(m.int_ptr[N]);
   m.pcols.resize(m.pc_ptr[N]);
   m.z_dof.resize(m.z_ptr[N]);
@@ -410,7 +450,6 @@ void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m) {
   parallel_for(N, nthreads, [&](int, int i0, int i1) {
     for (int i = i0; i < i1; ++i) {
       const PartOut& o = outp[i];
-      std::copy(o.dofs.begin(), o.dofs.end(), m.dom.begin() + m.dom_ptr[i]);
       std::copy(o.idofs.begin(), o.idofs.end(), m.inter.begin() + m.int_ptr[i]);
       std::copy(o.pcols.begin(), o.pcols.end(), m.pcols.begin() + m.pc_ptr[i]);
       std::copy(o.z_dof.begin(), o.z_dof.end(), m.z_dof.begin() + m.z_ptr[i]);

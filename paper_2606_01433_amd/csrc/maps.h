@@ -75,6 +75,11 @@ std::string build_level1_mesh(int64_t n, int n_nodes, const int* node_dof, int n
                               const int* elem_node, const int* elem_pdof, const int* elem_part,
                               int n_parts, LevelMesh& out);
 
+// S(v), the owning part of every dof and the overlapping sets D_i (dom_ptr /
+// dom) only: everything the local factorizations need.
+void build_domains(const LevelMesh& mesh, int delta, LevelMaps& m);
+
+// All maps of the level; reuses D_i (and S, owner) when build_domains ran on m.
 void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m);
 
 // Mesh of the next level: entities become nodes, parts become elements.
