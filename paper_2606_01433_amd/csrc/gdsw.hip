@@ -317,7 +317,12 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
   std::vector<int> sc_pos;
   const std::string err = scatter_lists(m, L.n, C->opt.combine == GDSW_COMBINE_ADDITIVE, sc_ptr, sc_pos);
   if (!err.empty()) throw Error(GDSW_EINVAL, err);
+  LuTiles tiles;
+  tiles.build(L.dims.data(), N);
+  int64_t *d_tiles_outer, *d_tiles_inner;
   UploadBatch B;
+  B.add(&d_tiles_outer, tiles.outer);
+  B.add(&d_tiles_inner, tiles.inner);
   B.add(&L.dom_ptr, m.dom_ptr);
   B.add(&L.dom, m.dom);
   B.add(&L.blk_off, L.blk_off_h);
@@ -342,6 +347,10 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
   b.piv = L.piv;
   b.poff = L.dom_ptr;
   b.info = L.info;
+  b.tiles_outer = d_tiles_outer;
+  b.tiles_inner = d_tiles_inner;
+  b.total_outer = tiles.total_outer.data();
+  b.total_inner = tiles.total_inner.data();
   lu_batched<T>(b, blocks, s);
   L.perm = A.alloc_n<int>((size_t)L.sum_n);
   lu_build_perm(b, L.perm, s);
@@ -416,6 +425,11 @@ CsrDev coarse_level(gdsw_ctx* C, Level& L, hipStream_t s, std::vector<int64_t>& 
   B.add(&d_c_off, c_off);
   B.add(&d_ni, ni);
   B.add(&d_mi, mi);
+  LuTiles itiles;
+  itiles.build(ni.data(), N);
+  int64_t *d_itiles_outer, *d_itiles_inner;
+  B.add(&d_itiles_outer, itiles.outer);
+  B.add(&d_itiles_inner, itiles.inner);
   B.flush(C, s);
   C->stats.ms_extract += now_ms() - th;
   T* aii = A.alloc_n<T>((size_t)aii_tot);
@@ -438,6 +452,10 @@ CsrDev coarse_level(gdsw_ctx* C, Level& L, hipStream_t s, std::vector<int64_t>& 
   b.piv = ipiv;
   b.poff = L.int_ptr;
   b.info = L.iinfo;
+  b.tiles_outer = d_itiles_outer;
+  b.tiles_inner = d_itiles_inner;
+  b.total_outer = itiles.total_outer.data();
+  b.total_inner = itiles.total_inner.data();
   lu_batched<T>(b, aii, s);
   T* phi;
   if (sizeof(T) == sizeof(double)) {
@@ -508,12 +526,18 @@ void coarsest_inverse(gdsw_ctx* C, const CsrDev& K, hipStream_t s, double** dens
   b.info = info;
   lu_batched<double>(b, D, s);
   double* X = A.alloc_n<double>((size_t)n * n);
-  set_identity<double>(X, n, s);
-  lu_solve_batched<double>(b, D, X, d_off, d_dim, n, s);
-  // keep the inverse transposed, so the per-apply GEMV reads rows contiguously (X becomes scratch)
-  transpose_square(n, X, D, s);
-  C->ainv = D;
-  D = X;
+  // the inverse is kept by rows, so the per-apply GEMV reads rows contiguously
+  int* perm = A.alloc_n<int>(n);
+  lu_build_perm(b, perm, s);
+  if (lu_inverse_transposed(D, perm, X, n, s)) {
+    C->ainv = X;                 // D (the factors) becomes scratch
+  } else {
+    set_identity<double>(X, n, s);
+    lu_solve_batched<double>(b, D, X, d_off, d_dim, n, s);
+    transpose_square(n, X, D, s);
+    C->ainv = D;
+    D = X;
+  }
   *dense_out = D;
   *info_out = info;
 }

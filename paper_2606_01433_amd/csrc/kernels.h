@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace gdsw {
 
@@ -17,6 +18,21 @@ struct LuBatch {
   int* piv = nullptr;              // pivots, matrix i at poff[i]
   const int64_t* poff = nullptr;
   int* info = nullptr;             // first zero pivot (1-based) or 0
+  // Optional compact update grids (see LuTiles): per outer step s, prefix sums
+  // over the matrices of their 64 x 64 update tiles (device, [steps][count+1]),
+  // and the per-step totals (host).  Without them every matrix gets the tiles
+  // of the largest one.
+  const int64_t* tiles_outer = nullptr;
+  const int64_t* tiles_inner = nullptr;
+  const int64_t* total_outer = nullptr;
+  const int64_t* total_inner = nullptr;
+};
+
+// Host-built update tile tables of a batch with orders dims[0..count).
+struct LuTiles {
+  std::vector<int64_t> outer, inner;               // [steps][count+1] prefix sums
+  std::vector<int64_t> total_outer, total_inner;   // [steps]
+  void build(const int* dims, int count);
 };
 
 template <typename T> void lu_batched(const LuBatch& b, T* A, hipStream_t s);
@@ -24,6 +40,10 @@ template <typename T>
 void lu_solve_batched(const LuBatch& b, const T* A, T* X, const int64_t* xoff, const int* nrhs, int max_rhs,
                       hipStream_t s);
 void lu_build_perm(const LuBatch& b, int* perm, hipStream_t s);
+// A^{-1} of one LU-factored matrix of order n <= 4096 from its factors and row
+// permutation (perm[r] = original row at position r), stored by rows:
+// out[c + r n] = (A^{-1})[r][c].  Returns false (nothing launched) for larger n.
+bool lu_inverse_transposed(const double* LU, const int* perm, double* out, int n, hipStream_t s);
 
 // ---- setup ----------------------------------------------------------------
 struct CsrDev {

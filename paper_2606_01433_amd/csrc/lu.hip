@@ -16,6 +16,8 @@
 //   outer  : the step's interchanges on all other columns, U12 = L11^{-1} A12
 //            (one thread per column), A22 -= L21 U12 with MFMA (16x16x4, FP64
 //            or FP32), 64x64 tiles, inner dimension 2*NB.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -43,8 +45,8 @@ template <> struct Mfma<float> {
 };
 
 constexpr int TILE = 64;
-// Tallest panel held in registers: 512 threads x 3 rows (FP64) or x 6 rows (FP32).
-template <typename T> constexpr int panel_reg_rows() { return sizeof(T) == 8 ? 512 * 3 : 512 * 6; }
+// Tallest panel held in registers: 1024 threads x 2 rows (FP64) or 512 x 6 (FP32).
+template <typename T> constexpr int panel_reg_rows() { return sizeof(T) == 8 ? 1024 * 2 : 512 * 6; }
 
 // C[M x N] -= A[M x K] * B[K x N] on the 64x64 tile (ty, tx); K <= KMAX.
 // Column-major operands.  Four waves, each owning a 32x32 quarter computed as
@@ -618,11 +620,17 @@ __global__ __launch_bounds__(TRSM_COLS) void k_lu_outer_swap_trsm(T* __restrict_
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void k_lu_update(T* __restrict__ Ab, const int64_t* __restrict__ off,
                                                    const int* __restrict__ dim, int k, int inner, int tiles_m,
-                                                   int tiles_n) {
-  const int tiles = tiles_m * tiles_n;
+                                                   int tiles_n, const int64_t* __restrict__ tab, int count) {
   const int w = (int)xcd_remap(blockIdx.x, gridDim.x);
-  const int i = w / tiles;
-  const int tl = w - i * tiles;
+  int i, tl;
+  if (tab) {                                // compact grid: tab[i] = first tile of matrix i
+    i = segment_of(tab, count, w);
+    tl = w - (int)tab[i];
+  } else {
+    const int tiles = tiles_m * tiles_n;
+    i = w / tiles;
+    tl = w - i * tiles;
+  }
   const int n = dim[i];
   const int kw = inner ? NB : 2 * NB;
   if (k + kw >= n) return;
@@ -630,7 +638,8 @@ __global__ __launch_bounds__(256) void k_lu_update(T* __restrict__ Ab, const int
   const int c0 = inner ? k + NB : k + 2 * NB;
   const int c1 = inner ? min(n, k + 2 * NB) : n;
   const int M = n - r0, N = c1 - c0;
-  const int ty = tl % tiles_m, tx = tl / tiles_m;
+  const int tm = tab ? (M + TILE - 1) / TILE : tiles_m;
+  const int ty = tl % tm, tx = tl / tm;
   if (ty * TILE >= M || tx * TILE >= N) return;
   T* A = Ab + off[i];
   gemm_sub_tile_direct<T, 2 * NB>(A + r0 + (int64_t)c0 * n, n, A + r0 + (int64_t)k * n, n, A + k + (int64_t)c0 * n, n,
@@ -751,22 +760,168 @@ __global__ __launch_bounds__(64) void k_getrs_diag(const T* __restrict__ Ab, con
     if (r < jb) col[r] = x[r];
 }
 
-template <typename T>
-__global__ void k_build_perm(const int* __restrict__ dim, const int* __restrict__ pivb,
-                             const int64_t* __restrict__ poff, int* __restrict__ perm, int nbatch) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nbatch) return;
+// perm[r] = original row at position r after the interchanges piv[0..n) of
+// matrix blockIdx.x, applied in order.  The permutation lives in LDS while one
+// thread applies the interchanges (orders up to PERM_LDS; longer ones in global
+// memory).
+constexpr int PERM_LDS = 4096;
+__global__ __launch_bounds__(256) void k_build_perm(const int* __restrict__ dim, const int* __restrict__ pivb,
+                                                    const int64_t* __restrict__ poff, int* __restrict__ perm) {
+  __shared__ int sp[PERM_LDS];
+  const int i = blockIdx.x;
   const int n = dim[i];
   const int* piv = pivb + poff[i];
   int* p = perm + poff[i];
-  for (int a = 0; a < n; ++a) p[a] = a;
-  for (int j = 0; j < n; ++j) {
-    const int q = piv[j];
-    if (q != j) {
-      const int t = p[j];
-      p[j] = p[q];
-      p[q] = t;
+  if (n > PERM_LDS) {
+    if (threadIdx.x == 0) {
+      for (int a = 0; a < n; ++a) p[a] = a;
+      for (int j = 0; j < n; ++j) {
+        const int q = piv[j];
+        if (q != j) {
+          const int t = p[j];
+          p[j] = p[q];
+          p[q] = t;
+        }
+      }
     }
+    return;
+  }
+  for (int a = threadIdx.x; a < n; a += blockDim.x) sp[a] = a;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int j = 0; j < n; ++j) {
+      const int q = piv[j];
+      if (q != j) {
+        const int t = sp[j];
+        sp[j] = sp[q];
+        sp[q] = t;
+      }
+    }
+  __syncthreads();
+  for (int a = threadIdx.x; a < n; a += blockDim.x) p[a] = sp[a];
+}
+
+// Inverse of one LU-factored matrix (P A = L U) with the solution resident in
+// registers: workgroup b owns right-hand-side columns [NC b, NC b + NC) of
+// P I, thread t holds rows t + 512 q (q < R) of them through the forward sweep
+// with unit L and the backward sweep with U, in 32-row diagonal blocks.  Per
+// block the owners put its rows into LDS, the 32 x 32 triangle is solved with
+// one 32-lane group per column (lane i holds row i; step j broadcasts lane j
+// by shuffle), and every thread updates its own rows below (forward) or above
+// (backward) with VALU FMAs, all loads of a row issued first.  The result is stored transposed:
+// out[c + r n] = (A^{-1})[r][c], i.e. A^{-1} by rows.
+template <typename T, int R, int NC>
+__global__ __launch_bounds__(512) void k_inverse_resident(const T* __restrict__ A, const int* __restrict__ perm,
+                                                          T* __restrict__ out, int n) {
+  constexpr int NT = 512, KB = 32;
+  __shared__ T sX[KB][NC];
+  __shared__ T sD[KB][KB + 1];
+  const int tid = threadIdx.x;
+  const int c0 = blockIdx.x * NC;
+  T x[R][NC];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int r = tid + NT * q;
+    const int pr = (r < n) ? perm[r] : -1;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) x[q][c] = (pr == c0 + c) ? T(1) : T(0);
+  }
+  // forward: L Y = P I
+  for (int kb = 0; kb < n; kb += KB) {
+    const int kw = min(KB, n - kb);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int r = tid + NT * q;
+      if (r >= kb && r < kb + kw)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sX[r - kb][c] = x[q][c];
+    }
+    for (int e = tid; e < kw * kw; e += NT) {
+      const int i = e % kw, j = e / kw;
+      sD[i][j] = A[(kb + i) + (int64_t)(kb + j) * n];
+    }
+    __syncthreads();
+    if (tid < 32 * NC) {                    // lane group of 32: row i of column c
+      const int i = tid & 31, c = tid >> 5, base = tid & 32;
+      T y = (i < kw) ? sX[i][c] : T(0);
+      for (int j = 0; j < kw; ++j) {
+        const T yj = __shfl(y, base + j, WAVE);
+        if (i > j) y -= sD[i][j] * yj;
+      }
+      if (i < kw) sX[i][c] = y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int r = tid + NT * q;
+      if (r >= kb && r < kb + kw) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x[q][c] = sX[r - kb][c];
+      } else if (r >= kb + kw && r < n) {
+        T lv[KB];                           // all loads of the row issued before the FMAs
+#pragma unroll
+        for (int j = 0; j < KB; ++j) lv[j] = (j < kw) ? A[r + (int64_t)(kb + j) * n] : T(0);
+#pragma unroll
+        for (int j = 0; j < KB; ++j)
+          if (j < kw)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) x[q][c] -= lv[j] * sX[j][c];
+      }
+    }
+    __syncthreads();
+  }
+  // backward: U X = Y
+  for (int kb = ((n - 1) / KB) * KB; kb >= 0; kb -= KB) {
+    const int kw = min(KB, n - kb);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int r = tid + NT * q;
+      if (r >= kb && r < kb + kw)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sX[r - kb][c] = x[q][c];
+    }
+    for (int e = tid; e < kw * kw; e += NT) {
+      const int i = e % kw, j = e / kw;
+      sD[i][j] = A[(kb + i) + (int64_t)(kb + j) * n];
+    }
+    __syncthreads();
+    if (tid < 32 * NC) {
+      const int i = tid & 31, c = tid >> 5, base = tid & 32;
+      T y = (i < kw) ? sX[i][c] : T(0);
+      for (int j = kw - 1; j >= 0; --j) {
+        if (i == j) y = y / sD[j][j];
+        const T yj = __shfl(y, base + j, WAVE);
+        if (i < j) y -= sD[i][j] * yj;
+      }
+      if (i < kw) sX[i][c] = y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int r = tid + NT * q;
+      if (r >= kb && r < kb + kw) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x[q][c] = sX[r - kb][c];
+      } else if (r < kb) {
+        T uv[KB];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) uv[j] = (j < kw) ? A[r + (int64_t)(kb + j) * n] : T(0);
+#pragma unroll
+        for (int j = 0; j < KB; ++j)
+          if (j < kw)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) x[q][c] -= uv[j] * sX[j][c];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int r = tid + NT * q;
+    if (r < n)
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (c0 + c < n) out[(c0 + c) + (int64_t)r * n] = x[q][c];
   }
 }
 
@@ -789,12 +944,40 @@ void launch_panel_rot(const LuBatch& b, T* A, int k, int rows, hipStream_t s) {
   GDSW_PANEL(256, 3)
   GDSW_PANEL(512, 2)
   GDSW_PANEL(512, 3)
+  if constexpr (sizeof(T) == 8) {
+    GDSW_PANEL(1024, 2)
+  }
   if constexpr (sizeof(T) == 4) {
     GDSW_PANEL(512, 4)
     GDSW_PANEL(512, 6)
   }
 #undef GDSW_PANEL
   throw Error(-1, "panel taller than the register panel");
+}
+
+void LuTiles::build(const int* dims, int count) {
+  constexpr int NB = LU_NB;
+  int max_n = 0;
+  for (int i = 0; i < count; ++i) max_n = std::max(max_n, dims[i]);
+  const int steps = (max_n + 2 * NB - 1) / (2 * NB);
+  outer.assign((size_t)steps * (count + 1), 0);
+  inner.assign((size_t)steps * (count + 1), 0);
+  total_outer.assign(steps, 0);
+  total_inner.assign(steps, 0);
+  for (int st = 0; st < steps; ++st) {
+    const int k = st * 2 * NB;
+    int64_t* po = outer.data() + (size_t)st * (count + 1);
+    int64_t* pi = inner.data() + (size_t)st * (count + 1);
+    for (int i = 0; i < count; ++i) {
+      const int mo = dims[i] - k - 2 * NB, mi = dims[i] - k - NB;
+      const int64_t to = mo > 0 ? (int64_t)((mo + TILE - 1) / TILE) * ((mo + TILE - 1) / TILE) : 0;
+      const int64_t ti = mi > 0 ? (int64_t)((mi + TILE - 1) / TILE) : 0;
+      po[i + 1] = po[i] + to;
+      pi[i + 1] = pi[i] + ti;
+    }
+    total_outer[st] = po[count];
+    total_inner[st] = pi[count];
+  }
 }
 
 template <typename T>
@@ -816,8 +999,13 @@ void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
                          k);
       GDSW_LAUNCH_CHECK();
       const int tm = (int)blocks_for(b.max_n - k - NB, TILE);
-      hipLaunchKernelGGL((k_lu_update<T, NB>), dim3(b.count * tm), dim3(256), 0, s, A, b.off, b.dim, k, 1, tm, 1);
-      GDSW_LAUNCH_CHECK();
+      const int st = k / (2 * NB);
+      const int64_t grid = b.tiles_inner ? b.total_inner[st] : (int64_t)b.count * tm;
+      if (grid > 0) {
+        hipLaunchKernelGGL((k_lu_update<T, NB>), dim3((unsigned)grid), dim3(256), 0, s, A, b.off, b.dim, k, 1, tm, 1,
+                           b.tiles_inner ? b.tiles_inner + (size_t)st * (b.count + 1) : nullptr, b.count);
+        GDSW_LAUNCH_CHECK();
+      }
       panel(k + NB);
     }
     hipLaunchKernelGGL((k_lu_outer_swap_left<T, NB>), dim3(b.count, blocks_for(k + NB, 64)), dim3(64), 0, s, A, b.off,
@@ -829,8 +1017,13 @@ void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
                          s, A, b.off, b.dim, b.piv, b.poff, k);
       GDSW_LAUNCH_CHECK();
       const int t = (int)blocks_for(rest, TILE);
-      hipLaunchKernelGGL((k_lu_update<T, NB>), dim3(b.count * t * t), dim3(256), 0, s, A, b.off, b.dim, k, 0, t, t);
-      GDSW_LAUNCH_CHECK();
+      const int st = k / (2 * NB);
+      const int64_t grid = b.tiles_outer ? b.total_outer[st] : (int64_t)b.count * t * t;
+      if (grid > 0) {
+        hipLaunchKernelGGL((k_lu_update<T, NB>), dim3((unsigned)grid), dim3(256), 0, s, A, b.off, b.dim, k, 0, t, t,
+                           b.tiles_outer ? b.tiles_outer + (size_t)st * (b.count + 1) : nullptr, b.count);
+        GDSW_LAUNCH_CHECK();
+      }
     }
   }
 }
@@ -869,9 +1062,25 @@ void lu_solve_batched(const LuBatch& b, const T* A, T* X, const int64_t* xoff, c
   }
 }
 
+bool lu_inverse_transposed(const double* LU, const int* perm, double* out, int n, hipStream_t s) {
+  constexpr int NC = 8;
+  const unsigned grid = blocks_for(n, NC);
+#define GDSW_INV(R)                                                                                       \
+  if (n <= 512 * R) {                                                                                     \
+    hipLaunchKernelGGL((k_inverse_resident<double, R, NC>), dim3(grid), dim3(512), 0, s, LU, perm, out, n); \
+    GDSW_LAUNCH_CHECK();                                                                                  \
+    return true;                                                                                          \
+  }
+  GDSW_INV(1)
+  GDSW_INV(2)
+  GDSW_INV(4)
+  GDSW_INV(8)
+#undef GDSW_INV
+  return false;
+}
+
 void lu_build_perm(const LuBatch& b, int* perm, hipStream_t s) {
-  hipLaunchKernelGGL((k_build_perm<double>), dim3(blocks_for(b.count, 64)), dim3(64), 0, s, b.dim, b.piv, b.poff,
-                     perm, b.count);
+  hipLaunchKernelGGL(k_build_perm, dim3(b.count), dim3(256), 0, s, b.dim, b.piv, b.poff, perm);
   GDSW_LAUNCH_CHECK();
 }
 
