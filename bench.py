@@ -216,7 +216,12 @@ def main():
                    "ms_setup": st0["ms_total"], "ms_solve": infos[-1]["ms_total"],
                    "ms_setup_phases": {"host_maps": st0["ms_maps"], "host_prep": st0["ms_extract"],
                                        "factor": st0["ms_factor"],
-                                       "basis_galerkin": st0["ms_basis"], "coarsest": st0["ms_coarse"]}},
+                                       "basis_galerkin": st0["ms_basis"], "coarsest": st0["ms_coarse"]},
+                   "setup_timeline_ms": {
+                       "note": "GPU events, ms after the setup's first event: [begin, end]",
+                       "factor": [[round(a, 2), round(b, 2)] for a, b in st0["tl_factor"][:st0["levels"] - 1]],
+                       "basis_galerkin": [[round(a, 2), round(b, 2)] for a, b in st0["tl_basis"][:st0["levels"] - 1]],
+                       "coarsest": [round(x, 2) for x in st0["tl_coarsest"]]}},
         "roofline": {"kernel": "k_local_solve (level-1 batched pivoted LU forward/backward substitution)",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
