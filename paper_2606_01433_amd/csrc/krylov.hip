@@ -12,12 +12,33 @@ namespace {
 constexpr int DOT_BLOCK_ROWS = 512;
 constexpr int DOT_MAXC = 32;
 
+// One wavefront per row; lane l sums entries l, l + 64, ... in that order, then
+// a fixed butterfly.  Rows of up to 256 entries (the common case) issue all
+// their index, value and gathered loads before the first FMA.
 __global__ __launch_bounds__(256) void k_spmv(CsrDev K, const double* __restrict__ x, double* __restrict__ y) {
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= K.n) return;
   const int lane = threadIdx.x & 63;
+  const int64_t e0 = K.rowptr[row] + lane, e1 = K.rowptr[row + 1];
   double s = 0.0;
-  for (int64_t e = K.rowptr[row] + lane; e < K.rowptr[row + 1]; e += 64) s += K.val[e] * x[K.col[e]];
+  if (e1 - K.rowptr[row] <= 4 * 64) {
+    int c[4];
+    double v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t e = e0 + 64 * j;
+      c[j] = (e < e1) ? K.col[e] : 0;
+      v[j] = (e < e1) ? K.val[e] : 0.0;
+    }
+    double xv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xv[j] = (e0 + 64 * j < e1) ? x[c[j]] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (e0 + 64 * j < e1) s += v[j] * xv[j];
+  } else {
+    for (int64_t e = e0; e < e1; e += 64) s += K.val[e] * x[K.col[e]];
+  }
   s = wave_sum(s);
   if (lane == 0) y[row] = s;
 }
