@@ -22,7 +22,10 @@
  *
  * Ownership: the library copies everything it keeps during gdsw_setup; the
  * caller may free every input after it returns.  A context owns its device
- * memory until gdsw_destroy.  Calls on one context must not overlap.
+ * memory until gdsw_destroy, which waits for the device to drain and hands
+ * the blocks to a process-wide cache (per device, at most 64 GiB) that later
+ * setups reuse; cached blocks are released when the process exits.  Calls on
+ * one context must not overlap.
  *
  * Errors: every int-returning call returns one of the GDSW_* codes below;
  * gdsw_last_error() gives a message for the calling thread's last failure.
@@ -235,7 +238,9 @@ void gdsw_plan_destroy(gdsw_plan* plan);
  * control); host-only integer work, no device allocation. Returns 0 on error. */
 size_t gdsw_footprint_bytes(const gdsw_problem* prob, const gdsw_options* opt);
 
-/* Release every device and host resource of the context (NULL is a no-op). */
+/* Release every resource of the context (NULL is a no-op): waits for the
+ * device to drain, returns the device blocks to the process-wide cache and
+ * frees the host memory. */
 void gdsw_destroy(gdsw_ctx* ctx);
 
 /* Message of the calling thread's last failure ("" if none). */

@@ -31,37 +31,87 @@ double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Device memory owned by a context; released together on destroy.
+// Process-wide cache of device blocks, per device: the blocks of a destroyed
+// context are handed to the next setup instead of being freed (hipMalloc and
+// hipFree are slow and hipFree synchronizes the device).  A request takes the
+// smallest cached block that fits with at most 25% slack; at most
+// DEVICE_CACHE_LIMIT bytes stay cached, the rest is freed.
+constexpr size_t DEVICE_CACHE_LIMIT = size_t(64) << 30;
+std::mutex g_dev_mu;
+std::map<int, std::multimap<size_t, void*>> g_dev_free;
+size_t g_dev_cached = 0;
+
+void* device_take(size_t bytes, size_t& cap, int& dev) {
+  GDSW_HIP(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> g(g_dev_mu);
+    auto& m = g_dev_free[dev];
+    auto it = m.lower_bound(bytes);
+    if (it != m.end() && it->first <= bytes + bytes / 4) {
+      cap = it->first;
+      void* p = it->second;
+      m.erase(it);
+      g_dev_cached -= cap;
+      return p;
+    }
+  }
+  cap = (bytes + 255) & ~size_t(255);
+  void* p = nullptr;
+  GDSW_HIP(hipMalloc(&p, cap));
+  return p;
+}
+
+// The caller guarantees that no queued work still uses p.
+void device_give(void* p, size_t cap, int dev) {
+  {
+    std::lock_guard<std::mutex> g(g_dev_mu);
+    if (g_dev_cached + cap <= DEVICE_CACHE_LIMIT) {
+      g_dev_free[dev].emplace(cap, p);
+      g_dev_cached += cap;
+      return;
+    }
+  }
+  (void)hipFree(p);
+}
+
+// Device memory owned by a context, taken from and returned to the cache above.
+// Blocks go back on destroy, after the device has drained.
 class Arena {
  public:
   ~Arena() { release(); }
   void* alloc(size_t bytes) {
     if (bytes == 0) bytes = 16;
-    void* p = nullptr;
-    GDSW_HIP(hipMalloc(&p, bytes));
-    ptrs_.push_back(p);
+    Block b;
+    b.p = device_take(bytes, b.cap, b.dev);
+    blocks_.push_back(b);
     bytes_ += bytes;
-    return p;
+    return b.p;
   }
   template <typename T> T* alloc_n(size_t n) { return static_cast<T*>(alloc(n * sizeof(T))); }
+  // Only for blocks no queued work uses any more.
   void free_one(void* p) {
-    auto it = std::find(ptrs_.begin(), ptrs_.end(), p);
-    if (it != ptrs_.end()) {
-      (void)hipFree(p);
-      ptrs_.erase(it);
-    }
+    for (auto it = blocks_.begin(); it != blocks_.end(); ++it)
+      if (it->p == p) {
+        device_give(it->p, it->cap, it->dev);
+        blocks_.erase(it);
+        return;
+      }
   }
   void release() {
-    for (void* p : ptrs_) (void)hipFree(p);
-    ptrs_.clear();
+    for (const Block& b : blocks_) device_give(b.p, b.cap, b.dev);
+    blocks_.clear();
   }
   size_t bytes() const { return bytes_; }
 
  private:
-  std::vector<void*> ptrs_;
+  struct Block {
+    void* p = nullptr;
+    size_t cap = 0;
+    int dev = 0;
+  };
+  std::vector<Block> blocks_;
   size_t bytes_ = 0;
 };
-
 
 // Page-locked host buffers shared by all contexts of the process; a context
 // takes them while it uploads and gives them back at the end of its setup
@@ -1332,6 +1382,9 @@ size_t gdsw_footprint_bytes(const gdsw_problem* prob, const gdsw_options* opt) {
 
 void gdsw_destroy(gdsw_ctx* C) {
   if (!C) return;
+  // the device blocks go back to the process cache: drain the device first
+  // (the same wait hipFree implies), so no queued work still uses them
+  (void)hipDeviceSynchronize();
   if (C->hhost) (void)hipHostFree(C->hhost);
   delete C;
 }
