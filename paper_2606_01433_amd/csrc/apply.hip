@@ -25,6 +25,7 @@ constexpr int PW = 64;   // triangle / panel width of the blocked substitution
 // may pick 2 or 8).  Matrices are visited largest first (`order`), so the big
 // ones do not form the tail.
 // FIRST only separates the level-1 launch from deeper levels in profiles.
+// Columns are stored with leading dimension lead_dim(n, pad).
 // ---------------------------------------------------------------------------
 template <typename T, bool FIRST, int NW>
 __global__ __launch_bounds__(64 * NW) void k_local_solve_wg(const int* __restrict__ order,
@@ -32,7 +33,8 @@ __global__ __launch_bounds__(64 * NW) void k_local_solve_wg(const int* __restric
                                                             const int* __restrict__ gidx,
                                                             const int64_t* __restrict__ blk_off,
                                                             const T* __restrict__ blocks,
-                                                            const double* __restrict__ r, double* __restrict__ w) {
+                                                            const double* __restrict__ r, double* __restrict__ w,
+                                                            int pad) {
   constexpr int NT = 64 * NW;
   extern __shared__ unsigned char smem_raw[];
   T* x = reinterpret_cast<T*>(smem_raw);
@@ -40,6 +42,7 @@ __global__ __launch_bounds__(64 * NW) void k_local_solve_wg(const int* __restric
   const int64_t base = dom_ptr[i];
   const int n = (int)(dom_ptr[i + 1] - base);
   const T* A = blocks + blk_off[i];
+  const int ld = lead_dim(n, pad);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   for (int a = tid; a < n; a += NT) x[a] = (T)r[gidx[base + a]];
   __syncthreads();
@@ -49,7 +52,7 @@ __global__ __launch_bounds__(64 * NW) void k_local_solve_wg(const int* __restric
       const int row = p0 + lane;
       T d[PW];
 #pragma unroll
-      for (int j = 0; j < PW; ++j) d[j] = (lane < pw && j < lane) ? A[row + (int64_t)(p0 + j) * n] : T(0);
+      for (int j = 0; j < PW; ++j) d[j] = (lane < pw && j < lane) ? A[row + (int64_t)(p0 + j) * ld] : T(0);
       T xv = (lane < pw) ? x[row] : T(0);
 #pragma unroll
       for (int j = 0; j < PW; ++j) xv -= d[j] * lane_value(xv, j);
@@ -57,10 +60,10 @@ __global__ __launch_bounds__(64 * NW) void k_local_solve_wg(const int* __restric
     }
     __syncthreads();
     for (int rr = p0 + pw + tid; rr < n; rr += NT) {
-      const T* Ar = A + rr + (int64_t)p0 * n;
+      const T* Ar = A + rr + (int64_t)p0 * ld;
       T v[PW];
 #pragma unroll
-      for (int j = 0; j < PW; ++j) v[j] = (j < pw) ? Ar[(int64_t)j * n] : T(0);
+      for (int j = 0; j < PW; ++j) v[j] = (j < pw) ? Ar[(int64_t)j * ld] : T(0);
       T acc = T(0);
 #pragma unroll
       for (int j = 0; j < PW; ++j) acc += v[j] * x[p0 + min(j, pw - 1)];   // v[j] = 0 past pw
@@ -75,8 +78,8 @@ __global__ __launch_bounds__(64 * NW) void k_local_solve_wg(const int* __restric
       T d[PW];
 #pragma unroll
       for (int j = 0; j < PW; ++j)
-        d[j] = (lane < pw && j > lane && j < pw) ? A[row + (int64_t)(p0 + j) * n] : T(0);
-      const T rd = (lane < pw) ? T(1) / A[row + (int64_t)row * n] : T(0);
+        d[j] = (lane < pw && j > lane && j < pw) ? A[row + (int64_t)(p0 + j) * ld] : T(0);
+      const T rd = (lane < pw) ? T(1) / A[row + (int64_t)row * ld] : T(0);
       T xv = (lane < pw) ? x[row] : T(0);
 #pragma unroll
       for (int j = PW - 1; j >= 0; --j) {
@@ -87,10 +90,10 @@ __global__ __launch_bounds__(64 * NW) void k_local_solve_wg(const int* __restric
     }
     __syncthreads();
     for (int rr = tid; rr < p0; rr += NT) {
-      const T* Ar = A + rr + (int64_t)p0 * n;
+      const T* Ar = A + rr + (int64_t)p0 * ld;
       T v[PW];
 #pragma unroll
-      for (int j = 0; j < PW; ++j) v[j] = (j < pw) ? Ar[(int64_t)j * n] : T(0);
+      for (int j = 0; j < PW; ++j) v[j] = (j < pw) ? Ar[(int64_t)j * ld] : T(0);
       T acc = T(0);
 #pragma unroll
       for (int j = 0; j < PW; ++j) acc += v[j] * x[p0 + min(j, pw - 1)];
@@ -205,7 +208,7 @@ __global__ void k_transpose(int n, const double* __restrict__ A, double* __restr
 
 template <typename T>
 void local_solves(int nparts, int max_n, const int* order, const int64_t* dom_ptr, const int* gidx,
-                  const int64_t* blk_off, const T* blocks, const double* r, double* w, bool first_level,
+                  const int64_t* blk_off, const T* blocks, int pad, const double* r, double* w, bool first_level,
                   int waves, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (nparts == 0) return;
   const size_t lds = (size_t)max_n * sizeof(T);
@@ -216,10 +219,10 @@ void local_solves(int nparts, int max_n, const int* order, const int64_t* dom_pt
   do {                                                                                                          \
     if (ev_start)                                                                                               \
       hipExtLaunchKernelGGL((k_local_solve_wg<T, F, NW>), dim3(nparts), dim3(64 * NW), lds, s, ev_start, ev_stop, \
-                            0, order, dom_ptr, gidx, blk_off, blocks, r, w);                                    \
+                            0, order, dom_ptr, gidx, blk_off, blocks, r, w, pad);                               \
     else                                                                                                        \
       hipLaunchKernelGGL((k_local_solve_wg<T, F, NW>), dim3(nparts), dim3(64 * NW), lds, s, order, dom_ptr,     \
-                         gidx, blk_off, blocks, r, w);                                                          \
+                         gidx, blk_off, blocks, r, w, pad);                                                     \
   } while (0)
   if (first_level) {
     if (waves == 2) GDSW_LS(true, 2);
@@ -275,9 +278,9 @@ void dense_gemv_rows(int n, const double* AT, const double* x, double* y, hipStr
 }
 
 template void local_solves<double>(int, int, const int*, const int64_t*, const int*, const int64_t*,
-                                   const double*, const double*, double*, bool, int, hipStream_t, hipEvent_t,
+                                   const double*, int, const double*, double*, bool, int, hipStream_t, hipEvent_t,
                                    hipEvent_t);
-template void local_solves<float>(int, int, const int*, const int64_t*, const int*, const int64_t*, const float*,
+template void local_solves<float>(int, int, const int*, const int64_t*, const int*, const int64_t*, const float*, int,
                                   const double*, double*, bool, int, hipStream_t, hipEvent_t, hipEvent_t);
 template void restrict_phi<double>(int, const int64_t*, const int*, const int64_t*, const int*, const int*,
                                    const int64_t*, const int*, const int64_t*, const double*, const double*, double*,

@@ -62,6 +62,11 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned G) {
   return x * q + (x < r ? x : r) + j;
 }
 
+// Leading dimension of a dense column-major block of order n whose columns are
+// padded to a multiple of `pad` rows (pad <= 1: none).  Padding to 128 bytes
+// keeps every 64-row panel boundary on a cache-line boundary.
+__host__ __device__ __forceinline__ int lead_dim(int n, int pad) { return pad > 1 ? (n + pad - 1) / pad * pad : n; }
+
 // Lower bound of `key` in the sorted array a[0..n).
 __device__ __forceinline__ int lower_bound_i32(const int* a, int n, int key) {
   int lo = 0, hi = n;

@@ -174,7 +174,8 @@ struct Level {
   LevelMaps maps;
   // local blocks
   int max_n = 0;
-  int64_t sum_n = 0, sum_n2 = 0;
+  int64_t sum_n = 0, sum_n2 = 0;  // sum_n2: elements of the stored blocks (n_i x lead_dim(n_i, pad))
+  int pad = 1;                     // block columns padded to 128 bytes
   std::vector<int> dims;
   std::vector<int> order_h;
   std::vector<int64_t> blk_off_h;
@@ -351,11 +352,12 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
   L.max_n = 0;
   L.sum_n = 0;
   L.sum_n2 = 0;
+  L.pad = (int)(128 / sizeof(T));
   for (int i = 0; i < N; ++i) {
     const int ni = (int)(m.dom_ptr[i + 1] - m.dom_ptr[i]);
     L.dims[i] = ni;
     L.blk_off_h[i] = L.sum_n2;
-    L.sum_n2 += (int64_t)ni * ni;
+    L.sum_n2 += (int64_t)ni * lead_dim(ni, L.pad);
     L.sum_n += ni;
     L.max_n = std::max(L.max_n, ni);
   }
@@ -385,7 +387,7 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
   T* blocks = A.alloc_n<T>((size_t)L.sum_n2);
   L.blocks = blocks;
   GDSW_HIP(hipMemsetAsync(blocks, 0, (size_t)L.sum_n2 * sizeof(T), s));
-  extract_blocks<T>(L.K, N, L.sum_n, L.dom_ptr, L.dom, L.blk_off, blocks, s);
+  extract_blocks<T>(L.K, N, L.sum_n, L.dom_ptr, L.dom, L.blk_off, blocks, L.pad, s);
   L.piv = A.alloc_n<int>((size_t)L.sum_n);
   L.info = A.alloc_n<int>(N);
   GDSW_HIP(hipMemsetAsync(L.info, 0, N * sizeof(int), s));
@@ -397,6 +399,7 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
   b.piv = L.piv;
   b.poff = L.dom_ptr;
   b.info = L.info;
+  b.pad = L.pad;
   b.tiles_outer = d_tiles_outer;
   b.tiles_inner = d_tiles_inner;
   b.total_outer = tiles.total_outer.data();
@@ -863,8 +866,8 @@ void tune_local_solves(gdsw_ctx* C, hipStream_t s) {
     for (int wv : {2, 4, 8}) {
       for (int rep = 0; rep < 2; ++rep) {
         GDSW_HIP(hipEventRecord(e0, s));
-        local_solves<T>(L.nparts, L.max_n, L.order, L.dom_ptr, L.gidx, L.blk_off, static_cast<const T*>(L.blocks), r0,
-                        L.w, l == 0, wv, s);
+        local_solves<T>(L.nparts, L.max_n, L.order, L.dom_ptr, L.gidx, L.blk_off, static_cast<const T*>(L.blocks),
+                        L.pad, r0, L.w, l == 0, wv, s);
         GDSW_HIP(hipEventRecord(e1, s));
         GDSW_HIP(hipEventSynchronize(e1));
         float ms = 0;
@@ -916,8 +919,8 @@ void apply_level(gdsw_ctx* C, int l, const double* r, double* z, hipStream_t s) 
     e_start = next_event(C);
     e_stop = next_event(C);
   }
-  local_solves<T>(L.nparts, L.max_n, L.order, L.dom_ptr, L.gidx, L.blk_off, static_cast<const T*>(L.blocks), r, L.w,
-                  l == 0, L.ls_waves, s, e_start, e_stop);
+  local_solves<T>(L.nparts, L.max_n, L.order, L.dom_ptr, L.gidx, L.blk_off, static_cast<const T*>(L.blocks), L.pad,
+                  r, L.w, l == 0, L.ls_waves, s, e_start, e_stop);
   scatter_sum(L.n, L.sc_ptr, L.sc_pos, L.w, z, s);
   if (!L.has_coarse) return;
   if (fork) GDSW_HIP(hipStreamWaitEvent(s, C->ev_join, 0));
@@ -1361,7 +1364,7 @@ size_t gdsw_footprint_bytes(const gdsw_problem* prob, const gdsw_options* opt) {
       size_t n2 = 0, sn = 0;
       for (size_t i = 0; i < N; ++i) {
         const size_t ni = (size_t)(m.dom_ptr[i + 1] - m.dom_ptr[i]);
-        n2 += ni * ni;
+        n2 += ni * (size_t)gdsw::lead_dim((int)ni, (int)(128 / s));
         sn += ni;
       }
       total += n2 * s + sn * 24;

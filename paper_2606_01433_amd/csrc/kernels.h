@@ -18,6 +18,9 @@ struct LuBatch {
   int* piv = nullptr;              // pivots, matrix i at poff[i]
   const int64_t* poff = nullptr;
   int* info = nullptr;             // first zero pivot (1-based) or 0
+  // Columns stored with their length padded to a multiple of `pad` rows
+  // (leading dimension lead_dim(order, pad); 0 or 1: ld = order).
+  int pad = 0;
   // Optional compact update grids (see LuTiles): per outer step s, prefix sums
   // over the matrices of their 64 x 64 update tiles (device, [steps][count+1]),
   // and the per-step totals (host).  Without them every matrix gets the tiles
@@ -57,7 +60,7 @@ struct CsrDev {
 // Dense local blocks A_i = K[D_i, D_i] (blocks pre-zeroed).
 template <typename T>
 void extract_blocks(const CsrDev& K, int nparts, int64_t total_rows, const int64_t* dom_ptr, const int* dom,
-                    const int64_t* blk_off, T* blocks, hipStream_t s);
+                    const int64_t* blk_off, T* blocks, int pad, hipStream_t s);
 // Interior blocks K[I_i, I_i] and right-hand sides -K[I_i, Gamma] Phi_Gamma (both pre-zeroed).
 template <typename T>
 void extract_interior(const CsrDev& K, int nparts, int64_t total_rows, const int64_t* int_ptr, const int* inter,
@@ -97,7 +100,7 @@ template <typename S, typename D> void convert(const S* in, D* out, int64_t n, h
 // waves: wavefronts per matrix (2, 4 or 8).
 template <typename T>
 void local_solves(int nparts, int max_n, const int* order, const int64_t* dom_ptr, const int* gidx,
-                  const int64_t* blk_off, const T* blocks, const double* r, double* w, bool first_level,
+                  const int64_t* blk_off, const T* blocks, int pad, const double* r, double* w, bool first_level,
                   int waves, hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // z[g] = 0.0 + sum_k w[pos[k]] over sc_ptr[g]..sc_ptr[g+1]; with sc_ptr == nullptr, z[g] = 0.0 + w[pos[g]]
 void scatter_sum(int64_t n, const int64_t* sc_ptr, const int* sc_pos, const double* w, double* z, hipStream_t s);

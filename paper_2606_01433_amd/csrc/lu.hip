@@ -173,11 +173,12 @@ template <typename T, int NB>
 __global__ __launch_bounds__(256) void k_lu_panel(T* __restrict__ Ab, const int64_t* __restrict__ off,
                                                   const int* __restrict__ dim, int* __restrict__ pivb,
                                                   const int64_t* __restrict__ poff, int* __restrict__ info,
-                                                  int k) {
+                                                  int k, int pad) {
   const int i = blockIdx.x;
   const int n = dim[i];
   if (k >= n || n - k <= panel_reg_rows<T>()) return;   // shorter panels go to k_lu_panel_rot
   const int jb = min(NB, n - k);
+  const int ld = lead_dim(n, pad);
   T* A = Ab + off[i];
   int* piv = pivb + poff[i];
   __shared__ double s_val[4];
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(256) void k_lu_panel(T* __restrict__ Ab, const int6
   __shared__ int s_p;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int j = k; j < k + jb; ++j) {
-    T* colj = A + (int64_t)j * n;
+    T* colj = A + (int64_t)j * ld;
     double best = -1.0;
     int bi = n;
     for (int r = j + tid; r < n; r += 256) {
@@ -228,7 +229,7 @@ __global__ __launch_bounds__(256) void k_lu_panel(T* __restrict__ Ab, const int6
     const int p = s_p;
     if (p != j) {
       for (int c = tid; c < jb; c += 256) {
-        T* cc = A + (int64_t)(k + c) * n;
+        T* cc = A + (int64_t)(k + c) * ld;
         const T t = cc[j];
         cc[j] = cc[p];
         cc[p] = t;
@@ -243,7 +244,7 @@ __global__ __launch_bounds__(256) void k_lu_panel(T* __restrict__ Ab, const int6
     for (int r = j + 1 + tid; r < n; r += 256) {
       const T l = colj[r];
       for (int c = j + 1; c < k + jb; ++c) {
-        T* cc = A + (int64_t)c * n;
+        T* cc = A + (int64_t)c * ld;
         cc[r] -= l * cc[j];
       }
     }
@@ -325,7 +326,7 @@ template <typename T, int NB, int NT, int R>
 __global__ __launch_bounds__(NT) void k_lu_panel_rot(T* __restrict__ Ab, const int64_t* __restrict__ off,
                                                      const int* __restrict__ dim, int* __restrict__ pivb,
                                                      const int64_t* __restrict__ poff, int* __restrict__ info,
-                                                     int k) {
+                                                     int k, int pad) {
   static_assert(NB % 8 == 0, "panel width must be a multiple of 8");
   constexpr int NW = NT / 64;
   constexpr int CH = 8;
@@ -334,7 +335,8 @@ __global__ __launch_bounds__(NT) void k_lu_panel_rot(T* __restrict__ Ab, const i
   const int m = n - k;
   if (m <= 0 || m > NT * R) return;         // taller panels go to k_lu_panel
   const int jb = min(NB, m);
-  T* A = Ab + off[i] + k + (int64_t)k * n;  // panel origin
+  const int ld = lead_dim(n, pad);
+  T* A = Ab + off[i] + k + (int64_t)k * ld;  // panel origin
   int* piv = pivb + poff[i] + k;
   __shared__ double s_val[2][NW];
   __shared__ int s_lab[2][NW];
@@ -349,7 +351,7 @@ __global__ __launch_bounds__(NT) void k_lu_panel_rot(T* __restrict__ Ab, const i
     const int r = tid + NT * q;
     lab[q] = r < m ? r : NO_ROW;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) v[q][c] = (r < m && c < jb) ? A[r + (int64_t)c * n] : T(0);
+    for (int c = 0; c < NB; ++c) v[q][c] = (r < m && c < jb) ? A[r + (int64_t)c * ld] : T(0);
   }
 #pragma clang loop unroll(disable)
   for (int g = 0; g < NB / CH; ++g) {
@@ -452,53 +454,8 @@ __global__ __launch_bounds__(NT) void k_lu_panel_rot(T* __restrict__ Ab, const i
     if (lab[q] != NO_ROW) {
 #pragma unroll
       for (int c = 0; c < NB; ++c)
-        if (c < jb) A[lab[q] + (int64_t)c * n] = v[q][c];
+        if (c < jb) A[lab[q] + (int64_t)c * ld] = v[q][c];
     }
-}
-
-// Interchanges of panel k on every non-panel column; U12 = L11^{-1} A12 right of the panel.
-template <typename T, int NB>
-__global__ __launch_bounds__(64) void k_lu_swap_trsm(T* __restrict__ Ab, const int64_t* __restrict__ off,
-                                                     const int* __restrict__ dim, const int* __restrict__ pivb,
-                                                     const int64_t* __restrict__ poff, int k) {
-  const int i = blockIdx.x;
-  const int n = dim[i];
-  if (k >= n) return;
-  const int jb = min(NB, n - k);
-  T* A = Ab + off[i];
-  const int* piv = pivb + poff[i];
-  __shared__ T L11[NB * NB];
-  for (int t = threadIdx.x; t < jb * jb; t += 64) {
-    const int r = t % jb, c = t / jb;
-    L11[t] = A[(k + r) + (int64_t)(k + c) * n];
-  }
-  __syncthreads();
-  const int c = blockIdx.y * 64 + threadIdx.x;
-  if (c >= n || (c >= k && c < k + jb)) return;
-  T* col = A + (int64_t)c * n;
-  for (int j = k; j < k + jb; ++j) {
-    const int p = piv[j];
-    if (p != j) {
-      const T t = col[j];
-      col[j] = col[p];
-      col[p] = t;
-    }
-  }
-  if (c < k + jb) return;
-  T x[NB];
-#pragma unroll
-  for (int r = 0; r < NB; ++r) x[r] = (r < jb) ? col[k + r] : T(0);
-#pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    if (j < jb) {
-#pragma unroll
-      for (int r = j + 1; r < NB; ++r)
-        if (r < jb) x[r] -= L11[r + j * jb] * x[j];
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < NB; ++r)
-    if (r < jb) col[k + r] = x[r];
 }
 
 // ---- two-level blocking: outer width 2 * NB, two NB-wide sub-panels ----------
@@ -508,21 +465,22 @@ __global__ __launch_bounds__(64) void k_lu_swap_trsm(T* __restrict__ Ab, const i
 template <typename T, int NB>
 __global__ __launch_bounds__(64) void k_lu_inner_swap_trsm(T* __restrict__ Ab, const int64_t* __restrict__ off,
                                                            const int* __restrict__ dim, const int* __restrict__ pivb,
-                                                           const int64_t* __restrict__ poff, int k) {
+                                                           const int64_t* __restrict__ poff, int k, int pad) {
   const int i = blockIdx.x;
   const int n = dim[i];
   if (k + NB >= n) return;                  // no second sub-panel
+  const int ld = lead_dim(n, pad);
   T* A = Ab + off[i];
   const int* piv = pivb + poff[i];
   __shared__ T L11[NB * NB];
   for (int t = threadIdx.x; t < NB * NB; t += 64) {
     const int r = t % NB, c = t / NB;
-    L11[t] = A[(k + r) + (int64_t)(k + c) * n];
+    L11[t] = A[(k + r) + (int64_t)(k + c) * ld];
   }
   __syncthreads();
   const int c = k + NB + (int)threadIdx.x;
   if (threadIdx.x >= NB || c >= n) return;
-  T* col = A + (int64_t)c * n;
+  T* col = A + (int64_t)c * ld;
   for (int j = k; j < k + NB; ++j) {
     const int p = piv[j];
     if (p != j) {
@@ -548,14 +506,14 @@ __global__ __launch_bounds__(64) void k_lu_inner_swap_trsm(T* __restrict__ Ab, c
 template <typename T, int NB>
 __global__ __launch_bounds__(64) void k_lu_outer_swap_left(T* __restrict__ Ab, const int64_t* __restrict__ off,
                                                            const int* __restrict__ dim, const int* __restrict__ pivb,
-                                                           const int64_t* __restrict__ poff, int k) {
+                                                           const int64_t* __restrict__ poff, int k, int pad) {
   const int i = blockIdx.x;
   const int n = dim[i];
   if (k >= n) return;
   const int c = blockIdx.y * 64 + threadIdx.x;
   if (c >= k + NB || c >= n) return;
   const int kw = min(2 * NB, n - k);
-  T* col = Ab + off[i] + (int64_t)c * n;
+  T* col = Ab + off[i] + (int64_t)c * lead_dim(n, pad);
   const int* piv = pivb + poff[i];
   for (int j = (c < k ? k : k + NB); j < k + kw; ++j) {
     const int p = piv[j];
@@ -576,25 +534,26 @@ template <typename T, int NB>
 __global__ __launch_bounds__(TRSM_COLS) void k_lu_outer_swap_trsm(T* __restrict__ Ab, const int64_t* __restrict__ off,
                                                                   const int* __restrict__ dim,
                                                                   const int* __restrict__ pivb,
-                                                                  const int64_t* __restrict__ poff, int k) {
+                                                                  const int64_t* __restrict__ poff, int k, int pad) {
   constexpr int KW = 2 * NB;
   const int i = blockIdx.x;
   const int n = dim[i];
   const int cfirst = k + KW + blockIdx.y * TRSM_COLS;
   if (cfirst >= n) return;                  // no trailing columns in this block
+  const int ld = lead_dim(n, pad);
   T* A = Ab + off[i];
   const int* piv = pivb + poff[i];
   __shared__ T L11[KW * KW];
   __shared__ int sp[KW];
   for (int t = threadIdx.x; t < KW * KW; t += TRSM_COLS) {
     const int r = t % KW, c = t / KW;
-    L11[t] = A[(k + r) + (int64_t)(k + c) * n];
+    L11[t] = A[(k + r) + (int64_t)(k + c) * ld];
   }
   if (threadIdx.x < KW) sp[threadIdx.x] = piv[k + threadIdx.x];
   __syncthreads();
   const int c = cfirst + (int)threadIdx.x;
   if (c >= n) return;
-  T* col = A + (int64_t)c * n;
+  T* col = A + (int64_t)c * ld;
   for (int j = 0; j < KW; ++j) {
     const int p = sp[j];
     if (p != k + j) {
@@ -620,7 +579,7 @@ __global__ __launch_bounds__(TRSM_COLS) void k_lu_outer_swap_trsm(T* __restrict_
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void k_lu_update(T* __restrict__ Ab, const int64_t* __restrict__ off,
                                                    const int* __restrict__ dim, int k, int inner, int tiles_m,
-                                                   int tiles_n, const int64_t* __restrict__ tab, int count) {
+                                                   int tiles_n, const int64_t* __restrict__ tab, int count, int pad) {
   const int w = (int)xcd_remap(blockIdx.x, gridDim.x);
   int i, tl;
   if (tab) {                                // compact grid: tab[i] = first tile of matrix i
@@ -641,9 +600,10 @@ __global__ __launch_bounds__(256) void k_lu_update(T* __restrict__ Ab, const int
   const int tm = tab ? (M + TILE - 1) / TILE : tiles_m;
   const int ty = tl % tm, tx = tl / tm;
   if (ty * TILE >= M || tx * TILE >= N) return;
+  const int ld = lead_dim(n, pad);
   T* A = Ab + off[i];
-  gemm_sub_tile_direct<T, 2 * NB>(A + r0 + (int64_t)c0 * n, n, A + r0 + (int64_t)k * n, n, A + k + (int64_t)c0 * n, n,
-                                  M, N, kw, ty, tx);
+  gemm_sub_tile_direct<T, 2 * NB>(A + r0 + (int64_t)c0 * ld, ld, A + r0 + (int64_t)k * ld, ld, A + k + (int64_t)c0 * ld,
+                                  ld, M, N, kw, ty, tx);
 }
 
 // mode 0: LU trailing update; 1: forward-solve update of X; 2: backward-solve update of X.
@@ -935,7 +895,7 @@ void launch_panel_rot(const LuBatch& b, T* A, int k, int rows, hipStream_t s) {
 #define GDSW_PANEL(NT, R)                                                                                       \
   if (rows <= NT * R) {                                                                                         \
     hipLaunchKernelGGL((k_lu_panel_rot<T, NB, NT, R>), dim3(b.count), dim3(NT), 0, s, A, b.off, b.dim, b.piv, \
-                       b.poff, b.info, k);                                                                      \
+                       b.poff, b.info, k, b.pad);                                                                      \
     GDSW_LAUNCH_CHECK();                                                                                        \
     return;                                                                                                     \
   }
@@ -987,7 +947,7 @@ void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
     const int rows = b.max_n - k;
     if (rows > panel_reg_rows<T>()) {
       hipLaunchKernelGGL((k_lu_panel<T, NB>), dim3(b.count), dim3(256), 0, s, A, b.off, b.dim, b.piv, b.poff,
-                         b.info, k);
+                         b.info, k, b.pad);
       GDSW_LAUNCH_CHECK();
     }
     launch_panel_rot<T>(b, A, k, std::min(rows, panel_reg_rows<T>()), s);
@@ -996,32 +956,32 @@ void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
     panel(k);
     if (b.max_n > k + NB) {
       hipLaunchKernelGGL((k_lu_inner_swap_trsm<T, NB>), dim3(b.count), dim3(64), 0, s, A, b.off, b.dim, b.piv, b.poff,
-                         k);
+                         k, b.pad);
       GDSW_LAUNCH_CHECK();
       const int tm = (int)blocks_for(b.max_n - k - NB, TILE);
       const int st = k / (2 * NB);
       const int64_t grid = b.tiles_inner ? b.total_inner[st] : (int64_t)b.count * tm;
       if (grid > 0) {
         hipLaunchKernelGGL((k_lu_update<T, NB>), dim3((unsigned)grid), dim3(256), 0, s, A, b.off, b.dim, k, 1, tm, 1,
-                           b.tiles_inner ? b.tiles_inner + (size_t)st * (b.count + 1) : nullptr, b.count);
+                           b.tiles_inner ? b.tiles_inner + (size_t)st * (b.count + 1) : nullptr, b.count, b.pad);
         GDSW_LAUNCH_CHECK();
       }
       panel(k + NB);
     }
     hipLaunchKernelGGL((k_lu_outer_swap_left<T, NB>), dim3(b.count, blocks_for(k + NB, 64)), dim3(64), 0, s, A, b.off,
-                       b.dim, b.piv, b.poff, k);
+                       b.dim, b.piv, b.poff, k, b.pad);
     GDSW_LAUNCH_CHECK();
     const int rest = b.max_n - k - 2 * NB;
     if (rest > 0) {
       hipLaunchKernelGGL((k_lu_outer_swap_trsm<T, NB>), dim3(b.count, blocks_for(rest, TRSM_COLS)), dim3(TRSM_COLS), 0,
-                         s, A, b.off, b.dim, b.piv, b.poff, k);
+                         s, A, b.off, b.dim, b.piv, b.poff, k, b.pad);
       GDSW_LAUNCH_CHECK();
       const int t = (int)blocks_for(rest, TILE);
       const int st = k / (2 * NB);
       const int64_t grid = b.tiles_outer ? b.total_outer[st] : (int64_t)b.count * t * t;
       if (grid > 0) {
         hipLaunchKernelGGL((k_lu_update<T, NB>), dim3((unsigned)grid), dim3(256), 0, s, A, b.off, b.dim, k, 0, t, t,
-                           b.tiles_outer ? b.tiles_outer + (size_t)st * (b.count + 1) : nullptr, b.count);
+                           b.tiles_outer ? b.tiles_outer + (size_t)st * (b.count + 1) : nullptr, b.count, b.pad);
         GDSW_LAUNCH_CHECK();
       }
     }
@@ -1031,6 +991,7 @@ void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
 template <typename T>
 void lu_solve_batched(const LuBatch& b, const T* A, T* X, const int64_t* xoff, const int* nrhs, int max_rhs,
                       hipStream_t s) {
+  if (b.pad > 1) throw Error(-1, "lu_solve_batched: padded blocks are not supported");
   constexpr int NB = LU_NB;
   const unsigned rhsblocks = blocks_for(max_rhs, 64);
   hipLaunchKernelGGL((k_getrs_swap<T>), dim3(b.count, rhsblocks), dim3(64), 0, s, b.dim, b.piv, b.poff, X, xoff,

@@ -19,7 +19,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_extract_blocks(CsrDev K, int nparts, int64_t total_rows,
                                                         const int64_t* __restrict__ dom_ptr,
                                                         const int* __restrict__ dom,
-                                                        const int64_t* __restrict__ blk_off, T* __restrict__ blocks) {
+                                                        const int64_t* __restrict__ blk_off, T* __restrict__ blocks,
+                                                        int pad) {
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= total_rows) return;
   const int lane = threadIdx.x & 63;
@@ -30,10 +31,11 @@ __global__ __launch_bounds__(256) void k_extract_blocks(CsrDev K, int nparts, in
   const int* D = dom + base;
   const int g = D[a];
   T* A = blocks + blk_off[i];
+  const int ld = lead_dim(n, pad);
   for (int64_t e = K.rowptr[g] + lane; e < K.rowptr[g + 1]; e += 64) {
     const int h = K.col[e];
     const int b = lower_bound_i32(D, n, h);
-    if (b < n && D[b] == h) A[a + (int64_t)b * n] = (T)K.val[e];
+    if (b < n && D[b] == h) A[a + (int64_t)b * ld] = (T)K.val[e];
   }
 }
 
@@ -333,10 +335,10 @@ __global__ void k_convert(const S* __restrict__ in, D* __restrict__ out, int64_t
 
 template <typename T>
 void extract_blocks(const CsrDev& K, int nparts, int64_t total_rows, const int64_t* dom_ptr, const int* dom,
-                    const int64_t* blk_off, T* blocks, hipStream_t s) {
+                    const int64_t* blk_off, T* blocks, int pad, hipStream_t s) {
   if (total_rows == 0) return;
   hipLaunchKernelGGL((k_extract_blocks<T>), dim3(blocks_for(total_rows, 4)), dim3(256), 0, s, K, nparts,
-                     total_rows, dom_ptr, dom, blk_off, blocks);
+                     total_rows, dom_ptr, dom, blk_off, blocks, pad);
   GDSW_LAUNCH_CHECK();
 }
 
@@ -420,9 +422,9 @@ void convert(const S* in, D* out, int64_t n, hipStream_t s) {
 }
 
 template void extract_blocks<double>(const CsrDev&, int, int64_t, const int64_t*, const int*, const int64_t*,
-                                     double*, hipStream_t);
+                                     double*, int, hipStream_t);
 template void extract_blocks<float>(const CsrDev&, int, int64_t, const int64_t*, const int*, const int64_t*, float*,
-                                    hipStream_t);
+                                    int, hipStream_t);
 template void extract_interior<double>(const CsrDev&, int, int64_t, const int64_t*, const int*, const int*,
                                        const int*, const int*, const int64_t*, const int*, const int64_t*, double*,
                                        const int64_t*, double*, int*, hipStream_t);
