@@ -387,7 +387,7 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
   T* blocks = A.alloc_n<T>((size_t)L.sum_n2);
   L.blocks = blocks;
   GDSW_HIP(hipMemsetAsync(blocks, 0, (size_t)L.sum_n2 * sizeof(T), s));
-  extract_blocks<T>(L.K, N, L.sum_n, L.dom_ptr, L.dom, L.blk_off, blocks, L.pad, s);
+  extract_blocks<T>(L.K, N, L.max_n, L.order, L.dom_ptr, L.dom, L.blk_off, blocks, L.pad, s);
   L.piv = A.alloc_n<int>((size_t)L.sum_n);
   L.info = A.alloc_n<int>(N);
   GDSW_HIP(hipMemsetAsync(L.info, 0, N * sizeof(int), s));

@@ -57,9 +57,10 @@ struct CsrDev {
   const double* val = nullptr;
 };
 
-// Dense local blocks A_i = K[D_i, D_i] (blocks pre-zeroed).
+// Dense local blocks A_i = K[D_i, D_i] (blocks pre-zeroed); one workgroup per
+// part in the given order, D_i staged in LDS (max_n = largest order).
 template <typename T>
-void extract_blocks(const CsrDev& K, int nparts, int64_t total_rows, const int64_t* dom_ptr, const int* dom,
+void extract_blocks(const CsrDev& K, int nparts, int max_n, const int* order, const int64_t* dom_ptr, const int* dom,
                     const int64_t* blk_off, T* blocks, int pad, hipStream_t s);
 // Interior blocks K[I_i, I_i] and right-hand sides -K[I_i, Gamma] Phi_Gamma (both pre-zeroed).
 template <typename T>

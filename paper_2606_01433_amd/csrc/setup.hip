@@ -16,29 +16,36 @@ namespace gdsw {
 namespace {
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_extract_blocks(CsrDev K, int nparts, int64_t total_rows,
+__global__ __launch_bounds__(256) void k_extract_blocks(CsrDev K, const int* __restrict__ order,
                                                         const int64_t* __restrict__ dom_ptr,
                                                         const int* __restrict__ dom,
                                                         const int64_t* __restrict__ blk_off, T* __restrict__ blocks,
                                                         int pad) {
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= total_rows) return;
-  const int lane = threadIdx.x & 63;
-  const int i = segment_of(dom_ptr, nparts, row);
+  // one workgroup per part (largest first); the part's sorted dof list lives
+  // in LDS for the binary searches, one wave per local row
+  extern __shared__ int sD[];
+  const int i = order[blockIdx.x];
   const int64_t base = dom_ptr[i];
   const int n = (int)(dom_ptr[i + 1] - base);
-  const int a = (int)(row - base);
-  const int* D = dom + base;
-  const int g = D[a];
+  for (int a = threadIdx.x; a < n; a += blockDim.x) sD[a] = dom[base + a];
+  __syncthreads();
   T* A = blocks + blk_off[i];
   const int ld = lead_dim(n, pad);
-  for (int64_t e = K.rowptr[g] + lane; e < K.rowptr[g + 1]; e += 64) {
-    const int h = K.col[e];
-    const int b = lower_bound_i32(D, n, h);
-    if (b < n && D[b] == h) A[a + (int64_t)b * ld] = (T)K.val[e];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int a = wid; a < n; a += nw) {
+    const int g = sD[a];
+    for (int64_t e = K.rowptr[g] + lane; e < K.rowptr[g + 1]; e += 64) {
+      const int h = K.col[e];
+      const int b = lower_bound_i32(sD, n, h);
+      if (b < n && sD[b] == h) A[a + (int64_t)b * ld] = (T)K.val[e];
+    }
   }
 }
 
+// Interior block rows and right-hand sides, one wave per interior row: the
+// lanes fetch 64 couplings of the row and classify them; interior couplings
+// are stored directly, interface couplings are summed into the right-hand
+// side in row order (lane c owns coarse column c; R starts at zero).
 template <typename T>
 __global__ __launch_bounds__(256) void k_extract_interior(CsrDev K, int nparts, int64_t total_rows,
                                                           const int64_t* __restrict__ int_ptr,
@@ -51,8 +58,9 @@ __global__ __launch_bounds__(256) void k_extract_interior(CsrDev K, int nparts, 
                                                           const int64_t* __restrict__ aii_off, T* __restrict__ aii,
                                                           const int64_t* __restrict__ rhs_off,
                                                           double* __restrict__ rhs, int* __restrict__ bad) {
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= total_rows) return;
+  const int lane = threadIdx.x & 63;
   const int i = segment_of(int_ptr, nparts, row);
   const int64_t base = int_ptr[i];
   const int nI = (int)(int_ptr[i + 1] - base);
@@ -62,21 +70,33 @@ __global__ __launch_bounds__(256) void k_extract_interior(CsrDev K, int nparts, 
   const int* pc = pcols + pc_ptr[i];
   T* A = aii + aii_off[i];
   double* R = rhs + rhs_off[i];
-  for (int64_t e = K.rowptr[g]; e < K.rowptr[g + 1]; ++e) {
-    const int h = K.col[e];
-    const double v = K.val[e];
-    if (dof_ipart[h] == i) {
-      A[a + (int64_t)dof_irow[h] * nI] = (T)v;
-    } else {
-      const int c = dof_gcol[h];
-      if (c >= 0) {
-        const int lc = lower_bound_i32(pc, m, c);
-        if (lc < m && pc[lc] == c) R[a + (int64_t)lc * nI] -= v;
-        else *bad = 1;                 // K couples an interior dof outside its part's closure
-      } else {
-        *bad = 1;
+  const int64_t e_beg = K.rowptr[g], e_end = K.rowptr[g + 1];
+  for (int c0 = 0; c0 < m || c0 == 0; c0 += 64) {
+    const int c = c0 + lane;
+    double acc = 0.0;
+    for (int64_t e0 = e_beg; e0 < e_end; e0 += 64) {
+      const int64_t e = e0 + lane;
+      int lc = -1;
+      double v = 0.0;
+      if (e < e_end) {
+        const int h = K.col[e];
+        v = K.val[e];
+        if (dof_ipart[h] == i) {
+          if (c0 == 0) A[a + (int64_t)dof_irow[h] * nI] = (T)v;
+        } else {
+          const int gc = dof_gcol[h];
+          const int p = gc >= 0 ? lower_bound_i32(pc, m, gc) : m;
+          if (p < m && pc[p] == gc) lc = p;
+          else *bad = 1;                  // K couples an interior dof outside its part's closure
+        }
+      }
+      const int cnt = (int)min((int64_t)64, e_end - e0);
+      for (int l = 0; l < cnt; ++l) {
+        const int lcl = lane_value(lc, l);
+        if (lcl >= 0 && lcl == c) acc -= lane_value(v, l);
       }
     }
+    if (c < m) R[a + (int64_t)c * nI] = acc;
   }
 }
 
@@ -334,11 +354,12 @@ __global__ void k_convert(const S* __restrict__ in, D* __restrict__ out, int64_t
 }  // namespace
 
 template <typename T>
-void extract_blocks(const CsrDev& K, int nparts, int64_t total_rows, const int64_t* dom_ptr, const int* dom,
+void extract_blocks(const CsrDev& K, int nparts, int max_n, const int* order, const int64_t* dom_ptr, const int* dom,
                     const int64_t* blk_off, T* blocks, int pad, hipStream_t s) {
-  if (total_rows == 0) return;
-  hipLaunchKernelGGL((k_extract_blocks<T>), dim3(blocks_for(total_rows, 4)), dim3(256), 0, s, K, nparts,
-                     total_rows, dom_ptr, dom, blk_off, blocks, pad);
+  if (nparts == 0) return;
+  if ((size_t)max_n * sizeof(int) > 64 * 1024) throw Error(-1, "extract_blocks: local block too large");
+  hipLaunchKernelGGL((k_extract_blocks<T>), dim3(nparts), dim3(256), (size_t)max_n * sizeof(int), s, K, order,
+                     dom_ptr, dom, blk_off, blocks, pad);
   GDSW_LAUNCH_CHECK();
 }
 
@@ -348,7 +369,7 @@ void extract_interior(const CsrDev& K, int nparts, int64_t total_rows, const int
                       const int* pcols, const int64_t* aii_off, T* aii, const int64_t* rhs_off, double* rhs,
                       int* bad, hipStream_t s) {
   if (total_rows == 0) return;
-  hipLaunchKernelGGL((k_extract_interior<T>), dim3(blocks_for(total_rows, 128)), dim3(128), 0, s, K, nparts,
+  hipLaunchKernelGGL((k_extract_interior<T>), dim3(blocks_for(total_rows, 4)), dim3(256), 0, s, K, nparts,
                      total_rows, int_ptr, inter, dof_ipart, dof_irow, dof_gcol, pc_ptr, pcols, aii_off, aii, rhs_off,
                      rhs, bad);
   GDSW_LAUNCH_CHECK();
@@ -421,10 +442,10 @@ void convert(const S* in, D* out, int64_t n, hipStream_t s) {
   GDSW_LAUNCH_CHECK();
 }
 
-template void extract_blocks<double>(const CsrDev&, int, int64_t, const int64_t*, const int*, const int64_t*,
-                                     double*, int, hipStream_t);
-template void extract_blocks<float>(const CsrDev&, int, int64_t, const int64_t*, const int*, const int64_t*, float*,
-                                    int, hipStream_t);
+template void extract_blocks<double>(const CsrDev&, int, int, const int*, const int64_t*, const int*,
+                                     const int64_t*, double*, int, hipStream_t);
+template void extract_blocks<float>(const CsrDev&, int, int, const int*, const int64_t*, const int*, const int64_t*,
+                                    float*, int, hipStream_t);
 template void extract_interior<double>(const CsrDev&, int, int64_t, const int64_t*, const int*, const int*,
                                        const int*, const int*, const int64_t*, const int*, const int64_t*, double*,
                                        const int64_t*, double*, int*, hipStream_t);
