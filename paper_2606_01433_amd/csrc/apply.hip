@@ -130,13 +130,27 @@ __global__ __launch_bounds__(256) void k_restrict(int n_coarse, const int64_t* _
   const int lane = threadIdx.x & 63;
   double s = 0.0;
   for (int64_t k = col_ptr[c] + lane; k < col_ptr[c + 1]; k += 64) s += r[col_dofs[k]];
-  for (int64_t t = cp_ptr[c]; t < cp_ptr[c + 1]; ++t) {
-    const int i = cp_part[t];
-    const int64_t ib = int_ptr[i];
-    const int nI = (int)(int_ptr[i + 1] - ib);
-    const T* ph = phi + phi_off[i] + (int64_t)cp_lc[t] * nI;
-    const int* I = inter + ib;
-    for (int a = lane; a < nI; a += 64) s += (double)ph[a] * r[I[a]];
+  // the parts holding c: lane t fetches entry t's part data, then the parts are
+  // visited in order with their data broadcast from the owning lane
+  const int64_t t0 = cp_ptr[c], t1 = cp_ptr[c + 1];
+  for (int64_t tb = t0; tb < t1; tb += 64) {
+    const int cnt = (int)min((int64_t)64, t1 - tb);
+    int64_t ib = 0, poff = 0;
+    int nI = 0;
+    if (lane < cnt) {
+      const int i = cp_part[tb + lane];
+      ib = int_ptr[i];
+      nI = (int)(int_ptr[i + 1] - ib);
+      poff = phi_off[i] + (int64_t)cp_lc[tb + lane] * nI;
+    }
+    for (int t = 0; t < cnt; ++t) {
+      const int64_t ibt = ((int64_t)lane_value((int)(ib >> 32), t) << 32) | (unsigned int)lane_value((int)ib, t);
+      const int64_t pot = ((int64_t)lane_value((int)(poff >> 32), t) << 32) | (unsigned int)lane_value((int)poff, t);
+      const int nIt = lane_value(nI, t);
+      const T* ph = phi + pot;
+      const int* I = inter + ibt;
+      for (int a = lane; a < nIt; a += 64) s += (double)ph[a] * r[I[a]];
+    }
   }
   s = wave_sum(s);
   if (lane == 0) rc[c] = s;

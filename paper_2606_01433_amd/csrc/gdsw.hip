@@ -189,7 +189,8 @@ struct Level {
   int* gidx = nullptr;
   int* info = nullptr;
   int* order = nullptr;          // parts by decreasing block size (apply visiting order)
-  int ls_waves = 4;              // wavefronts per matrix of the local solves (autotuned with tune = 1)
+  int ls_waves = 4;              // wavefronts per matrix of the local solves: 4 on level 1 (HBM-bound,
+                                 // many matrices), 8 deeper (few, latency-bound); autotuned with tune = 1
   int64_t* sc_ptr = nullptr;
   int* sc_pos = nullptr;
   double* w = nullptr;           // local solutions, sum_n
@@ -247,6 +248,7 @@ struct gdsw_ctx {
   // during setup `side` factors level 1 and `side2` the deeper levels
   hipStream_t side = nullptr, side2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork2 = nullptr, ev_join2 = nullptr;   // level 2's coarse chain on side2
   // host-to-device uploads run on `up`, which never holds compute work
   hipStream_t up = nullptr;
   hipEvent_t ev_up = nullptr;
@@ -271,6 +273,8 @@ struct gdsw_ctx {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (ev_fork2) (void)hipEventDestroy(ev_fork2);
+    if (ev_join2) (void)hipEventDestroy(ev_join2);
     if (side) {
       (void)hipStreamSynchronize(side);
       (void)hipStreamDestroy(side);
@@ -713,6 +717,7 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
     C->levels.emplace_back();
     Level& L = C->levels.back();
     L.index = l + 1;
+    L.ls_waves = (l == 0) ? 4 : 8;
     L.nparts = meshes[l].n_parts;
     L.n = K.n;
     L.K = K;
@@ -900,17 +905,22 @@ void coarse_chain(gdsw_ctx* C, int l, const double* r, hipStream_t s) {
   else dense_gemv_rows(C->nc, C->ainv, L.rc, L.yc, s);
 }
 
-// z = B_l r (eq. (2.2) from level l down).  On level 1 the coarse chain runs on
-// the side stream concurrently with the local solves; both join before z += Phi y.
+// z = B_l r (eq. (2.2) from level l down).  On levels 1 and 2 (level 1 only in
+// captured graphs) the coarse chain runs on a side stream concurrently with the
+// local solves; both join before z += Phi y.
 template <typename T>
 void apply_level(gdsw_ctx* C, int l, const double* r, double* z, hipStream_t s) {
   Level& L = C->levels[l];
-  const bool fork = (l == 0) && L.has_coarse && C->side;
+  hipStream_t fs = (l == 0) ? C->side : (l == 1) ? C->side2 : nullptr;
+  hipEvent_t ev_fork = (l == 0) ? C->ev_fork : C->ev_fork2, ev_join = (l == 0) ? C->ev_join : C->ev_join2;
+  // (inside a graph capture only level 1 forks: a nested fork during capture
+  // is not used)
+  const bool fork = L.has_coarse && fs != nullptr && ev_fork != nullptr && (l == 0 || !C->capturing);
   if (fork) {
-    GDSW_HIP(hipEventRecord(C->ev_fork, s));
-    GDSW_HIP(hipStreamWaitEvent(C->side, C->ev_fork, 0));
-    coarse_chain<T>(C, l, r, C->side);
-    GDSW_HIP(hipEventRecord(C->ev_join, C->side));
+    GDSW_HIP(hipEventRecord(ev_fork, s));
+    GDSW_HIP(hipStreamWaitEvent(fs, ev_fork, 0));
+    coarse_chain<T>(C, l, r, fs);
+    GDSW_HIP(hipEventRecord(ev_join, fs));
   }
   const bool prof = C->opt.profile && l == 0 && !C->capturing;
   hipEvent_t e_start = nullptr, e_stop = nullptr;
@@ -923,7 +933,7 @@ void apply_level(gdsw_ctx* C, int l, const double* r, double* z, hipStream_t s) 
                   r, L.w, l == 0, L.ls_waves, s, e_start, e_stop);
   scatter_sum(L.n, L.sc_ptr, L.sc_pos, L.w, z, s);
   if (!L.has_coarse) return;
-  if (fork) GDSW_HIP(hipStreamWaitEvent(s, C->ev_join, 0));
+  if (fork) GDSW_HIP(hipStreamWaitEvent(s, ev_join, 0));
   else coarse_chain<T>(C, l, r, s);
   const T* phi = static_cast<const T*>(L.phi);
   prolong_add<T>(L.nparts, L.max_m, L.n_gdofs, L.gdofs, L.dof_gcol, L.int_ptr, L.inter, L.pc_ptr, L.pcols, L.phi_off,
@@ -1181,6 +1191,8 @@ int gdsw_setup(const gdsw_problem* prob, const gdsw_options* opt, void* stream, 
     GDSW_HIP(hipEventCreateWithFlags(&C->ev_up, hipEventDisableTiming));
     GDSW_HIP(hipEventCreateWithFlags(&C->ev_fork, hipEventDisableTiming));
     GDSW_HIP(hipEventCreateWithFlags(&C->ev_join, hipEventDisableTiming));
+    GDSW_HIP(hipEventCreateWithFlags(&C->ev_fork2, hipEventDisableTiming));
+    GDSW_HIP(hipEventCreateWithFlags(&C->ev_join2, hipEventDisableTiming));
     if (C->mixed) gdsw::setup_impl<float>(C, prob, s);
     else gdsw::setup_impl<double>(C, prob, s);
     for (size_t l = 0; l < C->levels.size() && l < 8; ++l) C->stats.ls_waves[l] = C->levels[l].ls_waves;
