@@ -239,6 +239,7 @@ struct gdsw_ctx {
   gdsw_stats stats;
   // FGMRES workspace
   int ws_m = -1;
+  hipEvent_t ev_fetch = nullptr;       // Hessenberg column copied to the host
   double *V = nullptr, *Z = nullptr, *wv = nullptr, *dpart = nullptr, *hdev = nullptr, *ydev = nullptr;
   double* hhost = nullptr;
   // event pairs around level-1 local-solve launches (profile = 1)
@@ -289,6 +290,7 @@ struct gdsw_ctx {
     }
     release_pinned();
     if (ev_up) (void)hipEventDestroy(ev_up);
+    if (ev_fetch) (void)hipEventDestroy(ev_fetch);
   }
 };
 
@@ -957,6 +959,7 @@ void ensure_workspace(gdsw_ctx* C) {
   C->hdev = A.alloc_n<double>((size_t)2 * (m + 2) + 2);
   C->ydev = A.alloc_n<double>((size_t)m + 1);
   if (!C->hhost) GDSW_HIP(hipHostMalloc((void**)&C->hhost, sizeof(double) * (2 * 256 + 8), hipHostMallocDefault));
+  if (!C->ev_fetch) GDSW_HIP(hipEventCreateWithFlags(&C->ev_fetch, hipEventDisableTiming));
   C->ws_m = m;
 }
 
@@ -1023,9 +1026,15 @@ int solve_impl(gdsw_ctx* C, const double* b, double* x, hipStream_t caller, gdsw
   double* h2 = C->hdev + (m + 1);     // [m+1]
   double* nr = C->hdev + 2 * (m + 1); // [1]
   double* hh = C->hhost;
+  // the host polls an event after the copy (lower wake-up latency than a
+  // blocking stream synchronization; the Krylov loop waits here every step)
   auto fetch = [&](int count) {
     GDSW_HIP(hipMemcpyAsync(hh, C->hdev, count * sizeof(double), hipMemcpyDeviceToHost, s));
-    GDSW_HIP(hipStreamSynchronize(s));
+    GDSW_HIP(hipEventRecord(C->ev_fetch, s));
+    hipError_t q;
+    while ((q = hipEventQuery(C->ev_fetch)) == hipErrorNotReady) {
+    }
+    GDSW_HIP(q);
   };
   multi_dot(n, 1, b, n, b, C->dpart, nr, s);
   GDSW_HIP(hipMemcpyAsync(hh, nr, sizeof(double), hipMemcpyDeviceToHost, s));
