@@ -110,6 +110,31 @@ def serving_bench(seed=0, n_requests=24):
             "max_rel_diff_fp32_vs_fp64_solution": err}
 
 
+def mixed_precision_leg(P, step, x64, t64, n_steps=3):
+    """The same step with FP32 local factors and bases (FP64 Krylov, residuals and coarsest solve),
+    against the FP64 GPU path just timed: step time, iterations, error, FP32 factor rate."""
+    import numpy as np
+    import torch
+    step(False, "mixed")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_steps):
+        x, info, st = step(True, "mixed")
+    torch.cuda.synchronize()
+    T = (time.perf_counter() - t0) / n_steps
+    xh, x64h = x.cpu().numpy(), x64.cpu().numpy()
+    launches = st["local_solve_launches"]
+    return {"solves_per_s": 1.0 / T, "ms_per_step": T * 1e3, "speedup_vs_fp64": t64 / T,
+            "ms_setup": st["ms_total"], "ms_solve": info["ms_total"], "iterations": info["iterations"],
+            "true_rel_residual": float(np.linalg.norm(P.K() @ xh - P.b) / np.linalg.norm(P.b)),
+            "rel_diff_vs_fp64_gpu_solution": float(np.linalg.norm(xh - x64h) / np.linalg.norm(x64h)),
+            "level1_local_solve_gbs": (st["local_solve_bytes"] / (st["ms_local_solve"] / launches * 1e-3) / 1e9
+                                       if launches else None),
+            "factor": {"flops_level1": st["factor_flops"][0], "ms_factor_all_levels": st["ms_factor"],
+                       "tflops_level1_lower_bound": st["factor_flops"][0] / (st["ms_factor"] * 1e-3) / 1e12,
+                       "peak_tflops": FP32_MFMA_TFLOPS}}
+
+
 def solve_only_bench(P, Kdev, b, precision, n_solves=5):
     """Setup amortized: several solves on one context, eager applies vs captured hipGraph applies."""
     import torch
@@ -164,8 +189,8 @@ def main():
     b = torch.as_tensor(P.b, device=dev)
     stream = torch.cuda.current_stream()
 
-    def step(profile):
-        ctx = gdsw.Context(P, K=Kdev, tol=1e-8, precision=args.precision, profile=profile, stream=stream)
+    def step(profile, precision=args.precision):
+        ctx = gdsw.Context(P, K=Kdev, tol=1e-8, precision=precision, profile=profile, stream=stream)
         x, info = ctx.solve(b, stream=stream)
         st = ctx.stats()
         ctx.close()
@@ -232,6 +257,8 @@ def main():
                    "peak_tflops": FP64_MFMA_TFLOPS if args.precision == "fp64" else FP32_MFMA_TFLOPS},
     }
     out["solve_only"] = solve_only_bench(P, Kdev, b, args.precision)
+    if args.precision == "fp64":
+        out["mixed_precision"] = mixed_precision_leg(P, step, x, T)
     if not args.no_serving:
         out["serving"] = serving_bench(args.seed)
     if not args.no_cpu_baseline:
