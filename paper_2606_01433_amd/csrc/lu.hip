@@ -525,6 +525,29 @@ __global__ __launch_bounds__(64) void k_lu_outer_swap_left(T* __restrict__ Ab, c
   }
 }
 
+// Interchanges piv[j0, j0 + nj) applied in order to columns [c0, c0 + nc).
+template <typename T>
+__global__ __launch_bounds__(64) void k_lu_swap_cols(T* __restrict__ Ab, const int64_t* __restrict__ off,
+                                                     const int* __restrict__ dim, const int* __restrict__ pivb,
+                                                     const int64_t* __restrict__ poff, int j0, int nj, int c0, int nc,
+                                                     int pad) {
+  const int i = blockIdx.x;
+  const int n = dim[i];
+  const int c = c0 + blockIdx.y * 64 + (int)threadIdx.x;
+  if (c >= c0 + nc || c >= n) return;
+  T* col = Ab + off[i] + (int64_t)c * lead_dim(n, pad);
+  const int* piv = pivb + poff[i];
+  const int j1 = min(j0 + nj, n);
+  for (int j = j0; j < j1; ++j) {
+    const int p = piv[j];
+    if (p != j) {
+      const T t = col[j];
+      col[j] = col[p];
+      col[p] = t;
+    }
+  }
+}
+
 // Columns right of outer step k: all of its interchanges, then
 // U12 = L11^{-1} A12 with the 2NB x 2NB unit lower L11.  One thread per
 // column, TRSM_COLS columns per workgroup; L11 and the step's pivots are staged
@@ -889,8 +912,37 @@ __global__ __launch_bounds__(512) void k_inverse_resident(const T* __restrict__ 
 
 // Register panel for the tallest panel of the launch: the smallest workgroup
 // shape (threads x rows per thread) that holds min(rows, register limit) rows.
+// A panel of width NB too tall for the register file, factored as two halves
+// of width NB/2 (each a register panel of 512 threads x R rows): half 1; its
+// interchanges and unit-lower solve on half 2's top rows; half 2 minus the
+// rank-NB/2 product; half 2; half 2's interchanges on half 1.  The result (factors
+// and pivots of the NB columns) is that of the NB-wide panel.
+template <typename T, int R>
+void launch_panel_split(const LuBatch& b, T* A, int k, hipStream_t s) {
+  constexpr int H = LU_NB / 2;
+  hipLaunchKernelGGL((k_lu_panel_rot<T, H, 512, R>), dim3(b.count), dim3(512), 0, s, A, b.off, b.dim, b.piv, b.poff,
+                     b.info, k, b.pad);
+  GDSW_LAUNCH_CHECK();
+  if (b.max_n <= k + H) return;
+  hipLaunchKernelGGL((k_lu_inner_swap_trsm<T, H>), dim3(b.count), dim3(64), 0, s, A, b.off, b.dim, b.piv, b.poff, k,
+                     b.pad);
+  GDSW_LAUNCH_CHECK();
+  const int tm = (int)blocks_for(b.max_n - k - H, TILE);
+  hipLaunchKernelGGL((k_lu_update<T, H>), dim3((unsigned)((int64_t)b.count * tm)), dim3(256), 0, s, A, b.off, b.dim,
+                     k, 1, tm, 1, nullptr, b.count, b.pad);
+  GDSW_LAUNCH_CHECK();
+  hipLaunchKernelGGL((k_lu_panel_rot<T, H, 512, R>), dim3(b.count), dim3(512), 0, s, A, b.off, b.dim, b.piv, b.poff,
+                     b.info, k + H, b.pad);
+  GDSW_LAUNCH_CHECK();
+  hipLaunchKernelGGL((k_lu_swap_cols<T>), dim3(b.count, 1), dim3(64), 0, s, A, b.off, b.dim, b.piv, b.poff, k + H, H,
+                     k, H, b.pad);
+  GDSW_LAUNCH_CHECK();
+}
+
+// split: every matrix of the batch is held by the register panels at this step
+// (none is left to k_lu_panel), so the half-width path may run on all of them.
 template <typename T>
-void launch_panel_rot(const LuBatch& b, T* A, int k, int rows, hipStream_t s) {
+void launch_panel_rot(const LuBatch& b, T* A, int k, int rows, bool split, hipStream_t s) {
   constexpr int NB = LU_NB;
 #define GDSW_PANEL(NT, R)                                                                                       \
   if (rows <= NT * R) {                                                                                         \
@@ -905,10 +957,18 @@ void launch_panel_rot(const LuBatch& b, T* A, int k, int rows, hipStream_t s) {
   GDSW_PANEL(512, 2)
   GDSW_PANEL(512, 3)
   if constexpr (sizeof(T) == 8) {
+    if (split && rows <= 512 * 4) {
+      launch_panel_split<T, 4>(b, A, k, s);
+      return;
+    }
     GDSW_PANEL(1024, 2)
   }
   if constexpr (sizeof(T) == 4) {
     GDSW_PANEL(512, 4)
+    if (split && rows <= 512 * 6) {
+      launch_panel_split<T, 6>(b, A, k, s);
+      return;
+    }
     GDSW_PANEL(512, 6)
   }
 #undef GDSW_PANEL
@@ -945,12 +1005,13 @@ void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
   constexpr int NB = LU_NB;
   auto panel = [&](int k) {
     const int rows = b.max_n - k;
-    if (rows > panel_reg_rows<T>()) {
+    const bool tall = rows > panel_reg_rows<T>();
+    if (tall) {
       hipLaunchKernelGGL((k_lu_panel<T, NB>), dim3(b.count), dim3(256), 0, s, A, b.off, b.dim, b.piv, b.poff,
                          b.info, k, b.pad);
       GDSW_LAUNCH_CHECK();
     }
-    launch_panel_rot<T>(b, A, k, std::min(rows, panel_reg_rows<T>()), s);
+    launch_panel_rot<T>(b, A, k, std::min(rows, panel_reg_rows<T>()), !tall, s);
   };
   for (int k = 0; k < b.max_n; k += 2 * NB) {
     panel(k);

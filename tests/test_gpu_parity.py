@@ -100,6 +100,33 @@ def test_apply_parity_fp64(gd, name, combine):
             assert err <= 1e-10
 
 
+def _tall():
+    return {
+        # coarsest order 1943: panels of 1537..2048 rows go through the half-width register panels
+        "die20x8x8_L2": (lambda: die_problem(20, 8, 8, seed=0, levels=2), (1537, 2048)),
+        # coarsest order 2273: panels above 2048 rows take the global-memory panel
+        "die18x10x8_L2": (lambda: die_problem(18, 10, 8, seed=0, levels=2), (2049, 4096)),
+    }
+
+
+@pytest.mark.parametrize("name", list(_tall()))
+def test_apply_parity_tall_coarsest(gd, name):
+    """Two levels with a coarsest problem taller than the full-width register panel."""
+    make, (lo, hi) = _tall()[name]
+    P = cached(("gpu", name), make)
+    H = cached(("orc", name), lambda: oracle.setup(P))
+    _say("apply fp64 tall coarsest", name, "n =", P.n, "coarsest", H.K_coarsest.shape[0])
+    assert lo <= H.K_coarsest.shape[0] <= hi
+    with gd.Context(P) as ctx:
+        assert ctx.stats()["n"][1] == H.K_coarsest.shape[0]
+        r = random_vector(P.n, 3)
+        z = ctx.apply(_dev(r)).cpu().numpy()
+    zo = oracle.apply(H, r)
+    err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+    _say("  rel err", err)
+    assert err <= 1e-10
+
+
 @pytest.mark.parametrize("name", ["cube4_L2", "die16_L3"])
 def test_apply_mixed_precision_error(gd, name):
     P = _problem(name)
