@@ -100,6 +100,21 @@ def test_apply_parity_fp64(gd, name, combine):
             assert err <= 1e-10
 
 
+def test_spmv_matches_cpu_product(gd):
+    """y = K x on the device against the CPU product; vertex rows (up to 407 entries) take the looped path."""
+    P = _problem("die16_L3")
+    K = P.K().tocsr()
+    L = np.diff(K.indptr)
+    assert L.max() > 256 and L.min() <= 256
+    x = random_vector(P.n, 8)
+    _say("spmv n =", P.n, "nnz =", K.nnz)
+    with gd.Context(P, no_coarse=True) as ctx:
+        y = ctx.spmv(_dev(x)).cpu().numpy()
+    ref = K @ x
+    scale = abs(K) @ np.abs(x)
+    assert np.all(np.abs(y - ref) <= 2.0 * L * np.finfo(np.float64).eps * scale)
+
+
 def _tall():
     return {
         # coarsest order 1943: panels of 1537..2048 rows go through the half-width register panels
