@@ -67,11 +67,13 @@ def serving_bench(seed=0, n_requests=24):
     from paper_2606_01433_amd.serving import Server, Request, summarize
     rng = np.random.Generator(np.random.PCG64(seed + 7))
     pool = []
-    for nx, ny, nz in [(16, 8, 8), (24, 12, 12), (32, 16, 16)]:
+    for nx, ny, nz in [(16, 16, 16), (32, 16, 16), (48, 24, 24), (64, 32, 32)]:
         for q in range(2):
             n_exp = float(rng.uniform(0.3, 0.9))
             lam = float(10.0 ** rng.uniform(-1.0, 1.0))
-            pool.append(die_problem(nx, ny, nz, seed=seed + q, nu0=1.0, lam=lam, n_exp=n_exp, levels=3))
+            # four levels on the larger dies keep the coarsest dense problem at order ~2k
+            levels = 3 if nx * ny * nz <= 8192 else 4
+            pool.append(die_problem(nx, ny, nz, seed=seed + q, nu0=1.0, lam=lam, n_exp=n_exp, levels=levels))
     picks = rng.integers(0, len(pool), n_requests)
     # service time of the plain FP64 path, one request at a time (also warms every size up)
     srv = Server(max_active=1)
@@ -104,8 +106,8 @@ def serving_bench(seed=0, n_requests=24):
     mixed["peak_active"] = srv.peak_active
     err = max(float(np.linalg.norm(m.x - b_.x) / np.linalg.norm(b_.x)) for m, b_ in zip(mix_reqs, base_reqs))
     return {"requests": n_requests, "arrival_rate_hz": rate,
-            "pool": "seeded dies 16x8x8, 24x12x12, 32x16x16; Carreau n ~ U[0.3,0.9], lambda = 10^U[-1,1]; "
-                    "three levels; FGMRES(30) to 1e-8",
+            "pool": "seeded dies 16x16x16, 32x16x16, 48x24x24, 64x32x32 (two each); Carreau n ~ U[0.3,0.9], "
+                    "lambda = 10^U[-1,1]; three levels up to 32x16x16, four above; FGMRES(30) to 1e-8",
             "serving_fp32_factors_4_slots": mixed, "fp64_one_at_a_time": base,
             "max_rel_diff_fp32_vs_fp64_solution": err}
 
@@ -150,7 +152,27 @@ def solve_only_bench(P, Kdev, b, precision, n_solves=5):
             torch.cuda.synchronize()
             out["graph" if graph else "eager"] = {"ms_per_solve": (time.perf_counter() - t0) / n_solves * 1e3,
                                                   "solves_per_s": n_solves / (time.perf_counter() - t0)}
+            if not graph:
+                out["spmv"] = spmv_roofline(ctx, P, b)
     return out
+
+
+def spmv_roofline(ctx, P, x, calls=50):
+    """y = K x through the library, timed with HIP events on the launching stream: algorithmic bytes
+    (CSR values and int32 columns, int64 row pointers, x once, y) over the mean duration."""
+    import torch
+    y = torch.empty_like(x)
+    ctx.spmv(x, out=y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(calls):
+        ctx.spmv(x, out=y)
+    e1.record()
+    e1.synchronize()
+    us = e0.elapsed_time(e1) / calls * 1e3
+    nbytes = 12.0 * len(P.col) + 8.0 * (P.n + 1) + 16.0 * P.n
+    return {"bound": "hbm", "achieved": nbytes / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_call": nbytes, "us_per_call": us}
 
 
 def main():

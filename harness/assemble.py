@@ -49,6 +49,9 @@ def gauss_gradients(mesh, nodal_u):
     return np.einsum("eai,qak->eqik", ue, _DPHI) * (2.0 / mesh.h)
 
 
+ASSEMBLY_CHUNK = 65536
+
+
 def assemble(mesh, nu_q, form, f=(0.0, 0.0, 0.0)):
     """Full (unconstrained) K in COO-summed CSR over all dofs and the load vector.
 
@@ -60,25 +63,42 @@ def assemble(mesh, nu_q, form, f=(0.0, 0.0, 0.0)):
     nv = 3 * mesh.n_nodes
     ntot = nv + 4 * E
     M = velocity_tables(form)
-    Ae = (0.5 * h) * (nu_q @ M.reshape(27, 81 * 81)).reshape(E, 81, 81)
     Be = -(0.5 * h) ** 2 * divergence_table()              # same for every element
-    vd = (3 * mesh.elem_node[:, :, None] + np.arange(3)[None, None, :]).reshape(E, 81)
-    pd = nv + 4 * np.arange(E)[:, None] + np.arange(4)[None, :]
     if form == "laplace":
         comp = np.tile(np.arange(3), 27)
         mask = comp[:, None] == comp[None, :]
     else:
         mask = np.ones((81, 81), dtype=bool)
     ii, jj = np.nonzero(mask)
-    rows = [vd[:, ii].ravel(), pd[:, :, None].repeat(81, 2).ravel(), vd[:, None, :].repeat(4, 1).ravel()]
-    cols = [vd[:, jj].ravel(), vd[:, None, :].repeat(4, 1).ravel(), pd[:, :, None].repeat(81, 2).ravel()]
-    vals = [Ae[:, ii, jj].ravel(), np.broadcast_to(Be, (E, 4, 81)).ravel(),
-            np.broadcast_to(Be, (E, 4, 81)).ravel()]
-    r = np.concatenate(rows)
-    c = np.concatenate(cols)
-    v = np.concatenate(vals)
-    K = sp.coo_matrix((v, (r, c)), shape=(ntot, ntot)).tocsr()
+
+    def block(e0, e1):
+        En = e1 - e0
+        Ae = (0.5 * h) * (nu_q[e0:e1] @ M.reshape(27, 81 * 81)).reshape(En, 81, 81)
+        vd = (3 * mesh.elem_node[e0:e1, :, None] + np.arange(3)[None, None, :]).reshape(En, 81)
+        pd = nv + 4 * np.arange(e0, e1)[:, None] + np.arange(4)[None, :]
+        rows = [vd[:, ii].ravel(), pd[:, :, None].repeat(81, 2).ravel(), vd[:, None, :].repeat(4, 1).ravel()]
+        cols = [vd[:, jj].ravel(), vd[:, None, :].repeat(4, 1).ravel(), pd[:, :, None].repeat(81, 2).ravel()]
+        vals = [Ae[:, ii, jj].ravel(), np.broadcast_to(Be, (En, 4, 81)).ravel(),
+                np.broadcast_to(Be, (En, 4, 81)).ravel()]
+        r = np.concatenate(rows)
+        c = np.concatenate(cols)
+        v = np.concatenate(vals)
+        return sp.coo_matrix((v, (r, c)), shape=(ntot, ntot)).tocsr()
+
+    # one COO pass for meshes up to ASSEMBLY_CHUNK elements; larger meshes are
+    # summed per chunk first (bounding the host memory of the triplets), then the
+    # chunk sums are summed in one more COO pass; explicit zeros stay in the pattern
+    if E <= ASSEMBLY_CHUNK:
+        K = block(0, E)
+    else:
+        parts = [block(e0, min(E, e0 + ASSEMBLY_CHUNK)).tocoo() for e0 in range(0, E, ASSEMBLY_CHUNK)]
+        r = np.concatenate([q.row for q in parts])
+        c = np.concatenate([q.col for q in parts])
+        v = np.concatenate([q.data for q in parts])
+        del parts
+        K = sp.coo_matrix((v, (r, c)), shape=(ntot, ntot)).tocsr()
     K.sort_indices()
+    vd = (3 * mesh.elem_node[:, :, None] + np.arange(3)[None, None, :]).reshape(E, 81)
     L = load_table()
     F = np.zeros(ntot)
     fe = (0.5 * h) ** 3 * L[:, None] * np.asarray(f, dtype=np.float64)[None, :]   # (a, i)

@@ -72,3 +72,14 @@ def test_die_generator_recipe():
     assert np.all(P.elem_pdof >= 0)
     again = die_problem(16, 8, 8, seed=0, levels=3)
     assert np.array_equal(again.val, P.val) and np.array_equal(again.b, P.b)
+
+
+def test_chunked_assembly_keeps_pattern_and_values(monkeypatch):
+    """Large meshes are assembled in element chunks: same pattern (explicit zeros kept), same values to rounding."""
+    import harness.assemble as A
+    P0 = die_problem(8, 4, 4, seed=2, levels=2)
+    monkeypatch.setattr(A, "ASSEMBLY_CHUNK", 37)
+    P1 = die_problem(8, 4, 4, seed=2, levels=2)
+    assert np.array_equal(P0.rowptr, P1.rowptr) and np.array_equal(P0.col, P1.col)
+    assert np.abs(P0.val - P1.val).max() <= 8 * np.finfo(np.float64).eps * np.abs(P0.val).max()
+    assert np.array_equal(P0.b, P1.b)
