@@ -115,6 +115,23 @@ def test_spmv_matches_cpu_product(gd):
     assert np.all(np.abs(y - ref) <= 2.0 * L * np.finfo(np.float64).eps * scale)
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-3)])
+def test_apply_parity_blocks_of_order_2295(gd, precision, tol):
+    """3^3-voxel parts: the interior part's block (order 2295) is taller than any register panel in FP64
+    (global-memory panel) and takes the half-width register panels in FP32."""
+    P = cached(("gpu", "cube9_b3_L2"), lambda: unit_cube_problem(n=9, block=3, levels=2))
+    H = cached(("orc", "cube9_b3_L2"), lambda: oracle.setup(P))
+    _say("apply", precision, "cube9_b3_L2 n =", P.n)
+    with gd.Context(P, precision=precision) as ctx:
+        assert ctx.stats()["max_ni"][0] == 2295
+        r = random_vector(P.n, 6)
+        z = ctx.apply(_dev(r)).cpu().numpy()
+    zo = oracle.apply(H, r)
+    err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+    _say("  rel err", err)
+    assert err <= tol
+
+
 def _tall():
     return {
         # coarsest order 1943: panels of 1537..2048 rows go through the half-width register panels
