@@ -410,6 +410,7 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
   b.tiles_inner = d_tiles_inner;
   b.total_outer = tiles.total_outer.data();
   b.total_inner = tiles.total_inner.data();
+  b.ut = A.alloc_n<T>((size_t)64 * L.sum_n);
   lu_batched<T>(b, blocks, s);
   L.perm = A.alloc_n<int>((size_t)L.sum_n);
   lu_build_perm(b, L.perm, s);
@@ -515,6 +516,7 @@ CsrDev coarse_level(gdsw_ctx* C, Level& L, hipStream_t s, std::vector<int64_t>& 
   b.tiles_inner = d_itiles_inner;
   b.total_outer = itiles.total_outer.data();
   b.total_inner = itiles.total_inner.data();
+  b.ut = A.alloc_n<T>((size_t)64 * m.inter.size());
   lu_batched<T>(b, aii, s);
   T* phi;
   if (sizeof(T) == sizeof(double)) {
@@ -583,6 +585,7 @@ void coarsest_inverse(gdsw_ctx* C, const CsrDev& K, hipStream_t s, double** dens
   b.piv = piv;
   b.poff = d_off;
   b.info = info;
+  b.ut = A.alloc_n<double>((size_t)64 * n);
   lu_batched<double>(b, D, s);
   double* X = A.alloc_n<double>((size_t)n * n);
   // the inverse is kept by rows, so the per-apply GEMV reads rows contiguously

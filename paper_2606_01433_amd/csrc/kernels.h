@@ -29,6 +29,10 @@ struct LuBatch {
   const int64_t* tiles_inner = nullptr;
   const int64_t* total_outer = nullptr;
   const int64_t* total_inner = nullptr;
+  // Optional device scratch of 64 * (sum of orders) elements of the batch's type
+  // (matrix i at 64 * poff[i]): each outer step's U12 rows are also written there
+  // row-major, so the trailing update reads them with coalesced loads.
+  void* ut = nullptr;
 };
 
 // Host-built update tile tables of a batch with orders dims[0..count).

@@ -110,7 +110,9 @@ __device__ __forceinline__ void gemm_sub_tile(T* __restrict__ C, int64_t ldc, co
 // fragments for all K straight into registers and prefetches its C values,
 // so every load is in flight before the MFMA chain starts.  Same transposed
 // product and C layout as gemm_sub_tile.
-template <typename T, int KMAX>
+// B_ROWS: B is stored by rows (B[k][c] at B[c + k * ldb]), so the 16 lanes of
+// a lane group read 16 consecutive values of one row.
+template <typename T, int KMAX, bool B_ROWS = false>
 __device__ __forceinline__ void gemm_sub_tile_direct(T* __restrict__ C, int64_t ldc, const T* __restrict__ A,
                                                      int64_t lda, const T* __restrict__ B, int64_t ldb, int M, int N,
                                                      int K, int ty, int tx) {
@@ -132,7 +134,7 @@ __device__ __forceinline__ void gemm_sub_tile_direct(T* __restrict__ C, int64_t 
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
       const int c = cbase + cb * 16 + li;
-      bv[st][cb] = (c < N && k < K) ? B[k + (int64_t)c * ldb] : T(0);
+      bv[st][cb] = (c < N && k < K) ? (B_ROWS ? B[c + (int64_t)k * ldb] : B[k + (int64_t)c * ldb]) : T(0);
     }
   }
   T cv[2][2][4];
@@ -557,7 +559,8 @@ template <typename T, int NB>
 __global__ __launch_bounds__(TRSM_COLS) void k_lu_outer_swap_trsm(T* __restrict__ Ab, const int64_t* __restrict__ off,
                                                                   const int* __restrict__ dim,
                                                                   const int* __restrict__ pivb,
-                                                                  const int64_t* __restrict__ poff, int k, int pad) {
+                                                                  const int64_t* __restrict__ poff, int k, int pad,
+                                                                  T* __restrict__ ut) {
   constexpr int KW = 2 * NB;
   const int i = blockIdx.x;
   const int n = dim[i];
@@ -594,15 +597,23 @@ __global__ __launch_bounds__(TRSM_COLS) void k_lu_outer_swap_trsm(T* __restrict_
     for (int r = j + 1; r < KW; ++r) x[r] -= L11[r + j * KW] * x[j];
 #pragma unroll
   for (int r = 0; r < KW; ++r) col[k + r] = x[r];
+  if (ut) {                                 // U12 by rows: row r of length n - k - KW
+    const int M = n - k - KW;
+    T* u = ut + 64 * poff[i] + (c - k - KW);
+#pragma unroll
+    for (int r = 0; r < KW; ++r) u[(int64_t)r * M] = x[r];
+  }
 }
 
 // A[r0:n, c0:c1) -= A[r0:n, k:k+kw) * A[k:k+kw, c0:c1), r0 = k + kw (64x64 MFMA tiles).
 // inner = 1: kw = NB, c0 = k+NB, c1 = k+2NB (sub-panel 2 before its factorization);
 // inner = 0: kw = 2NB, c0 = k+2NB, c1 = n (trailing matrix).
+// ut (outer steps only, may be null): the step's U12 by rows at 64 * poff[i].
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void k_lu_update(T* __restrict__ Ab, const int64_t* __restrict__ off,
                                                    const int* __restrict__ dim, int k, int inner, int tiles_m,
-                                                   int tiles_n, const int64_t* __restrict__ tab, int count, int pad) {
+                                                   int tiles_n, const int64_t* __restrict__ tab, int count, int pad,
+                                                   const T* __restrict__ ut, const int64_t* __restrict__ poff) {
   const int w = (int)xcd_remap(blockIdx.x, gridDim.x);
   int i, tl;
   if (tab) {                                // compact grid: tab[i] = first tile of matrix i
@@ -625,8 +636,12 @@ __global__ __launch_bounds__(256) void k_lu_update(T* __restrict__ Ab, const int
   if (ty * TILE >= M || tx * TILE >= N) return;
   const int ld = lead_dim(n, pad);
   T* A = Ab + off[i];
-  gemm_sub_tile_direct<T, 2 * NB>(A + r0 + (int64_t)c0 * ld, ld, A + r0 + (int64_t)k * ld, ld, A + k + (int64_t)c0 * ld,
-                                  ld, M, N, kw, ty, tx);
+  if (!inner && ut)
+    gemm_sub_tile_direct<T, 2 * NB, true>(A + r0 + (int64_t)c0 * ld, ld, A + r0 + (int64_t)k * ld, ld,
+                                          ut + 64 * poff[i], N, M, N, kw, ty, tx);
+  else
+    gemm_sub_tile_direct<T, 2 * NB>(A + r0 + (int64_t)c0 * ld, ld, A + r0 + (int64_t)k * ld, ld,
+                                    A + k + (int64_t)c0 * ld, ld, M, N, kw, ty, tx);
 }
 
 // mode 0: LU trailing update; 1: forward-solve update of X; 2: backward-solve update of X.
@@ -929,7 +944,7 @@ void launch_panel_split(const LuBatch& b, T* A, int k, hipStream_t s) {
   GDSW_LAUNCH_CHECK();
   const int tm = (int)blocks_for(b.max_n - k - H, TILE);
   hipLaunchKernelGGL((k_lu_update<T, H>), dim3((unsigned)((int64_t)b.count * tm)), dim3(256), 0, s, A, b.off, b.dim,
-                     k, 1, tm, 1, nullptr, b.count, b.pad);
+                     k, 1, tm, 1, nullptr, b.count, b.pad, nullptr, nullptr);
   GDSW_LAUNCH_CHECK();
   hipLaunchKernelGGL((k_lu_panel_rot<T, H, 512, R>), dim3(b.count), dim3(512), 0, s, A, b.off, b.dim, b.piv, b.poff,
                      b.info, k + H, b.pad);
@@ -1003,6 +1018,7 @@ void LuTiles::build(const int* dims, int count) {
 template <typename T>
 void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
   constexpr int NB = LU_NB;
+  T* ut = static_cast<T*>(b.ut);
   auto panel = [&](int k) {
     const int rows = b.max_n - k;
     const bool tall = rows > panel_reg_rows<T>();
@@ -1024,7 +1040,8 @@ void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
       const int64_t grid = b.tiles_inner ? b.total_inner[st] : (int64_t)b.count * tm;
       if (grid > 0) {
         hipLaunchKernelGGL((k_lu_update<T, NB>), dim3((unsigned)grid), dim3(256), 0, s, A, b.off, b.dim, k, 1, tm, 1,
-                           b.tiles_inner ? b.tiles_inner + (size_t)st * (b.count + 1) : nullptr, b.count, b.pad);
+                           b.tiles_inner ? b.tiles_inner + (size_t)st * (b.count + 1) : nullptr, b.count, b.pad,
+                           nullptr, nullptr);
         GDSW_LAUNCH_CHECK();
       }
       panel(k + NB);
@@ -1035,14 +1052,15 @@ void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
     const int rest = b.max_n - k - 2 * NB;
     if (rest > 0) {
       hipLaunchKernelGGL((k_lu_outer_swap_trsm<T, NB>), dim3(b.count, blocks_for(rest, TRSM_COLS)), dim3(TRSM_COLS), 0,
-                         s, A, b.off, b.dim, b.piv, b.poff, k, b.pad);
+                         s, A, b.off, b.dim, b.piv, b.poff, k, b.pad, ut);
       GDSW_LAUNCH_CHECK();
       const int t = (int)blocks_for(rest, TILE);
       const int st = k / (2 * NB);
       const int64_t grid = b.tiles_outer ? b.total_outer[st] : (int64_t)b.count * t * t;
       if (grid > 0) {
         hipLaunchKernelGGL((k_lu_update<T, NB>), dim3((unsigned)grid), dim3(256), 0, s, A, b.off, b.dim, k, 0, t, t,
-                           b.tiles_outer ? b.tiles_outer + (size_t)st * (b.count + 1) : nullptr, b.count, b.pad);
+                           b.tiles_outer ? b.tiles_outer + (size_t)st * (b.count + 1) : nullptr, b.count, b.pad,
+                           static_cast<const T*>(ut), b.poff);
         GDSW_LAUNCH_CHECK();
       }
     }
