@@ -325,7 +325,7 @@ constexpr int NO_ROW = 0x7fffffff;
 // column loop (pivot indices and the singularity flag are written after it),
 // so the barriers never wait on global stores.
 template <typename T, int NB, int NT, int R>
-__global__ __launch_bounds__(NT) void k_lu_panel_rot(T* __restrict__ Ab, const int64_t* __restrict__ off,
+__global__ __launch_bounds__(NT, (sizeof(T) == 8 && NT == 256 && R == 3) ? 2 : 1) void k_lu_panel_rot(T* __restrict__ Ab, const int64_t* __restrict__ off,
                                                      const int* __restrict__ dim, int* __restrict__ pivb,
                                                      const int64_t* __restrict__ poff, int* __restrict__ info,
                                                      int k, int pad) {
