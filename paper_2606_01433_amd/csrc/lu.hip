@@ -932,10 +932,10 @@ __global__ __launch_bounds__(512) void k_inverse_resident(const T* __restrict__ 
 // interchanges and unit-lower solve on half 2's top rows; half 2 minus the
 // rank-NB/2 product; half 2; half 2's interchanges on half 1.  The result (factors
 // and pivots of the NB columns) is that of the NB-wide panel.
-template <typename T, int R>
+template <typename T, int NT, int R>
 void launch_panel_split(const LuBatch& b, T* A, int k, hipStream_t s) {
   constexpr int H = LU_NB / 2;
-  hipLaunchKernelGGL((k_lu_panel_rot<T, H, 512, R>), dim3(b.count), dim3(512), 0, s, A, b.off, b.dim, b.piv, b.poff,
+  hipLaunchKernelGGL((k_lu_panel_rot<T, H, NT, R>), dim3(b.count), dim3(NT), 0, s, A, b.off, b.dim, b.piv, b.poff,
                      b.info, k, b.pad);
   GDSW_LAUNCH_CHECK();
   if (b.max_n <= k + H) return;
@@ -946,7 +946,7 @@ void launch_panel_split(const LuBatch& b, T* A, int k, hipStream_t s) {
   hipLaunchKernelGGL((k_lu_update<T, H>), dim3((unsigned)((int64_t)b.count * tm)), dim3(256), 0, s, A, b.off, b.dim,
                      k, 1, tm, 1, nullptr, b.count, b.pad, nullptr, nullptr);
   GDSW_LAUNCH_CHECK();
-  hipLaunchKernelGGL((k_lu_panel_rot<T, H, 512, R>), dim3(b.count), dim3(512), 0, s, A, b.off, b.dim, b.piv, b.poff,
+  hipLaunchKernelGGL((k_lu_panel_rot<T, H, NT, R>), dim3(b.count), dim3(NT), 0, s, A, b.off, b.dim, b.piv, b.poff,
                      b.info, k + H, b.pad);
   GDSW_LAUNCH_CHECK();
   hipLaunchKernelGGL((k_lu_swap_cols<T>), dim3(b.count, 1), dim3(64), 0, s, A, b.off, b.dim, b.piv, b.poff, k + H, H,
@@ -969,11 +969,23 @@ void launch_panel_rot(const LuBatch& b, T* A, int k, int rows, bool split, hipSt
   GDSW_PANEL(256, 1)
   GDSW_PANEL(256, 2)
   GDSW_PANEL(256, 3)
+  if constexpr (sizeof(T) == 8) {
+    // FP64 panels of 769..1536 rows: half-width register panels that leave room
+    // for two (256 threads) or three (512 threads) wavefronts per SIMD
+    if (split && rows <= 256 * 4) {
+      launch_panel_split<T, 256, 4>(b, A, k, s);
+      return;
+    }
+    if (split && rows <= 512 * 3) {
+      launch_panel_split<T, 512, 3>(b, A, k, s);
+      return;
+    }
+  }
   GDSW_PANEL(512, 2)
   GDSW_PANEL(512, 3)
   if constexpr (sizeof(T) == 8) {
     if (split && rows <= 512 * 4) {
-      launch_panel_split<T, 4>(b, A, k, s);
+      launch_panel_split<T, 512, 4>(b, A, k, s);
       return;
     }
     GDSW_PANEL(1024, 2)
@@ -981,7 +993,7 @@ void launch_panel_rot(const LuBatch& b, T* A, int k, int rows, bool split, hipSt
   if constexpr (sizeof(T) == 4) {
     GDSW_PANEL(512, 4)
     if (split && rows <= 512 * 6) {
-      launch_panel_split<T, 6>(b, A, k, s);
+      launch_panel_split<T, 512, 6>(b, A, k, s);
       return;
     }
     GDSW_PANEL(512, 6)
