@@ -588,15 +588,39 @@ __global__ __launch_bounds__(TRSM_COLS) void k_lu_outer_swap_trsm(T* __restrict_
       col[p] = t;
     }
   }
+  // padded columns (pad > 1: 128-byte aligned) move their 64 values in 16-byte pieces
+  constexpr int V = 16 / sizeof(T);
+  typedef T vec __attribute__((ext_vector_type(V)));
   T x[KW];
+  if (pad > 1) {
+    const vec* src = reinterpret_cast<const vec*>(col + k);
 #pragma unroll
-  for (int r = 0; r < KW; ++r) x[r] = col[k + r];
+    for (int r = 0; r < KW / V; ++r) {
+      const vec v = src[r];
+#pragma unroll
+      for (int e = 0; e < V; ++e) x[V * r + e] = v[e];
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < KW; ++r) x[r] = col[k + r];
+  }
 #pragma unroll
   for (int j = 0; j < KW; ++j)
 #pragma unroll
     for (int r = j + 1; r < KW; ++r) x[r] -= L11[r + j * KW] * x[j];
+  if (pad > 1) {
+    vec* dst = reinterpret_cast<vec*>(col + k);
 #pragma unroll
-  for (int r = 0; r < KW; ++r) col[k + r] = x[r];
+    for (int r = 0; r < KW / V; ++r) {
+      vec v;
+#pragma unroll
+      for (int e = 0; e < V; ++e) v[e] = x[V * r + e];
+      dst[r] = v;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < KW; ++r) col[k + r] = x[r];
+  }
   if (ut) {                                 // U12 by rows: row r of length n - k - KW
     const int M = n - k - KW;
     T* u = ut + 64 * poff[i] + (c - k - KW);
