@@ -2,9 +2,15 @@
 // that the recursion of section 2.2 works on.  Integer graph work only.
 #include "maps.h"
 
+#include <unistd.h>
+
 #include <algorithm>
 #include <atomic>
+#include <condition_variable>
+#include <cstdint>
 #include <cstdlib>
+#include <functional>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <thread>
@@ -22,6 +28,70 @@ int host_threads() {
   return (int)std::max(1u, std::min(16u, hw));
 }
 
+// Process-wide worker threads for parallel_for (creating and joining threads
+// per call costs a few hundred microseconds, and a setup makes dozens of calls).
+// One caller at a time: run() returns false while another thread uses the pool.
+// The pool is never destroyed (its threads live until the process ends); a
+// forked child builds its own.
+class HostPool {
+ public:
+  static HostPool* get(int workers) {
+    static std::mutex mk;
+    static HostPool* pool = nullptr;
+    static pid_t owner = 0;
+    std::lock_guard<std::mutex> lk(mk);
+    if (!pool || owner != getpid()) {
+      pool = new HostPool(workers);
+      owner = getpid();
+    }
+    return pool;
+  }
+  // work(t) for t in [0, nthreads) (the caller runs t = 0); false if busy
+  bool run(int nthreads, const std::function<void(int)>& work) {
+    std::unique_lock<std::mutex> busy(busy_, std::try_to_lock);
+    if (!busy.owns_lock()) return false;
+    const int want = std::min(nthreads, (int)workers_.size() + 1);
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      job_ = &work;
+      want_ = want;
+      pending_ = want - 1;
+      ++gen_;
+    }
+    cv_.notify_all();
+    work(0);
+    std::unique_lock<std::mutex> lk(m_);
+    done_.wait(lk, [&] { return pending_ == 0; });
+    job_ = nullptr;
+    return true;
+  }
+
+ private:
+  explicit HostPool(int workers) {
+    for (int t = 1; t <= workers; ++t) workers_.emplace_back([this, t] { loop(t); });
+  }
+  void loop(int id) {
+    uint64_t seen = 0;
+    std::unique_lock<std::mutex> lk(m_);
+    for (;;) {
+      cv_.wait(lk, [&] { return gen_ != seen; });
+      seen = gen_;
+      if (id >= want_) continue;
+      const std::function<void(int)>* job = job_;
+      lk.unlock();
+      (*job)(id);
+      lk.lock();
+      if (--pending_ == 0) done_.notify_one();
+    }
+  }
+  std::mutex busy_, m_;
+  std::condition_variable cv_, done_;
+  std::vector<std::thread> workers_;
+  const std::function<void(int)>* job_ = nullptr;
+  uint64_t gen_ = 0;
+  int want_ = 0, pending_ = 0;
+};
+
 // f(thread, begin, end) over [0, n) in dynamically scheduled chunks.
 template <typename F>
 void parallel_for(int n, int nthreads, F f) {
@@ -32,13 +102,14 @@ void parallel_for(int n, int nthreads, F f) {
   }
   std::atomic<int> next(0);
   const int chunk = std::max(8, n / (nthreads * 8));
-  auto work = [&](int t) {
+  const std::function<void(int)> work = [&](int t) {
     for (;;) {
       const int b = next.fetch_add(chunk);
       if (b >= n) break;
       f(t, b, std::min(n, b + chunk));
     }
   };
+  if (HostPool::get(host_threads() - 1)->run(nthreads, work)) return;
   std::vector<std::thread> pool;
   for (int t = 1; t < nthreads; ++t) pool.emplace_back(work, t);
   work(0);
