@@ -150,20 +150,16 @@ void parallel_copy(char* dst, const char* src, size_t n) {
     return;
   }
   const size_t pieces = (n + PIECE - 1) / PIECE;
-  const int nt = (int)std::min<size_t>(pieces, std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
+  const int nt = (int)std::min<size_t>(pieces, (size_t)host_thread_count());
   std::atomic<size_t> next(0);
-  auto work = [&] {
+  host_parallel(nt, [&](int) {
     for (;;) {
       const size_t k = next.fetch_add(1);
       if (k >= pieces) break;
       const size_t o = k * PIECE;
       std::memcpy(dst + o, src + o, std::min(PIECE, n - o));
     }
-  };
-  std::vector<std::thread> pool;
-  for (int t = 1; t < nt; ++t) pool.emplace_back(work);
-  work();
-  for (auto& th : pool) th.join();
+  });
 }
 
 struct Level {

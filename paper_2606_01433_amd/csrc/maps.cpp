@@ -157,6 +157,21 @@ bool same_set(const LevelMaps& m, int u, int v) {
 
 }  // namespace
 
+void host_parallel(int nthreads, const std::function<void(int)>& work) {
+  nthreads = std::max(1, std::min(nthreads, host_threads()));
+  if (nthreads == 1) {
+    work(0);
+    return;
+  }
+  if (HostPool::get(host_threads() - 1)->run(nthreads, work)) return;
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nthreads; ++t) pool.emplace_back(work, t);
+  work(0);
+  for (auto& th : pool) th.join();
+}
+
+int host_thread_count() { return host_threads(); }
+
 std::string build_level1_mesh(int64_t n, int n_nodes, const int* node_dof, int n_elem,
                               const int* elem_node, const int* elem_pdof, const int* elem_part,
                               int n_parts, LevelMesh& out) {

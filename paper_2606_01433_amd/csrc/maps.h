@@ -8,6 +8,7 @@
 #pragma once
 #include <cstdint>
 #include <string>
+#include <functional>
 #include <vector>
 
 namespace gdsw {
@@ -89,6 +90,12 @@ std::string build_next_mesh(const LevelMesh& mesh, const LevelMaps& m, const int
 // Sparsity of A_0 = Phi^T K Phi: row c holds the union of the column lists
 // of the parts that hold column c.
 void coarse_pattern(const LevelMaps& m, std::vector<int64_t>& rowptr, std::vector<int>& col);
+
+// work(t) for t in [0, nthreads) on the process-wide host worker threads (the
+// caller runs t = 0), or on threads created for this call while another caller
+// holds them.  nthreads is capped by the host thread count.
+void host_parallel(int nthreads, const std::function<void(int)>& work);
+int host_thread_count();
 
 // Combination lists of the local solutions: additive lists every position of
 // dof g over all domains (sc_ptr / sc_pos, ascending position); restricted
