@@ -1387,14 +1387,15 @@ size_t gdsw_footprint_bytes(const gdsw_problem* prob, const gdsw_options* opt) {
         n2 += ni * (size_t)gdsw::lead_dim((int)ni, (int)(128 / s));
         sn += ni;
       }
-      total += n2 * s + sn * 24;
+      // factors, pivots / gather / local vectors, and the U12 scratch of the factorization
+      total += n2 * s + sn * 24 + 64 * sn * s;
       size_t phi = 0;
       for (size_t i = 0; i < N; ++i)
         phi += (size_t)(m.int_ptr[i + 1] - m.int_ptr[i]) * (size_t)(m.pc_ptr[i + 1] - m.pc_ptr[i]);
-      total += phi * (s + 8) + m.owner.size() * 24;
+      total += phi * (s + 8) + m.owner.size() * 24 + 64 * m.inter.size() * s;
       n_last = (size_t)m.n_coarse;
     }
-    if (P.coarsest) total += 2 * n_last * n_last * 8;
+    if (P.coarsest) total += 2 * n_last * n_last * 8 + 64 * n_last * 8;
     const size_t n = (size_t)prob->n;
     total += (size_t)(o.restart * 2 + 4) * n * 8;
     return total;
