@@ -254,6 +254,8 @@ struct gdsw_ctx {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::vector<hipGraphExec_t> apply_exec;
   bool capturing = false;
+  // device scratch needed only during setup (returned to the block cache at its end)
+  std::vector<void*> setup_scratch;
   // page-locked staging buffers held while uploads may be in flight
   std::vector<std::pair<void*, size_t>> pinned;
   void release_pinned() {
@@ -407,6 +409,7 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
   b.total_outer = tiles.total_outer.data();
   b.total_inner = tiles.total_inner.data();
   b.ut = A.alloc_n<T>((size_t)64 * L.sum_n);
+  C->setup_scratch.push_back(b.ut);
   lu_batched<T>(b, blocks, s);
   L.perm = A.alloc_n<int>((size_t)L.sum_n);
   lu_build_perm(b, L.perm, s);
@@ -513,6 +516,7 @@ CsrDev coarse_level(gdsw_ctx* C, Level& L, hipStream_t s, std::vector<int64_t>& 
   b.total_outer = itiles.total_outer.data();
   b.total_inner = itiles.total_inner.data();
   b.ut = A.alloc_n<T>((size_t)64 * m.inter.size());
+  C->setup_scratch.push_back(b.ut);
   lu_batched<T>(b, aii, s);
   T* phi;
   if (sizeof(T) == sizeof(double)) {
@@ -582,6 +586,7 @@ void coarsest_inverse(gdsw_ctx* C, const CsrDev& K, hipStream_t s, double** dens
   b.poff = d_off;
   b.info = info;
   b.ut = A.alloc_n<double>((size_t)64 * n);
+  C->setup_scratch.push_back(b.ut);
   lu_batched<double>(b, D, s);
   double* X = A.alloc_n<double>((size_t)n * n);
   // the inverse is kept by rows, so the per-apply GEMV reads rows contiguously
@@ -791,6 +796,8 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
   GDSW_HIP(hipStreamSynchronize(s));
   GDSW_HIP(hipStreamSynchronize(C->up));
   C->release_pinned();
+  for (void* p : C->setup_scratch) C->arena.free_one(p);
+  C->setup_scratch.clear();
   for (const Level& L : C->levels) {
     check_info(L.info, L.nparts, "local block", L.index, s);
     if (L.has_coarse) {
