@@ -531,8 +531,11 @@ CsrDev coarse_level(gdsw_ctx* C, Level& L, hipStream_t s, std::vector<int64_t>& 
   double* W = A.alloc_n<double>((size_t)phi_tot);
   double* V = A.alloc_n<double>((size_t)v_tot);
   double* Cm = A.alloc_n<double>((size_t)c_tot);
+  T* phit = A.alloc_n<T>((size_t)std::max<int64_t>(phi_tot, 1));
+  C->setup_scratch.push_back(phit);
   galerkin_wv<T>(L.K, N, (int64_t)m.inter.size(), (int64_t)m.z_dof.size(), L.int_ptr, L.inter, L.dof_ipart,
-                 L.dof_irow, L.dof_gcol, L.pc_ptr, L.pcols, L.phi_off, phi, z_ptr, z_dof, d_v_off, W, V, bad, s);
+                 L.dof_irow, L.dof_gcol, L.pc_ptr, L.pcols, L.phi_off, phi, phit, z_ptr, z_dof, d_v_off, W, V, bad,
+                 s);
   galerkin_local<T>(N, (int64_t)m.pcols.size(), L.int_ptr, L.pc_ptr, L.phi_off, phi, W, z_ptr, z_lc, d_v_off, V,
                     d_c_off, Cm, s);
   // sparsity of the coarse operator, built on the host while the kernels above run

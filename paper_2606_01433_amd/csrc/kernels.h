@@ -76,10 +76,12 @@ void extract_interior(const CsrDev& K, int nparts, int64_t total_rows, const int
 void make_gather_index(int nparts, int64_t total, const int64_t* dom_ptr, const int* dom, const int* perm,
                        int* gidx, hipStream_t s);
 // Galerkin pieces of part i: W = K[I_i, :] Phi (|I_i| x m_i), V = K[Z_i, I_i] Phi_I (|Z_i| x m_i).
+// phit: scratch of the size of phi; it receives Phi_I by rows (part i at phi_off[i], row length m_i),
+// which the two products read.
 template <typename T>
 void galerkin_wv(const CsrDev& K, int nparts, int64_t total_irows, int64_t total_zrows, const int64_t* int_ptr,
                  const int* inter, const int* dof_ipart, const int* dof_irow, const int* dof_gcol,
-                 const int64_t* pc_ptr, const int* pcols, const int64_t* phi_off, const T* phi,
+                 const int64_t* pc_ptr, const int* pcols, const int64_t* phi_off, const T* phi, T* phit,
                  const int64_t* z_ptr, const int* z_dof, const int64_t* v_off, double* W, double* V,
                  int* bad, hipStream_t s);
 // C_i = Phi_I^T W + (V rows summed into their columns), m_i x m_i, column-major.

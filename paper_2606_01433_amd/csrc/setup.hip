@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void k_galerkin_w(CsrDev K, int nparts, int64_
                                                     const int* __restrict__ dof_irow,
                                                     const int* __restrict__ dof_gcol,
                                                     const int64_t* __restrict__ pc_ptr, const int* __restrict__ pcols,
-                                                    const int64_t* __restrict__ phi_off, const T* __restrict__ phi,
+                                                    const int64_t* __restrict__ phi_off, const T* __restrict__ phit,
                                                     double* __restrict__ W, int* __restrict__ bad) {
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= total_rows) return;
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void k_galerkin_w(CsrDev K, int nparts, int64_
   const int g = inter[row];
   const int m = (int)(pc_ptr[i + 1] - pc_ptr[i]);
   const int* pc = pcols + pc_ptr[i];
-  const T* ph = phi + phi_off[i];
+  const T* ph = phit + phi_off[i];           // Phi_I of the part by rows
   double* Wp = W + phi_off[i];
   const int64_t e_beg = K.rowptr[g], e_end = K.rowptr[g + 1];
   for (int c0 = 0; c0 < m; c0 += 64) {
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(256) void k_galerkin_w(CsrDev K, int nparts, int64_
         const double vl = lane_value(v, l);
         const int irl = lane_value(ir, l);
         if (irl >= 0) {
-          if (c < m) acc += vl * (double)ph[irl + (int64_t)c * nI];
+          if (c < m) acc += vl * (double)ph[(int64_t)irl * m + c];
         } else if (lane_value(lc, l) == c) {
           acc += vl;
         }
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void k_galerkin_v(CsrDev K, int nparts, int64_
                                                     const int* __restrict__ dof_ipart,
                                                     const int* __restrict__ dof_irow,
                                                     const int64_t* __restrict__ pc_ptr,
-                                                    const int64_t* __restrict__ phi_off, const T* __restrict__ phi,
+                                                    const int64_t* __restrict__ phi_off, const T* __restrict__ phit,
                                                     const int64_t* __restrict__ v_off, double* __restrict__ V) {
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= total_rows) return;
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void k_galerkin_v(CsrDev K, int nparts, int64_
   const int g = z_dof[row];
   const int nI = (int)(int_ptr[i + 1] - int_ptr[i]);
   const int m = (int)(pc_ptr[i + 1] - pc_ptr[i]);
-  const T* ph = phi + phi_off[i];
+  const T* ph = phit + phi_off[i];           // Phi_I of the part by rows
   double* Vp = V + v_off[i];
   const int64_t e_beg = K.rowptr[g], e_end = K.rowptr[g + 1];
   for (int c0 = 0; c0 < m; c0 += 64) {
@@ -208,10 +208,28 @@ __global__ __launch_bounds__(256) void k_galerkin_v(CsrDev K, int nparts, int64_
       const int cnt = (int)min((int64_t)64, e_end - e0);
       for (int l = 0; l < cnt; ++l) {
         const int irl = lane_value(ir, l);
-        if (irl >= 0 && c < m) acc += lane_value(v, l) * (double)ph[irl + (int64_t)c * nI];
+        if (irl >= 0 && c < m) acc += lane_value(v, l) * (double)ph[(int64_t)irl * m + c];
       }
     }
     if (c < m) Vp[t + (int64_t)c * nZ] = acc;
+  }
+}
+
+// Phi_I of part i (|I_i| x m_i, by columns) copied by rows; one workgroup per part.
+template <typename T>
+__global__ __launch_bounds__(256) void k_phi_rows(const int64_t* __restrict__ int_ptr,
+                                                  const int64_t* __restrict__ pc_ptr,
+                                                  const int64_t* __restrict__ phi_off, const T* __restrict__ phi,
+                                                  T* __restrict__ phit) {
+  const int i = blockIdx.x;
+  const int nI = (int)(int_ptr[i + 1] - int_ptr[i]);
+  const int m = (int)(pc_ptr[i + 1] - pc_ptr[i]);
+  const T* src = phi + phi_off[i];
+  T* dst = phit + phi_off[i];
+  const int64_t total = (int64_t)nI * m;
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const int r = (int)(e / m), c = (int)(e - (int64_t)r * m);
+    dst[e] = src[r + (int64_t)c * nI];
   }
 }
 
@@ -386,18 +404,22 @@ void make_gather_index(int nparts, int64_t total, const int64_t* dom_ptr, const 
 template <typename T>
 void galerkin_wv(const CsrDev& K, int nparts, int64_t total_irows, int64_t total_zrows, const int64_t* int_ptr,
                  const int* inter, const int* dof_ipart, const int* dof_irow, const int* dof_gcol,
-                 const int64_t* pc_ptr, const int* pcols, const int64_t* phi_off, const T* phi,
+                 const int64_t* pc_ptr, const int* pcols, const int64_t* phi_off, const T* phi, T* phit,
                  const int64_t* z_ptr, const int* z_dof, const int64_t* v_off, double* W, double* V,
                  int* bad, hipStream_t s) {
+  if (nparts > 0) {
+    hipLaunchKernelGGL((k_phi_rows<T>), dim3(nparts), dim3(256), 0, s, int_ptr, pc_ptr, phi_off, phi, phit);
+    GDSW_LAUNCH_CHECK();
+  }
   if (total_irows > 0) {
     hipLaunchKernelGGL((k_galerkin_w<T>), dim3(blocks_for(total_irows, 4)), dim3(256), 0, s, K, nparts,
-                       total_irows, int_ptr, inter, dof_ipart, dof_irow, dof_gcol, pc_ptr, pcols, phi_off, phi, W,
+                       total_irows, int_ptr, inter, dof_ipart, dof_irow, dof_gcol, pc_ptr, pcols, phi_off, phit, W,
                        bad);
     GDSW_LAUNCH_CHECK();
   }
   if (total_zrows > 0) {
     hipLaunchKernelGGL((k_galerkin_v<T>), dim3(blocks_for(total_zrows, 4)), dim3(256), 0, s, K, nparts,
-                       total_zrows, z_ptr, z_dof, int_ptr, dof_ipart, dof_irow, pc_ptr, phi_off, phi, v_off, V);
+                       total_zrows, z_ptr, z_dof, int_ptr, dof_ipart, dof_irow, pc_ptr, phi_off, phit, v_off, V);
     GDSW_LAUNCH_CHECK();
   }
 }
@@ -453,10 +475,10 @@ template void extract_interior<float>(const CsrDev&, int, int64_t, const int64_t
                                       const int*, const int*, const int64_t*, const int*, const int64_t*, float*,
                                       const int64_t*, double*, int*, hipStream_t);
 template void galerkin_wv<double>(const CsrDev&, int, int64_t, int64_t, const int64_t*, const int*, const int*,
-                                  const int*, const int*, const int64_t*, const int*, const int64_t*, const double*,
+                                  const int*, const int*, const int64_t*, const int*, const int64_t*, const double*, double*,
                                   const int64_t*, const int*, const int64_t*, double*, double*, int*, hipStream_t);
 template void galerkin_wv<float>(const CsrDev&, int, int64_t, int64_t, const int64_t*, const int*, const int*,
-                                 const int*, const int*, const int64_t*, const int*, const int64_t*, const float*,
+                                 const int*, const int*, const int64_t*, const int*, const int64_t*, const float*, float*,
                                  const int64_t*, const int*, const int64_t*, double*, double*, int*, hipStream_t);
 template void galerkin_local<double>(int, int64_t, const int64_t*, const int64_t*, const int64_t*, const double*,
                                      const double*, const int64_t*, const int*, const int64_t*, const double*,
