@@ -75,7 +75,8 @@ void extract_interior(const CsrDev& K, int nparts, int64_t total_rows, const int
 // gidx[k] = D_i[perm_i[a]] for the pivoted gather of the local solves.
 void make_gather_index(int nparts, int64_t total, const int64_t* dom_ptr, const int* dom, const int* perm,
                        int* gidx, hipStream_t s);
-// Galerkin pieces of part i: W = K[I_i, :] Phi (|I_i| x m_i), V = K[Z_i, I_i] Phi_I (|Z_i| x m_i).
+// Galerkin pieces of part i: W = K[I_i, :] Phi (|I_i| x m_i), V = K[Z_i, I_i] Phi_I (|Z_i| x m_i),
+// both stored by rows (row length m_i).
 // phit: scratch of the size of phi; it receives Phi_I by rows (part i at phi_off[i], row length m_i),
 // which the two products read.
 template <typename T>

@@ -126,7 +126,6 @@ __global__ __launch_bounds__(256) void k_galerkin_w(CsrDev K, int nparts, int64_
   const int lane = threadIdx.x & 63;
   const int i = segment_of(int_ptr, nparts, row);
   const int64_t base = int_ptr[i];
-  const int nI = (int)(int_ptr[i + 1] - base);
   const int a = (int)(row - base);
   const int g = inter[row];
   const int m = (int)(pc_ptr[i + 1] - pc_ptr[i]);
@@ -164,7 +163,7 @@ __global__ __launch_bounds__(256) void k_galerkin_w(CsrDev K, int nparts, int64_
         }
       }
     }
-    if (c < m) Wp[a + (int64_t)c * nI] = acc;
+    if (c < m) Wp[(int64_t)a * m + c] = acc;
   }
 }
 
@@ -183,10 +182,8 @@ __global__ __launch_bounds__(256) void k_galerkin_v(CsrDev K, int nparts, int64_
   const int lane = threadIdx.x & 63;
   const int i = segment_of(z_ptr, nparts, row);
   const int64_t base = z_ptr[i];
-  const int nZ = (int)(z_ptr[i + 1] - base);
   const int t = (int)(row - base);
   const int g = z_dof[row];
-  const int nI = (int)(int_ptr[i + 1] - int_ptr[i]);
   const int m = (int)(pc_ptr[i + 1] - pc_ptr[i]);
   const T* ph = phit + phi_off[i];           // Phi_I of the part by rows
   double* Vp = V + v_off[i];
@@ -211,7 +208,7 @@ __global__ __launch_bounds__(256) void k_galerkin_v(CsrDev K, int nparts, int64_
         if (irl >= 0 && c < m) acc += lane_value(v, l) * (double)ph[(int64_t)irl * m + c];
       }
     }
-    if (c < m) Vp[t + (int64_t)c * nZ] = acc;
+    if (c < m) Vp[(int64_t)t * m + c] = acc;
   }
 }
 
@@ -264,8 +261,8 @@ __global__ __launch_bounds__(256) void k_galerkin_local(int nparts, int64_t tota
     const int c = c0 + lane;
     if (c >= m) break;
     double acc = 0.0;
-    for (int a = 0; a < nI; ++a) acc += (double)ph[a] * Wp[a + (int64_t)c * nI];
-    for (int t = t0; t < t1; ++t) acc += Vp[t + (int64_t)c * nZ];
+    for (int a = 0; a < nI; ++a) acc += (double)ph[a] * Wp[(int64_t)a * m + c];
+    for (int t = t0; t < t1; ++t) acc += Vp[(int64_t)t * m + c];
     Cp[r + (int64_t)c * m] = acc;
   }
 }
