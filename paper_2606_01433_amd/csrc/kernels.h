@@ -85,7 +85,7 @@ void galerkin_wv(const CsrDev& K, int nparts, int64_t total_irows, int64_t total
                  const int64_t* pc_ptr, const int* pcols, const int64_t* phi_off, const T* phi, T* phit,
                  const int64_t* z_ptr, const int* z_dof, const int64_t* v_off, double* W, double* V,
                  int* bad, hipStream_t s);
-// C_i = Phi_I^T W + (V rows summed into their columns), m_i x m_i, column-major.
+// C_i = Phi_I^T W + (V rows summed into their columns), m_i x m_i, stored by rows.
 template <typename T>
 void galerkin_local(int nparts, int64_t total_crows, const int64_t* int_ptr, const int64_t* pc_ptr,
                     const int64_t* phi_off, const T* phi, const double* W, const int64_t* z_ptr, const int* z_lc,

@@ -263,7 +263,7 @@ __global__ __launch_bounds__(256) void k_galerkin_local(int nparts, int64_t tota
     double acc = 0.0;
     for (int a = 0; a < nI; ++a) acc += (double)ph[a] * Wp[(int64_t)a * m + c];
     for (int t = t0; t < t1; ++t) acc += Vp[(int64_t)t * m + c];
-    Cp[r + (int64_t)c * m] = acc;
+    Cp[(int64_t)r * m + c] = acc;
   }
 }
 
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(64) void k_galerkin_assemble(CsrDev K, const int64_
         const int p = lower_bound_i32(rc, len, pc[l2]);
         if (p < len && rc[p] == pc[l2]) {
           pos = p;
-          v = Ci[lc + (int64_t)l2 * m];
+          v = Ci[(int64_t)lc * m + l2];
         } else {
           *bad = 1;
         }
