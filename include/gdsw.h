@@ -24,8 +24,11 @@
  * caller may free every input after it returns.  A context owns its device
  * memory until gdsw_destroy, which waits for the device to drain and hands
  * the blocks to a process-wide cache (per device, at most 64 GiB) that later
- * setups reuse; cached blocks are released when the process exits.  Calls on
- * one context must not overlap.
+ * setups reuse; cached blocks are released when the process exits (scratch
+ * needed only during setup goes back to that cache when gdsw_setup returns).
+ * The host side of setup runs its parallel loops on worker threads the library
+ * creates once per process (at most 16, GDSW_HOST_THREADS to change); they
+ * stay until the process exits.  Calls on one context must not overlap.
  *
  * Errors: every int-returning call returns one of the GDSW_* codes below;
  * gdsw_last_error() gives a message for the calling thread's last failure.
@@ -234,8 +237,9 @@ int gdsw_plan_levels(gdsw_plan* plan, int32_t* schwarz_levels, int32_t* has_coar
 int gdsw_plan_maps(gdsw_plan* plan, int32_t level, gdsw_maps_view* out);
 void gdsw_plan_destroy(gdsw_plan* plan);
 
-/* Estimated device bytes the context of this problem would hold (for admission
- * control); host-only integer work, no device allocation. Returns 0 on error. */
+/* Estimated peak device bytes of the context of this problem (its setup scratch
+ * included), for admission control; host-only integer work, no device
+ * allocation. Returns 0 on error. */
 size_t gdsw_footprint_bytes(const gdsw_problem* prob, const gdsw_options* opt);
 
 /* Release every resource of the context (NULL is a no-op): waits for the
