@@ -408,7 +408,8 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
   b.tiles_inner = d_tiles_inner;
   b.total_outer = tiles.total_outer.data();
   b.total_inner = tiles.total_inner.data();
-  b.ut = A.alloc_n<T>((size_t)64 * L.sum_n);
+  b.wide = true;
+  b.ut = A.alloc_n<T>((size_t)128 * L.sum_n);
   C->setup_scratch.push_back(b.ut);
   lu_batched<T>(b, blocks, s);
   L.perm = A.alloc_n<int>((size_t)L.sum_n);
@@ -515,7 +516,8 @@ CsrDev coarse_level(gdsw_ctx* C, Level& L, hipStream_t s, std::vector<int64_t>& 
   b.tiles_inner = d_itiles_inner;
   b.total_outer = itiles.total_outer.data();
   b.total_inner = itiles.total_inner.data();
-  b.ut = A.alloc_n<T>((size_t)64 * m.inter.size());
+  b.wide = true;
+  b.ut = A.alloc_n<T>((size_t)128 * m.inter.size());
   C->setup_scratch.push_back(b.ut);
   lu_batched<T>(b, aii, s);
   T* phi;
@@ -588,7 +590,8 @@ void coarsest_inverse(gdsw_ctx* C, const CsrDev& K, hipStream_t s, double** dens
   b.piv = piv;
   b.poff = d_off;
   b.info = info;
-  b.ut = A.alloc_n<double>((size_t)64 * n);
+  b.wide = true;
+  b.ut = A.alloc_n<double>((size_t)128 * n);
   C->setup_scratch.push_back(b.ut);
   lu_batched<double>(b, D, s);
   double* X = A.alloc_n<double>((size_t)n * n);
@@ -1398,14 +1401,14 @@ size_t gdsw_footprint_bytes(const gdsw_problem* prob, const gdsw_options* opt) {
         sn += ni;
       }
       // factors, pivots / gather / local vectors, and the U12 scratch of the factorization
-      total += n2 * s + sn * 24 + 64 * sn * s;
+      total += n2 * s + sn * 24 + 128 * sn * s;
       size_t phi = 0;
       for (size_t i = 0; i < N; ++i)
         phi += (size_t)(m.int_ptr[i + 1] - m.int_ptr[i]) * (size_t)(m.pc_ptr[i + 1] - m.pc_ptr[i]);
-      total += phi * (s + 8) + m.owner.size() * 24 + 64 * m.inter.size() * s;
+      total += phi * (s + 8) + m.owner.size() * 24 + 128 * m.inter.size() * s;
       n_last = (size_t)m.n_coarse;
     }
-    if (P.coarsest) total += 2 * n_last * n_last * 8 + 64 * n_last * 8;
+    if (P.coarsest) total += 2 * n_last * n_last * 8 + 128 * n_last * 8;
     const size_t n = (size_t)prob->n;
     total += (size_t)(o.restart * 2 + 4) * n * 8;
     return total;

@@ -29,10 +29,13 @@ struct LuBatch {
   const int64_t* tiles_inner = nullptr;
   const int64_t* total_outer = nullptr;
   const int64_t* total_inner = nullptr;
-  // Optional device scratch of 64 * (sum of orders) elements of the batch's type
-  // (matrix i at 64 * poff[i]): each outer step's U12 rows are also written there
-  // row-major, so the trailing update reads them with coalesced loads.
+  // Optional device scratch of R * (sum of orders) elements of the batch's type
+  // (matrix i at R * poff[i]; R = 64, or 128 when wide): each outer step's U12
+  // rows are also written there row-major, so the trailing update reads them with
+  // coalesced loads.
   void* ut = nullptr;
+  // With ut (R = 128): pairs of 64-column steps share one rank-128 trailing update.
+  bool wide = false;
 };
 
 // Host-built update tile tables of a batch with orders dims[0..count).

@@ -117,7 +117,7 @@ template <typename T, int KMAX, bool B_ROWS = false>
 __device__ __forceinline__ void gemm_sub_tile_direct(T* __restrict__ C, int64_t ldc, const T* __restrict__ A,
                                                      int64_t lda, const T* __restrict__ B, int64_t ldb, int M, int N,
                                                      int K, int ty, int tx) {
-  constexpr int NPH = 2;
+  constexpr int NPH = KMAX > 64 ? KMAX / 32 : 2;
   constexpr int S = KMAX / 4 / NPH;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wy = w >> 1, wx = w & 1;
@@ -566,7 +566,8 @@ __global__ __launch_bounds__(TRSM_COLS) void k_lu_outer_swap_trsm(T* __restrict_
                                                                   const int* __restrict__ dim,
                                                                   const int* __restrict__ pivb,
                                                                   const int64_t* __restrict__ poff, int k, int pad,
-                                                                  T* __restrict__ ut) {
+                                                                  T* __restrict__ ut, int swap, int ut_rows,
+                                                                  int ut_row0, int ut_k0) {
   constexpr int KW = 2 * NB;
   const int i = blockIdx.x;
   const int n = dim[i];
@@ -586,12 +587,14 @@ __global__ __launch_bounds__(TRSM_COLS) void k_lu_outer_swap_trsm(T* __restrict_
   const int c = cfirst + (int)threadIdx.x;
   if (c >= n) return;
   T* col = A + (int64_t)c * ld;
-  for (int j = 0; j < KW; ++j) {
-    const int p = sp[j];
-    if (p != k + j) {
-      const T t = col[k + j];
-      col[k + j] = col[p];
-      col[p] = t;
+  if (swap) {
+    for (int j = 0; j < KW; ++j) {
+      const int p = sp[j];
+      if (p != k + j) {
+        const T t = col[k + j];
+        col[k + j] = col[p];
+        col[p] = t;
+      }
     }
   }
   // padded columns (pad > 1: 128-byte aligned) move their 64 values in 16-byte pieces
@@ -627,9 +630,9 @@ __global__ __launch_bounds__(TRSM_COLS) void k_lu_outer_swap_trsm(T* __restrict_
 #pragma unroll
     for (int r = 0; r < KW; ++r) col[k + r] = x[r];
   }
-  if (ut) {                                 // U12 by rows: row r of length n - k - KW
-    const int M = n - k - KW;
-    T* u = ut + 64 * poff[i] + (c - k - KW);
+  if (ut) {   // U12 by rows into the scratch: ut_rows rows of length n - ut_k0 - KW per matrix
+    const int M = n - ut_k0 - KW;
+    T* u = ut + (int64_t)ut_rows * poff[i] + (int64_t)ut_row0 * M + (c - ut_k0 - KW);
 #pragma unroll
     for (int r = 0; r < KW; ++r) u[(int64_t)r * M] = x[r];
   }
@@ -672,6 +675,48 @@ __global__ __launch_bounds__(256) void k_lu_update(T* __restrict__ Ab, const int
   else
     gemm_sub_tile_direct<T, 2 * NB>(A + r0 + (int64_t)c0 * ld, ld, A + r0 + (int64_t)k * ld, ld,
                                     A + k + (int64_t)c0 * ld, ld, M, N, kw, ty, tx);
+}
+
+// Updates of the paired-step factorization (lu_batched, wide): with k0 the
+// first column of the pair,
+//   A[r0 : r0 + M, c0 : c1) -= A[r0 : r0 + M, k0 : k0 + kw) * U[0 : kw, c0 : c1)
+// r0 = k0 + r0_rel, M = min(n - r0, m_cap), c0 = k0 + c0_rel, c1 = k0 + c1_rel (n if c1_rel < 0).
+// U's rows come from the row-major scratch (rows of length n - k0 - 64 starting
+// at column k0 + 64, matrix i at ut_rows * poff[i]).
+template <typename T, int KMAX>
+__global__ __launch_bounds__(256) void k_lu_update_ut(T* __restrict__ Ab, const int64_t* __restrict__ off,
+                                                      const int* __restrict__ dim, int k0, int r0_rel, int m_cap,
+                                                      int c0_rel, int c1_rel, int kw, int tiles_m, int tiles_n,
+                                                      const int64_t* __restrict__ tab, int count, int pad,
+                                                      const T* __restrict__ ut, const int64_t* __restrict__ poff,
+                                                      int ut_rows) {
+  const int w = (int)xcd_remap(blockIdx.x, gridDim.x);
+  int i, tl;
+  if (tab) {
+    i = segment_of(tab, count, w);
+    tl = w - (int)tab[i];
+  } else {
+    const int tiles = tiles_m * tiles_n;
+    i = w / tiles;
+    tl = w - i * tiles;
+  }
+  const int n = dim[i];
+  const int r0 = k0 + r0_rel;
+  if (r0 >= n) return;
+  const int M = min(n - r0, m_cap);
+  const int c0 = k0 + c0_rel;
+  const int c1 = c1_rel < 0 ? n : min(n, k0 + c1_rel);
+  if (c0 >= c1) return;
+  const int N = c1 - c0;
+  const int tm = tab ? (M + TILE - 1) / TILE : tiles_m;
+  const int ty = tl % tm, tx = tl / tm;
+  if (ty * TILE >= M || tx * TILE >= N) return;
+  const int ld = lead_dim(n, pad);
+  T* A = Ab + off[i];
+  const int urow = n - k0 - 2 * LU_NB;
+  const T* U = ut + (int64_t)ut_rows * poff[i] + (c0 - k0 - 2 * LU_NB);
+  gemm_sub_tile_direct<T, KMAX, true>(A + r0 + (int64_t)c0 * ld, ld, A + r0 + (int64_t)k0 * ld, ld, U, urow, M, N, kw,
+                                      ty, tx);
 }
 
 // mode 0: LU trailing update; 1: forward-solve update of X; 2: backward-solve update of X.
@@ -1071,7 +1116,9 @@ void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
     }
     launch_panel_rot<T>(b, A, k, std::min(rows, panel_reg_rows<T>()), !tall, s);
   };
-  for (int k = 0; k < b.max_n; k += 2 * NB) {
+  // columns [k, k + 2NB): both sub-panels (the second brought up to date by the first), then the
+  // interchanges of the step on the columns to their left
+  auto block = [&](int k) {
     panel(k);
     if (b.max_n > k + NB) {
       hipLaunchKernelGGL((k_lu_inner_swap_trsm<T, NB>), dim3(b.count), dim3(64), 0, s, A, b.off, b.dim, b.piv, b.poff,
@@ -1091,11 +1138,66 @@ void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
     hipLaunchKernelGGL((k_lu_outer_swap_left<T, NB>), dim3(b.count, blocks_for(k + NB, 64)), dim3(64), 0, s, A, b.off,
                        b.dim, b.piv, b.poff, k, b.pad);
     GDSW_LAUNCH_CHECK();
+  };
+  auto trsm = [&](int k, int rest, int swap, int ut_rows, int ut_row0, int ut_k0) {
+    hipLaunchKernelGGL((k_lu_outer_swap_trsm<T, NB>), dim3(b.count, blocks_for(rest, TRSM_COLS)), dim3(TRSM_COLS), 0, s,
+                       A, b.off, b.dim, b.piv, b.poff, k, b.pad, ut, swap, ut_rows, ut_row0, ut_k0);
+    GDSW_LAUNCH_CHECK();
+  };
+  if (b.wide && ut) {
+    // Pairs of 2NB-column steps with one rank-4NB trailing update per pair (half the
+    // passes over the trailing matrix).  For the pair at k0: the first block; U12 of
+    // its rows for every trailing column (scratch rows 0..2NB); the second block's
+    // columns updated; the second block; its interchanges, its rows updated by the
+    // first block and its U12 (scratch rows 2NB..4NB) on the columns beyond; then
+    // A22 -= L21 U12 over the 4NB columns of the pair.
+    const int64_t huge = 1 << 30;
+    for (int k0 = 0; k0 < b.max_n; k0 += 4 * NB) {
+      block(k0);
+      const int rest_a = b.max_n - k0 - 2 * NB;
+      if (rest_a <= 0) break;
+      trsm(k0, rest_a, 1, 4 * NB, 0, k0);
+      {
+        const int tm = (int)blocks_for(rest_a, TILE);
+        hipLaunchKernelGGL((k_lu_update_ut<T, 2 * NB>), dim3((unsigned)((int64_t)b.count * tm)), dim3(256), 0, s, A,
+                           b.off, b.dim, k0, 2 * NB, (int)huge, 2 * NB, 4 * NB, 2 * NB, tm, 1, nullptr, b.count, b.pad,
+                           static_cast<const T*>(ut), b.poff, 4 * NB);
+        GDSW_LAUNCH_CHECK();
+      }
+      block(k0 + 2 * NB);
+      const int rest_b = b.max_n - k0 - 4 * NB;
+      if (rest_b <= 0) break;
+      hipLaunchKernelGGL((k_lu_swap_cols<T>), dim3(b.count, blocks_for(rest_b, 64)), dim3(64), 0, s, A, b.off, b.dim,
+                         b.piv, b.poff, k0 + 2 * NB, 2 * NB, k0 + 4 * NB, rest_b, b.pad);
+      GDSW_LAUNCH_CHECK();
+      {
+        const int tn = (int)blocks_for(rest_b, TILE);
+        hipLaunchKernelGGL((k_lu_update_ut<T, 2 * NB>), dim3((unsigned)((int64_t)b.count * tn)), dim3(256), 0, s, A,
+                           b.off, b.dim, k0, 2 * NB, 2 * NB, 4 * NB, -1, 2 * NB, 1, tn, nullptr, b.count, b.pad,
+                           static_cast<const T*>(ut), b.poff, 4 * NB);
+        GDSW_LAUNCH_CHECK();
+      }
+      trsm(k0 + 2 * NB, rest_b, 0, 4 * NB, 2 * NB, k0);
+      {
+        const int t = (int)blocks_for(rest_b, TILE);
+        const int st = k0 / (2 * NB) + 1;
+        const int64_t grid = b.tiles_outer ? b.total_outer[st] : (int64_t)b.count * t * t;
+        if (grid > 0) {
+          hipLaunchKernelGGL((k_lu_update_ut<T, 4 * NB>), dim3((unsigned)grid), dim3(256), 0, s, A, b.off, b.dim, k0,
+                             4 * NB, (int)huge, 4 * NB, -1, 4 * NB, t, t,
+                             b.tiles_outer ? b.tiles_outer + (size_t)st * (b.count + 1) : nullptr, b.count, b.pad,
+                             static_cast<const T*>(ut), b.poff, 4 * NB);
+          GDSW_LAUNCH_CHECK();
+        }
+      }
+    }
+    return;
+  }
+  for (int k = 0; k < b.max_n; k += 2 * NB) {
+    block(k);
     const int rest = b.max_n - k - 2 * NB;
     if (rest > 0) {
-      hipLaunchKernelGGL((k_lu_outer_swap_trsm<T, NB>), dim3(b.count, blocks_for(rest, TRSM_COLS)), dim3(TRSM_COLS), 0,
-                         s, A, b.off, b.dim, b.piv, b.poff, k, b.pad, ut);
-      GDSW_LAUNCH_CHECK();
+      trsm(k, rest, 1, 2 * NB, 0, k);
       const int t = (int)blocks_for(rest, TILE);
       const int st = k / (2 * NB);
       const int64_t grid = b.tiles_outer ? b.total_outer[st] : (int64_t)b.count * t * t;
