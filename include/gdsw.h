@@ -114,7 +114,7 @@ typedef struct gdsw_problem {
  *             stream of the context, ordered after and before `stream`.
  * tune      : 1 = at the end of setup, time the local solves of every level
  *             with 2, 4 and 8 wavefronts per matrix and keep the fastest
- *             (reported in gdsw_stats.ls_waves); 0 = 4 wavefronts.
+ *             (reported in gdsw_stats.ls_waves); 0 = 8 wavefronts.
  */
 typedef struct gdsw_options {
   int32_t overlap;

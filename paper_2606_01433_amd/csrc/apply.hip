@@ -16,26 +16,124 @@ constexpr int PW = 64;   // triangle / panel width of the blocked substitution
 // Local solves w_i = A_i^{-1} R_i r with the pivoted LU stored in place.
 // Forward substitution with unit L, then backward with U, in 64-wide panels:
 // the diagonal triangle is solved by one wave (lane j's value is broadcast with
-// readlane; U's diagonal reciprocals are formed in parallel first), then the
-// panel is applied to the remaining rows as a GEMV in row-outer order (each
-// thread streams its row's 64 panel entries with all loads in flight).  The
-// gathered right-hand side lives in LDS.
+// readlane), then the panel is applied to the remaining rows as a GEMV in
+// row-outer order (each thread streams its row's 64 panel entries with the
+// loads in flight together).  The gathered right-hand side lives in LDS.
 //
-// NW wavefronts per matrix share the GEMV rows (4 by default; the autotuner
-// may pick 2 or 8).  Matrices are visited largest first (`order`), so the big
-// ones do not form the tail.
-// FIRST only separates the level-1 launch from deeper levels in profiles.
-// Columns are stored with leading dimension lead_dim(n, pad).
+// NW wavefronts per matrix share the GEMV rows (8 by default; the autotuner may
+// pick 2 or 4).  With 8, a panel row is loaded in two phases of 32 columns
+// (half the registers: four waves per SIMD instead of three) into the same
+// 64-term accumulation, so every choice gives bit-identical results.
+// Matrices are visited largest first (`order`), so the big ones do not form
+// the tail.  FIRST only separates the level-1 launch from deeper levels in
+// profiles.  Columns are stored with leading dimension lead_dim(n, pad).
+//
+// Register discipline: a panel row is addressed through one running 64-bit
+// offset made opaque to the optimizer after each step, and the per-column lane
+// masks of the triangles are formed next to their use from an opaque copy of
+// the lane index; otherwise the compiler hoists 64 column offsets and 64 lane
+// masks into scalar registers and spills them (half of a lone matrix's time).
+// FULL = false handles the one ragged panel of a matrix (pw < 64 columns).
 // ---------------------------------------------------------------------------
+template <typename T, int NPH, bool FULL>
+__device__ __forceinline__ void ls_row_update(const T* __restrict__ A, int ld, T* x, int row, int q0, int pw) {
+  constexpr int H = PW / NPH;
+  T acc = T(0);
+#pragma unroll
+  for (int h = 0; h < NPH; ++h) {
+    int64_t o = row + (int64_t)(q0 + h * H) * ld;
+    if (h > 0) asm volatile("" : "+v"(o) : "v"(acc));   // phase h loads after phase h-1 (register budget)
+    T v[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      v[j] = (FULL || h * H + j < pw) ? A[o] : T(0);
+      o += ld;
+      asm volatile("" : "+v"(o));
+    }
+#pragma unroll
+    for (int j = 0; j < H; ++j) acc += v[j] * x[q0 + (FULL ? h * H + j : min(h * H + j, pw - 1))];
+  }
+  x[row] -= acc;
+}
+
+// Unit-lower triangle of rows/columns [q0, q0 + pw) solved in place in x by one wave.
+// Lanes at or past pw address row q0 (valid memory) and are masked out.
+template <typename T, int NPH, bool FULL>
+__device__ __forceinline__ void ls_tri_lower(const T* __restrict__ A, int ld, T* x, int q0, int pw, int lane) {
+  constexpr int H = PW / NPH;
+  const bool ok = FULL || lane < pw;
+  const int row = ok ? q0 + lane : q0;
+  const int lj = ok ? lane : 0;
+  T xv = ok ? x[row] : T(0);
+#pragma unroll
+  for (int h = 0; h < NPH; ++h) {
+    if (!(FULL || h * H < pw)) continue;
+    int64_t o = row + (int64_t)(q0 + h * H) * ld;
+    if (h > 0) asm volatile("" : "+v"(o) : "v"(xv));
+    T d[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      d[j] = (FULL || h * H + j < pw) ? A[o] : T(0);
+      o += ld;
+      asm volatile("" : "+v"(o));
+    }
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const int jj = h * H + j;
+      if (FULL || jj < pw) {
+        int l = lj;
+        asm volatile("" : "+v"(l));
+        xv -= (jj < l ? d[j] : T(0)) * lane_value(xv, jj);
+      }
+    }
+  }
+  if (ok) x[row] = xv;
+}
+
+// Upper triangle (non-unit diagonal) of rows/columns [q0, q0 + pw), one wave: the value of
+// column jj is broadcast as x_jj * (1 / U_jj); each lane scales its own value once at the end.
+template <typename T, int NPH, bool FULL>
+__device__ __forceinline__ void ls_tri_upper(const T* __restrict__ A, int ld, T* x, int q0, int pw, int lane) {
+  constexpr int H = PW / NPH;
+  const bool ok = FULL || lane < pw;
+  const int row = ok ? q0 + lane : q0;
+  const T rd = ok ? T(1) / A[row + (int64_t)row * ld] : T(0);
+  const int lj = ok ? lane : PW;
+  T xv = ok ? x[row] : T(0);
+#pragma unroll
+  for (int h = NPH - 1; h >= 0; --h) {
+    if (!(FULL || h * H < pw)) continue;
+    int64_t o = row + (int64_t)(q0 + h * H) * ld;
+    if (h < NPH - 1) asm volatile("" : "+v"(o) : "v"(xv));
+    T d[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      d[j] = (FULL || h * H + j < pw) ? A[o] : T(0);
+      o += ld;
+      asm volatile("" : "+v"(o));
+    }
+#pragma unroll
+    for (int j = H - 1; j >= 0; --j) {
+      const int jj = h * H + j;
+      if (FULL || jj < pw) {
+        const T t = lane_value(xv, jj) * lane_value(rd, jj);
+        int l = lj;
+        asm volatile("" : "+v"(l));
+        xv -= (jj > l ? d[j] : T(0)) * t;
+      }
+    }
+  }
+  xv *= rd;
+  if (ok) x[row] = xv;
+}
+
 template <typename T, bool FIRST, int NW>
-__global__ __launch_bounds__(64 * NW) void k_local_solve_wg(const int* __restrict__ order,
-                                                            const int64_t* __restrict__ dom_ptr,
-                                                            const int* __restrict__ gidx,
-                                                            const int64_t* __restrict__ blk_off,
-                                                            const T* __restrict__ blocks,
-                                                            const double* __restrict__ r, double* __restrict__ w,
-                                                            int pad) {
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 4 : 1))) void k_local_solve_wg(
+    const int* __restrict__ order, const int64_t* __restrict__ dom_ptr, const int* __restrict__ gidx,
+    const int64_t* __restrict__ blk_off, const T* __restrict__ blocks, const double* __restrict__ r,
+    double* __restrict__ w, int pad) {
   constexpr int NT = 64 * NW;
+  constexpr int NPH = NW == 8 ? 2 : 1;
   extern __shared__ unsigned char smem_raw[];
   T* x = reinterpret_cast<T*>(smem_raw);
   const int i = order[blockIdx.x];
@@ -49,56 +147,25 @@ __global__ __launch_bounds__(64 * NW) void k_local_solve_wg(const int* __restric
   for (int p0 = 0; p0 < n; p0 += PW) {
     const int pw = min(PW, n - p0);
     if (wid == 0) {
-      const int row = p0 + lane;
-      T d[PW];
-#pragma unroll
-      for (int j = 0; j < PW; ++j) d[j] = (lane < pw && j < lane) ? A[row + (int64_t)(p0 + j) * ld] : T(0);
-      T xv = (lane < pw) ? x[row] : T(0);
-#pragma unroll
-      for (int j = 0; j < PW; ++j) xv -= d[j] * lane_value(xv, j);
-      if (lane < pw) x[row] = xv;
+      if (pw == PW) ls_tri_lower<T, NPH, true>(A, ld, x, p0, PW, lane);
+      else ls_tri_lower<T, NPH, false>(A, ld, x, p0, pw, lane);
     }
     __syncthreads();
-    for (int rr = p0 + pw + tid; rr < n; rr += NT) {
-      const T* Ar = A + rr + (int64_t)p0 * ld;
-      T v[PW];
-#pragma unroll
-      for (int j = 0; j < PW; ++j) v[j] = (j < pw) ? Ar[(int64_t)j * ld] : T(0);
-      T acc = T(0);
-#pragma unroll
-      for (int j = 0; j < PW; ++j) acc += v[j] * x[p0 + min(j, pw - 1)];   // v[j] = 0 past pw
-      x[rr] -= acc;
-    }
+    // rows below a ragged (last) panel: none
+    for (int rr = p0 + pw + tid; rr < n; rr += NT) ls_row_update<T, NPH, true>(A, ld, x, rr, p0, PW);
     __syncthreads();
   }
   for (int p0 = ((n - 1) / PW) * PW; p0 >= 0; p0 -= PW) {
     const int pw = min(PW, n - p0);
     if (wid == 0) {
-      const int row = p0 + lane;
-      T d[PW];
-#pragma unroll
-      for (int j = 0; j < PW; ++j)
-        d[j] = (lane < pw && j > lane && j < pw) ? A[row + (int64_t)(p0 + j) * ld] : T(0);
-      const T rd = (lane < pw) ? T(1) / A[row + (int64_t)row * ld] : T(0);
-      T xv = (lane < pw) ? x[row] : T(0);
-#pragma unroll
-      for (int j = PW - 1; j >= 0; --j) {
-        if (lane == j) xv *= rd;
-        xv -= d[j] * lane_value(xv, j);
-      }
-      if (lane < pw) x[row] = xv;
+      if (pw == PW) ls_tri_upper<T, NPH, true>(A, ld, x, p0, PW, lane);
+      else ls_tri_upper<T, NPH, false>(A, ld, x, p0, pw, lane);
     }
     __syncthreads();
-    for (int rr = tid; rr < p0; rr += NT) {
-      const T* Ar = A + rr + (int64_t)p0 * ld;
-      T v[PW];
-#pragma unroll
-      for (int j = 0; j < PW; ++j) v[j] = (j < pw) ? Ar[(int64_t)j * ld] : T(0);
-      T acc = T(0);
-#pragma unroll
-      for (int j = 0; j < PW; ++j) acc += v[j] * x[p0 + min(j, pw - 1)];
-      x[rr] -= acc;
-    }
+    if (pw == PW)
+      for (int rr = tid; rr < p0; rr += NT) ls_row_update<T, NPH, true>(A, ld, x, rr, p0, PW);
+    else
+      for (int rr = tid; rr < p0; rr += NT) ls_row_update<T, NPH, false>(A, ld, x, rr, p0, pw);
     __syncthreads();
   }
   for (int a = tid; a < n; a += NT) w[base + a] = (double)x[a];

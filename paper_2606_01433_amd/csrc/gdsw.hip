@@ -185,8 +185,8 @@ struct Level {
   int* gidx = nullptr;
   int* info = nullptr;
   int* order = nullptr;          // parts by decreasing block size (apply visiting order)
-  int ls_waves = 4;              // wavefronts per matrix of the local solves: 4 on level 1 (HBM-bound,
-                                 // many matrices), 8 deeper (few, latency-bound); autotuned with tune = 1
+  int ls_waves = 8;              // wavefronts per matrix of the local solves (2, 4 or 8); autotuned
+                                 // with tune = 1
   int64_t* sc_ptr = nullptr;
   int* sc_pos = nullptr;
   double* w = nullptr;           // local solutions, sum_n
@@ -729,7 +729,7 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
     C->levels.emplace_back();
     Level& L = C->levels.back();
     L.index = l + 1;
-    L.ls_waves = (l == 0) ? 4 : 8;
+    L.ls_waves = 8;
     L.nparts = meshes[l].n_parts;
     L.n = K.n;
     L.K = K;
