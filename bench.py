@@ -23,7 +23,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of one level-1 local-solve launch on this workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a 1 GiB copy (profiles/local_solve_die32x16x16.md), valid only for the
 # local-solve kernel source it was measured on.
-LOCAL_SOLVE_TRAFFIC = {"bytes": 3.993e9, "source_hash": "d7f1243e591bd739", "precision": "fp64"}
+LOCAL_SOLVE_TRAFFIC = {"bytes": 3.993e9, "source_hash": "935223e387098f25", "precision": "fp64"}
 
 
 def local_solve_source_hash():

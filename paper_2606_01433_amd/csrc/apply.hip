@@ -70,21 +70,19 @@ __device__ __forceinline__ void ls_tri_lower(const T* __restrict__ A, int ld, T*
     if (!(FULL || h * H < pw)) continue;
     int64_t o = row + (int64_t)(q0 + h * H) * ld;
     if (h > 0) asm volatile("" : "+v"(o) : "v"(xv));
-    T d[H];
+    T d[H];   // strictly lower part only: the other lanes fetch nothing
 #pragma unroll
     for (int j = 0; j < H; ++j) {
-      d[j] = (FULL || h * H + j < pw) ? A[o] : T(0);
+      int l = lj;
+      asm volatile("" : "+v"(l));
+      d[j] = (h * H + j < l) ? A[o] : T(0);
       o += ld;
       asm volatile("" : "+v"(o));
     }
 #pragma unroll
     for (int j = 0; j < H; ++j) {
       const int jj = h * H + j;
-      if (FULL || jj < pw) {
-        int l = lj;
-        asm volatile("" : "+v"(l));
-        xv -= (jj < l ? d[j] : T(0)) * lane_value(xv, jj);
-      }
+      if (FULL || jj < pw) xv -= d[j] * lane_value(xv, jj);
     }
   }
   if (ok) x[row] = xv;
@@ -105,22 +103,19 @@ __device__ __forceinline__ void ls_tri_upper(const T* __restrict__ A, int ld, T*
     if (!(FULL || h * H < pw)) continue;
     int64_t o = row + (int64_t)(q0 + h * H) * ld;
     if (h < NPH - 1) asm volatile("" : "+v"(o) : "v"(xv));
-    T d[H];
+    T d[H];   // strictly upper part within the pw columns only
 #pragma unroll
     for (int j = 0; j < H; ++j) {
-      d[j] = (FULL || h * H + j < pw) ? A[o] : T(0);
+      int l = lj;
+      asm volatile("" : "+v"(l));
+      d[j] = (h * H + j > l && (FULL || h * H + j < pw)) ? A[o] : T(0);
       o += ld;
       asm volatile("" : "+v"(o));
     }
 #pragma unroll
     for (int j = H - 1; j >= 0; --j) {
       const int jj = h * H + j;
-      if (FULL || jj < pw) {
-        const T t = lane_value(xv, jj) * lane_value(rd, jj);
-        int l = lj;
-        asm volatile("" : "+v"(l));
-        xv -= (jj > l ? d[j] : T(0)) * t;
-      }
+      if (FULL || jj < pw) xv -= d[j] * (lane_value(xv, jj) * lane_value(rd, jj));
     }
   }
   xv *= rd;
