@@ -114,7 +114,10 @@ typedef struct gdsw_problem {
  *             stream of the context, ordered after and before `stream`.
  * tune      : 1 = at the end of setup, time the local solves of every level
  *             with 2, 4 and 8 wavefronts per matrix and keep the fastest
- *             (reported in gdsw_stats.ls_waves); 0 = 8 wavefronts.
+ *             (reported in gdsw_stats.ls_waves); 0 = ls_waves.
+ * ls_waves  : wavefronts per matrix of the local solves on every level when
+ *             tune = 0: 0 = default (8), or 2, 4, 8.  Every choice gives
+ *             bit-identical results (only the scheduling differs).
  */
 typedef struct gdsw_options {
   int32_t overlap;
@@ -128,6 +131,7 @@ typedef struct gdsw_options {
   int32_t profile;
   int32_t graph;
   int32_t tune;
+  int32_t ls_waves;
 } gdsw_options;
 
 typedef struct gdsw_solve_info {

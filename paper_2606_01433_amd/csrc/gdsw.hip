@@ -729,7 +729,7 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
     C->levels.emplace_back();
     Level& L = C->levels.back();
     L.index = l + 1;
-    L.ls_waves = 8;
+    L.ls_waves = C->opt.ls_waves ? C->opt.ls_waves : 8;
     L.nparts = meshes[l].n_parts;
     L.n = K.n;
     L.K = K;
@@ -1182,6 +1182,7 @@ void gdsw_default_options(gdsw_options* o) {
   o->profile = 0;
   o->graph = 0;
   o->tune = 0;
+  o->ls_waves = 0;
 }
 
 const char* gdsw_last_error(void) { return gdsw::g_last_error.c_str(); }
@@ -1202,7 +1203,8 @@ int gdsw_setup(const gdsw_problem* prob, const gdsw_options* opt, void* stream, 
     if (opt) C->opt = *opt;
     if (C->opt.overlap < 0 || C->opt.restart < 1 || C->opt.restart > 250 || C->opt.max_it < 0 ||
         !(C->opt.tol >= 0.0) || (C->opt.combine != 0 && C->opt.combine != 1) ||
-        (C->opt.precision != 0 && C->opt.precision != 1))
+        (C->opt.precision != 0 && C->opt.precision != 1) ||
+        (C->opt.ls_waves != 0 && C->opt.ls_waves != 2 && C->opt.ls_waves != 4 && C->opt.ls_waves != 8))
       throw Error(GDSW_EINVAL, "invalid options");
     C->mixed = C->opt.precision == GDSW_MIXED;
     hipStream_t s = static_cast<hipStream_t>(stream);

@@ -27,7 +27,7 @@ class Problem(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("overlap", c_i32), ("combine", c_i32), ("precision", c_i32), ("restart", c_i32),
                 ("max_it", c_i32), ("tol", c_dbl), ("no_coarse", c_i32), ("panel", c_i32), ("profile", c_i32),
-                ("graph", c_i32), ("tune", c_i32)]
+                ("graph", c_i32), ("tune", c_i32), ("ls_waves", c_i32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -103,7 +103,7 @@ def _check(code):
 
 
 def make_options(overlap=1, combine="restricted", precision="fp64", restart=30, max_it=1000, tol=1e-8,
-                 no_coarse=False, panel=0, profile=False, graph=False, tune=False):
+                 no_coarse=False, panel=0, profile=False, graph=False, tune=False, ls_waves=0):
     o = Options()
     load_library().gdsw_default_options(ctypes.byref(o))
     o.overlap = overlap
@@ -117,6 +117,7 @@ def make_options(overlap=1, combine="restricted", precision="fp64", restart=30, 
     o.profile = int(bool(profile))
     o.graph = int(bool(graph))
     o.tune = int(bool(tune))
+    o.ls_waves = int(ls_waves)
     return o
 
 
