@@ -279,24 +279,25 @@ def test_graph_solves_match_eager(gd):
                 assert np.isfinite(z.cpu().numpy()).all()
 
 
-def test_local_solve_wave_counts_are_bit_identical(gd):
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-3)])
+def test_local_solve_wave_counts_are_bit_identical(gd, precision, tol):
     """2 and 4 wavefronts per matrix load a 64-column panel row at once, 8 in two 32-column phases;
-    all three keep each row's summation order, so the applies agree bit for bit, and they match
-    the oracle on a hierarchy with ragged last panels (uneven part sizes)."""
+    all three keep each row's summation order, so the applies agree bit for bit (FP64 and FP32
+    factors), and they match the oracle on a hierarchy with ragged last panels (uneven parts)."""
     name = "die16_L4_uneven"
     P = _problem(name)
     r = random_vector(P.n, 9)
     zo = oracle.apply(_orc(name), r)
     zs = {}
     for wv in (2, 4, 8):
-        _say("local solves with", wv, "waves per matrix")
-        with gd.Context(P, ls_waves=wv) as ctx:
+        _say("local solves", precision, "with", wv, "waves per matrix")
+        with gd.Context(P, ls_waves=wv, precision=precision) as ctx:
             zs[wv] = ctx.apply(_dev(r)).cpu().numpy()
             assert list(ctx.stats()["ls_waves"][:3]) == [wv] * 3
     assert np.array_equal(zs[2], zs[8]) and np.array_equal(zs[4], zs[8])
-    assert np.linalg.norm(zs[8] - zo) <= 1e-10 * np.linalg.norm(zo)
+    assert np.linalg.norm(zs[8] - zo) <= tol * np.linalg.norm(zo)
     with pytest.raises(gd.GdswError):
-        gd.Context(P, ls_waves=3)
+        gd.Context(P, ls_waves=3, precision=precision)
 
 
 def test_autotuned_local_solves_are_bit_identical(gd):
