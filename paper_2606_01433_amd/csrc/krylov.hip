@@ -43,24 +43,32 @@ __global__ __launch_bounds__(256) void k_spmv(CsrDev K, const double* __restrict
   if (lane == 0) y[row] = s;
 }
 
-// partial[b * ncols + c] = sum over this block's rows of V[r, c0 + c] w[r]
+// partial[b * ncols + c] = sum over this block's rows of V[r, c0 + c] w[r].  Thread t takes rows
+// r0 + t and r0 + t + 256, in that order; both rows' loads are issued before the first FMA (one
+// memory round trip per thread instead of two).
+static_assert(DOT_BLOCK_ROWS == 512, "two rows per thread of a 256-thread block");
 __global__ __launch_bounds__(256) void k_multi_dot_partial(int64_t n, int ncols, const double* __restrict__ V,
                                                            int64_t ldv, const double* __restrict__ w,
                                                            double* __restrict__ partial) {
   __shared__ double red[4][DOT_MAXC];
-  const int64_t r0 = (int64_t)blockIdx.x * DOT_BLOCK_ROWS;
-  const int64_t r1 = min(n, r0 + DOT_BLOCK_ROWS);
+  const int64_t ra = (int64_t)blockIdx.x * DOT_BLOCK_ROWS + threadIdx.x, rb = ra + 256;
+  const bool ha = ra < n, hb = rb < n;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int c0 = 0; c0 < ncols; c0 += DOT_MAXC) {
     const int nc = min(DOT_MAXC, ncols - c0);
+    const double wa = ha ? w[ra] : 0.0, wb = hb ? w[rb] : 0.0;
+    double va[DOT_MAXC], vb[DOT_MAXC];
+#pragma unroll
+    for (int c = 0; c < DOT_MAXC; ++c) {
+      va[c] = (c < nc && ha) ? V[ra + (int64_t)(c0 + c) * ldv] : 0.0;
+      vb[c] = (c < nc && hb) ? V[rb + (int64_t)(c0 + c) * ldv] : 0.0;
+    }
     double acc[DOT_MAXC];
 #pragma unroll
-    for (int c = 0; c < DOT_MAXC; ++c) acc[c] = 0.0;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
-      const double wr = w[r];
-#pragma unroll
-      for (int c = 0; c < DOT_MAXC; ++c)
-        if (c < nc) acc[c] += V[r + (int64_t)(c0 + c) * ldv] * wr;
+    for (int c = 0; c < DOT_MAXC; ++c) {
+      acc[c] = 0.0;
+      if (ha) acc[c] += va[c] * wa;
+      if (hb) acc[c] += vb[c] * wb;
     }
 #pragma unroll
     for (int c = 0; c < DOT_MAXC; ++c) {
@@ -92,7 +100,8 @@ __global__ __launch_bounds__(256) void k_multi_dot_reduce(int nblocks, int ncols
 
 // Fused pass of classical Gram-Schmidt: w -= V[:, :ncols] h, then per-block
 // partial dots of the updated w with V's columns (norm = 0) or with itself
-// (norm = 1).  Same row blocking and reduction tree as k_multi_dot_partial.
+// (norm = 1).  Same rows per thread, load order and reduction tree as
+// k_multi_dot_partial.
 __global__ __launch_bounds__(256) void k_axpy_dot_partial(int64_t n, int ncols, const double* __restrict__ V,
                                                           int64_t ldv, const double* __restrict__ h,
                                                           double* __restrict__ w, double* __restrict__ partial,
@@ -102,21 +111,24 @@ __global__ __launch_bounds__(256) void k_axpy_dot_partial(int64_t n, int ncols, 
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (threadIdx.x < ncols) hs[threadIdx.x] = h[threadIdx.x];
   __syncthreads();
-  const int64_t r0 = (int64_t)blockIdx.x * DOT_BLOCK_ROWS;
-  const int64_t r1 = min(n, r0 + DOT_BLOCK_ROWS);
+  const int64_t ra = (int64_t)blockIdx.x * DOT_BLOCK_ROWS + threadIdx.x, rb = ra + 256;
+  const bool ha = ra < n, hb = rb < n;
   const int nout = norm ? 1 : ncols;
+  double va[DOT_MAXC], vb[DOT_MAXC];
+#pragma unroll
+  for (int c = 0; c < DOT_MAXC; ++c) {
+    va[c] = (c < ncols && ha) ? V[ra + (int64_t)c * ldv] : 0.0;
+    vb[c] = (c < ncols && hb) ? V[rb + (int64_t)c * ldv] : 0.0;
+  }
+  const double wa0 = ha ? w[ra] : 0.0, wb0 = hb ? w[rb] : 0.0;
   double acc[DOT_MAXC];
 #pragma unroll
   for (int c = 0; c < DOT_MAXC; ++c) acc[c] = 0.0;
-  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
-    double v[DOT_MAXC];
+  auto row = [&](const double* v, double w0, int64_t r) {
     double t = 0.0;
 #pragma unroll
-    for (int c = 0; c < DOT_MAXC; ++c) {
-      v[c] = (c < ncols) ? V[r + (int64_t)c * ldv] : 0.0;
-      t += v[c] * hs[min(c, ncols - 1)] * (c < ncols ? 1.0 : 0.0);
-    }
-    const double wr = w[r] - t;
+    for (int c = 0; c < DOT_MAXC; ++c) t += v[c] * hs[min(c, ncols - 1)] * (c < ncols ? 1.0 : 0.0);
+    const double wr = w0 - t;
     w[r] = wr;
     if (norm) {
       acc[0] += wr * wr;
@@ -125,7 +137,9 @@ __global__ __launch_bounds__(256) void k_axpy_dot_partial(int64_t n, int ncols, 
       for (int c = 0; c < DOT_MAXC; ++c)
         if (c < ncols) acc[c] += v[c] * wr;
     }
-  }
+  };
+  if (ha) row(va, wa0, ra);
+  if (hb) row(vb, wb0, rb);
 #pragma unroll
   for (int c = 0; c < DOT_MAXC; ++c) {
     if (c < nout) {
