@@ -223,7 +223,13 @@ int gdsw_spmv(gdsw_ctx* ctx, const double* x, double* y, void* stream);
  * w, z: DEVICE FP64.  level is 1-based and must carry local solves. */
 int gdsw_scatter_local(gdsw_ctx* ctx, int32_t level, const double* w, double* z, void* stream);
 
-/* Host views of the index maps of a level that carries local solves (1-based). */
+/* Host views of the index maps of a level that carries local solves (1-based):
+ * the overlapping dof sets D_i and interior sets I_i, the interface nodes and
+ * their entities (vertices, edges, faces), the coarse columns of Phi and the
+ * owner of every dof -- the sets section 2.1 defines for one level, on the
+ * level mesh of the recursion of section 2.2 for levels >= 2.
+ * The view points into the context (valid until gdsw_destroy; not to be freed).
+ * Returns GDSW_EINVAL for a NULL argument or a level without local solves. */
 int gdsw_export_maps(gdsw_ctx* ctx, int32_t level, gdsw_maps_view* out);
 
 /* Sizes, algorithmic work and setup timings of the hierarchy. */

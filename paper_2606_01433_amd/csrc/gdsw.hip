@@ -1162,6 +1162,19 @@ int fail(const Error& e) {
   return e.code;
 }
 
+// A setup that fails part way may already have queued kernels on the caller's
+// stream that write blocks of the context's arena.  Those blocks go back to the
+// process-wide cache when the context is deleted, where a concurrent setup on
+// another stream could take them, so the caller's stream is drained first (the
+// context's own streams are drained by its destructor).  The message of the
+// original failure is kept.
+void discard_failed_setup(gdsw_ctx* C, hipStream_t s) {
+  const std::string msg = g_last_error;
+  (void)hipStreamSynchronize(s);
+  delete C;
+  g_last_error = msg;
+}
+
 }  // namespace
 }  // namespace gdsw
 
@@ -1225,10 +1238,10 @@ int gdsw_setup(const gdsw_problem* prob, const gdsw_options* opt, void* stream, 
     }
     GDSW_HIP(hipStreamSynchronize(s));
   } catch (const Error& e) {
-    delete C;
+    gdsw::discard_failed_setup(C, static_cast<hipStream_t>(stream));
     return gdsw::fail(e);
   } catch (const std::bad_alloc&) {
-    delete C;
+    gdsw::discard_failed_setup(C, static_cast<hipStream_t>(stream));
     gdsw::g_last_error = "host allocation failed";
     return GDSW_ENOMEM;
   }

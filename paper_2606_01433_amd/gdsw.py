@@ -205,6 +205,22 @@ def plan_maps(problem, **opts):
         lib.gdsw_plan_destroy(plan)
 
 
+def _check_csr(K, n, dev):
+    """The device CSR arrays exactly as gdsw_setup reads them: int64 row pointers (n + 1),
+    int32 columns and float64 values of length rowptr[-1], contiguous, on the context's GPU."""
+    import torch
+    rowptr, col, val = K
+    for name, t, dt in (("rowptr", rowptr, torch.int64), ("col", col, torch.int32), ("val", val, torch.float64)):
+        if not isinstance(t, torch.Tensor) or t.device != dev or t.dtype != dt or not t.is_contiguous() or t.dim() != 1:
+            raise TypeError(f"K.{name} must be a contiguous 1-D {dt} tensor on {dev}")
+    if rowptr.numel() != n + 1:
+        raise ValueError(f"K.rowptr has {rowptr.numel()} entries, expected n + 1 = {n + 1}")
+    nnz = int(rowptr[-1].item())
+    if col.numel() != nnz or val.numel() != nnz:
+        raise ValueError(f"K.col / K.val have {col.numel()} / {val.numel()} entries, rowptr[-1] = {nnz}")
+    return rowptr, col, val
+
+
 class Context:
     """A built GDSW hierarchy on the current GPU (gdsw_setup ... gdsw_destroy)."""
 
@@ -218,7 +234,7 @@ class Context:
             K = (torch.as_tensor(np.asarray(problem.rowptr, dtype=np.int64), device=dev),
                  torch.as_tensor(np.asarray(problem.col, dtype=np.int32), device=dev),
                  torch.as_tensor(np.asarray(problem.val, dtype=np.float64), device=dev))
-        rowptr, col, val = K
+        rowptr, col, val = _check_csr(K, self.n, dev)
         st = Problem()
         st.n = self.n
         st.rowptr, st.col, st.val = rowptr.data_ptr(), col.data_ptr(), val.data_ptr()

@@ -111,10 +111,10 @@ class Server:
             stream = torch.cuda.Stream(device=self.device)
             P = req.problem
             with torch.cuda.stream(stream):
-                K = (torch.as_tensor(P.rowptr).to(self.device, non_blocking=False),
-                     torch.as_tensor(P.col).to(self.device, non_blocking=False),
-                     torch.as_tensor(P.val).to(self.device, non_blocking=False))
-                b = torch.as_tensor(P.b).to(self.device)
+                K = (torch.as_tensor(np.asarray(P.rowptr, dtype=np.int64)).to(self.device),
+                     torch.as_tensor(np.asarray(P.col, dtype=np.int32)).to(self.device),
+                     torch.as_tensor(np.asarray(P.val, dtype=np.float64)).to(self.device))
+                b = torch.as_tensor(np.asarray(P.b, dtype=np.float64)).to(self.device)
                 ctx = gdsw.Context(P, K=K, stream=stream, **req.options)
                 try:
                     x, info = ctx.solve(b, stream=stream)

@@ -1,16 +1,16 @@
-"""GPU checks at the size of the benchmark workload (32x16x16 die, 914 parts).
+"""GPU parity at the size of the three-level FP64 workload (32x16x16 die, 914 parts).
 
-At this size the oracle cannot run the whole method in test time, so:
   * the level-1 local solves (batched pivoted LU + substitution, the register
-    panels for tall blocks and the compact update grids) are checked on sampled
-    dofs: a one-level restricted apply must equal, at each sampled dof g, the
-    entry of A_i^{-1} R_i r of g's owning part, computed on the CPU with a dense
-    LU of the local block taken from the oracle's maps (section 2.1);
-  * the three-level solve (coarsest of order 1655: the tall-panel factorization
-    and the register-resident inverse) is checked through properties that hold
-    at any size: convergence to the requested tolerance, the true residual
-    ||b - K x|| / ||b|| computed on the CPU, and an iteration count in the
-    range the method reaches on this workload.
+    panels for tall blocks and the compact update grids) on sampled dofs: a
+    one-level restricted apply must equal, at each sampled dof g, the entry of
+    A_i^{-1} R_i r of g's owning part, computed on the CPU with a dense LU of the
+    local block taken from the oracle's maps (section 2.1);
+  * the whole three-level apply of eq. (2.2) against the oracle's, element by
+    element (coarsest of order 1655: the tall-panel factorization and the
+    register-resident inverse);
+  * the FGMRES solve against the oracle's FGMRES with the oracle's
+    preconditioner: convergence, the true residual recomputed on the CPU,
+    iteration counts within 2, and the two solutions.
 """
 import sys
 
@@ -76,16 +76,34 @@ def test_fullsize_local_solves_on_sampled_dofs(gd):
     assert worst <= 1e-10
 
 
-def test_fullsize_three_level_solve_properties(gd):
+def _errs(z, zo):
+    return (float(np.linalg.norm(z - zo) / np.linalg.norm(zo)),
+            float(np.abs(z - zo).max() / np.abs(zo).max()))
+
+
+def test_fullsize_three_level_apply_and_solve_match_oracle(gd):
     P = _die(3)
-    _say("fullsize three-level solve, n =", P.n)
+    _say("fullsize three-level oracle setup, n =", P.n)
+    H = cached(("die32_h", 3), lambda: oracle.setup(P))
+    K = P.K()
+    r = random_vector(P.n, 12)
+    zo = oracle.apply(H, r)
+    _say("oracle FGMRES")
+    xo, info_o = oracle.fgmres(lambda v: K @ v, lambda v: oracle.apply(H, v), P.b, tol=1e-8)
     with gd.Context(P, tol=1e-8) as ctx:
+        z = ctx.apply(_dev(r)).cpu().numpy()
         x, info = ctx.solve(_dev(P.b))
         st = ctx.stats()
     x = x.cpu().numpy()
-    res = np.linalg.norm(P.b - P.K() @ x) / np.linalg.norm(P.b)
-    _say("iterations", info["iterations"], "true residual", res, "coarsest order", st["n"][2])
-    assert info["converged"]
-    assert res <= 1e-8
-    assert st["n"][2] > 1536          # the coarsest takes the tall-panel path
-    assert info["iterations"] <= 60
+    err, emax = _errs(z, zo)
+    res = np.linalg.norm(P.b - K @ x) / np.linalg.norm(P.b)
+    xerr, xmax = _errs(x, xo)
+    _say("apply rel err", err, "max err", emax, "| iterations gpu", info["iterations"], "oracle",
+         info_o["iterations"], "| true residual", res, "| solution vs oracle", xerr, xmax,
+         "| coarsest order", st["n"][2])
+    assert st["n"][2] == H.K_coarsest.shape[0] > 1536      # the coarsest takes the tall-panel path
+    assert err <= 1e-10 and emax <= 1e-10
+    assert info["converged"] and info_o["converged"]
+    assert res <= 1e-8 * 1.0001
+    assert abs(info["iterations"] - info_o["iterations"]) <= 2
+    assert xerr <= 1e-5 and xmax <= 1e-5

@@ -57,6 +57,12 @@ def _dev(x):
     return torch.as_tensor(np.asarray(x, dtype=np.float64), device="cuda")
 
 
+def _errs(z, zo):
+    """(||z - zo||_2 / ||zo||_2, max_g |z_g - zo_g| / max_g |zo_g|)"""
+    return (float(np.linalg.norm(z - zo) / np.linalg.norm(zo)),
+            float(np.abs(z - zo).max() / np.abs(zo).max()))
+
+
 def test_mfma_layout_and_lu_via_tiny_solve(gd):
     """Single part covering a 2^3 cube, no coarse level: the apply is K^{-1} (one dense LU of order n)."""
     P = unit_cube_problem(n=2, block=2)
@@ -95,9 +101,9 @@ def test_apply_parity_fp64(gd, name, combine):
             r = random_vector(P.n, seed)
             z = ctx.apply(_dev(r)).cpu().numpy()
             zo = oracle.apply(H, r)
-            err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
-            _say("  seed", seed, "rel err", err)
-            assert err <= 1e-10
+            err, emax = _errs(z, zo)
+            _say("  seed", seed, "rel err", err, "max err", emax)
+            assert err <= 1e-10 and emax <= 1e-10
 
 
 def test_spmv_matches_cpu_product(gd):
@@ -127,9 +133,9 @@ def test_apply_parity_blocks_of_order_2295(gd, precision, tol):
         r = random_vector(P.n, 6)
         z = ctx.apply(_dev(r)).cpu().numpy()
     zo = oracle.apply(H, r)
-    err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
-    _say("  rel err", err)
-    assert err <= tol
+    err, emax = _errs(z, zo)
+    _say("  rel err", err, "max err", emax)
+    assert err <= tol and emax <= tol
 
 
 def _tall():
@@ -154,9 +160,9 @@ def test_apply_parity_tall_coarsest(gd, name):
         r = random_vector(P.n, 3)
         z = ctx.apply(_dev(r)).cpu().numpy()
     zo = oracle.apply(H, r)
-    err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
-    _say("  rel err", err)
-    assert err <= 1e-10
+    err, emax = _errs(z, zo)
+    _say("  rel err", err, "max err", emax)
+    assert err <= 1e-10 and emax <= 1e-10
 
 
 @pytest.mark.parametrize("name", ["cube4_L2", "die16_L3"])
@@ -168,9 +174,9 @@ def test_apply_mixed_precision_error(gd, name):
         r = random_vector(P.n, 5)
         z = ctx.apply(_dev(r)).cpu().numpy()
     zo = oracle.apply(H, r)
-    err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
-    _say("  mixed rel err vs fp64 oracle", err)
-    assert err <= 1e-3
+    err, emax = _errs(z, zo)
+    _say("  mixed rel err vs fp64 oracle", err, "max err", emax)
+    assert err <= 1e-3 and emax <= 1e-3
 
 
 @pytest.mark.parametrize("combine", ["RAS", "AS"])
@@ -295,7 +301,8 @@ def test_local_solve_wave_counts_are_bit_identical(gd, precision, tol):
             zs[wv] = ctx.apply(_dev(r)).cpu().numpy()
             assert list(ctx.stats()["ls_waves"][:3]) == [wv] * 3
     assert np.array_equal(zs[2], zs[8]) and np.array_equal(zs[4], zs[8])
-    assert np.linalg.norm(zs[8] - zo) <= tol * np.linalg.norm(zo)
+    err, emax = _errs(zs[8], zo)
+    assert err <= tol and emax <= tol
     with pytest.raises(gd.GdswError):
         gd.Context(P, ls_waves=3, precision=precision)
 
@@ -312,3 +319,78 @@ def test_autotuned_local_solves_are_bit_identical(gd):
         waves = t.stats()["ls_waves"][:3]
     assert all(w in (2, 4, 8) for w in waves), waves
     assert np.array_equal(za, zt)
+
+
+@pytest.mark.parametrize("name", ["cube4_L2", "die16_L2"])
+def test_solve_parity_additive_two_levels(gd, name):
+    """The additive combination printed in eq. (2.2) converges with two levels: GPU FGMRES against the
+    oracle's FGMRES with the same preconditioner."""
+    P = cached(("gpu", name), lambda: unit_cube_problem() if name == "cube4_L2"
+               else die_problem(16, 8, 8, seed=0, levels=2))
+    K = P.K()
+    H = cached(("orc-as", name), lambda: oracle.setup(P, combine="AS"))
+    tol = 1e-8
+    xo, info_o = oracle.fgmres(lambda v: K @ v, lambda v: oracle.apply(H, v), P.b, tol=tol)
+    _say("solve additive", name, "oracle iterations", info_o["iterations"])
+    with gd.Context(P, combine="AS", tol=tol) as ctx:
+        x, info = ctx.solve(_dev(P.b))
+    x = x.cpu().numpy()
+    _say("  gpu iterations", info["iterations"], "rel residual", info["rel_residual"])
+    assert info_o["converged"] and info["converged"]
+    assert np.linalg.norm(K @ x - P.b) <= tol * np.linalg.norm(P.b) * 1.0001
+    assert abs(info["iterations"] - info_o["iterations"]) <= 2
+    assert np.linalg.norm(x - xo) <= 1e3 * tol * np.linalg.norm(xo)
+
+
+def test_notconv_returns_last_iterate(gd):
+    """max_it reached: GDSW_NOTCONV, x holds the last iterate (the oracle's after the same number of
+    iterations) and info the true residual of that iterate."""
+    name = "die16_L3"
+    P = _problem(name)
+    K = P.K()
+    its = 7
+    xo, info_o = oracle.fgmres(lambda v: K @ v, lambda v: oracle.apply(_orc(name), v), P.b, tol=1e-12, max_it=its)
+    _say("notconv after", its, "iterations")
+    with gd.Context(P, tol=1e-12, max_it=its) as ctx:
+        x, info = ctx.solve(_dev(P.b))
+    x = x.cpu().numpy()
+    assert info["code"] == gd.NOTCONV and not info["converged"]
+    assert info["iterations"] == its == info_o["iterations"]
+    res = np.linalg.norm(P.b - K @ x) / np.linalg.norm(P.b)
+    _say("  residual", res, "reported", info["rel_residual"], "oracle", info_o["rel_residual"])
+    assert abs(info["rel_residual"] - res) <= 1e-10 * res
+    assert abs(res - info_o["rel_residual"]) <= 1e-6 * res
+    err, emax = _errs(x, xo)
+    assert err <= 1e-8 and emax <= 1e-8
+
+
+def test_failed_setup_leaves_the_library_usable(gd):
+    """A three-level setup whose part hierarchy is out of range fails with EINVAL after level-1 work was
+    queued; the library drains it before recycling the blocks, and a later setup + apply is bit-identical
+    to one made before the failure."""
+    P = _problem("die16_L3")
+    r = _dev(random_vector(P.n, 4))
+    _say("failed setup then reuse")
+    with gd.Context(P) as ctx:
+        z1 = ctx.apply(r).cpu().numpy()
+    bad_parent = np.full_like(P.part_parent[0], P.n_parts[1] + 5)
+    bad = P.with_hierarchy(P.elem_part, P.n_parts, [bad_parent], P.levels)
+    with pytest.raises(gd.GdswError, match="EINVAL"):
+        gd.Context(bad)
+    with gd.Context(P) as ctx:
+        z2 = ctx.apply(r).cpu().numpy()
+    assert np.array_equal(z1, z2)
+
+
+def test_context_rejects_mistyped_csr(gd):
+    """K handed in with the wrong index width is refused on the host, before any kernel reads it."""
+    P = _problem("cube4_L2")
+    dev = torch.device("cuda", torch.cuda.current_device())
+    K = (torch.as_tensor(P.rowptr, device=dev), torch.as_tensor(P.col.astype(np.int64), device=dev),
+         torch.as_tensor(P.val, device=dev))
+    with pytest.raises(TypeError):
+        gd.Context(P, K=K)
+    K = (torch.as_tensor(P.rowptr[:-1], device=dev), torch.as_tensor(P.col, device=dev),
+         torch.as_tensor(P.val, device=dev))
+    with pytest.raises(ValueError):
+        gd.Context(P, K=K)
