@@ -4,6 +4,7 @@
 #include "../../include/gdsw.h"
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <map>
@@ -29,6 +30,20 @@ thread_local std::string g_last_error;
 
 double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Wait for an event by polling it: the Krylov loop waits once per iteration for
+// a few microseconds of copy after its apply, so a blocking synchronization's
+// wake-up latency is avoided; after the first 50 us the thread yields its core
+// between queries, so that concurrent solves on other threads (serving) are
+// not starved by spinning ones.
+void wait_event_polling(hipEvent_t e) {
+  const auto t0 = std::chrono::steady_clock::now();
+  hipError_t q;
+  while ((q = hipEventQuery(e)) == hipErrorNotReady) {
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(50)) std::this_thread::yield();
+  }
+  if (q != hipSuccess) throw Error(GDSW_EHIP, std::string("hipEventQuery: ") + hipGetErrorString(q));
 }
 
 // Process-wide cache of device blocks, per device: the blocks of a destroyed
@@ -238,6 +253,8 @@ struct gdsw_ctx {
   hipEvent_t ev_fetch = nullptr;       // Hessenberg column copied to the host
   double *V = nullptr, *Z = nullptr, *wv = nullptr, *dpart = nullptr, *hdev = nullptr, *ydev = nullptr;
   double* hhost = nullptr;
+  // host-side Givens/Hessenberg arrays of the solve, sized at setup for the restart length
+  std::vector<double> kH, kcs, ksn, kg, ky;
   // event pairs around level-1 local-solve launches (profile = 1)
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
@@ -959,20 +976,66 @@ void apply_any(gdsw_ctx* C, const double* r, double* z, hipStream_t s) {
   else apply_level<double>(C, 0, r, z, s);
 }
 
-void ensure_workspace(gdsw_ctx* C) {
+// Device workspace of one FGMRES(m) solve on n rows.
+struct KrylovWs {
+  double *V = nullptr, *Z = nullptr, *w = nullptr, *dpart = nullptr, *hdev = nullptr, *ydev = nullptr;
+};
+
+// Sizes (doubles) of the workspace pieces, in the order V, Z, w, dpart, hdev, ydev.
+std::array<size_t, 6> krylov_ws_sizes(int64_t n, int m) {
+  return {(size_t)n * (m + 1), (size_t)n * m, (size_t)n, (size_t)multi_dot_blocks(n) * (m + 2),
+          (size_t)2 * (m + 2) + 2, (size_t)m + 1};
+}
+
+// Carve the pieces out of one region; every piece starts on a 256-byte boundary.
+// Returns the doubles used (base == nullptr: only the size).
+size_t carve_krylov_ws(double* base, int64_t n, int m, KrylovWs* ws) {
+  const std::array<size_t, 6> sz = krylov_ws_sizes(n, m);
+  double** dst[6] = {&ws->V, &ws->Z, &ws->w, &ws->dpart, &ws->hdev, &ws->ydev};
+  size_t off = 0;
+  for (int k = 0; k < 6; ++k) {
+    if (base) *dst[k] = base + off;
+    off += (sz[k] + 31) & ~size_t(31);
+  }
+  return off;
+}
+
+// Host-side resources every solve needs, created at setup (the page-locked
+// buffer the Hessenberg column is read into, its event, the Givens arrays).
+void create_solve_host_state(gdsw_ctx* C) {
   const int m = C->opt.restart;
-  if (C->ws_m == m) return;
-  const int64_t n = C->levels[0].n;
-  Arena& A = C->arena;
-  C->V = A.alloc_n<double>((size_t)n * (m + 1));
-  C->Z = A.alloc_n<double>((size_t)n * m);
-  C->wv = A.alloc_n<double>((size_t)n);
-  C->dpart = A.alloc_n<double>((size_t)multi_dot_blocks(n) * (m + 2));
-  C->hdev = A.alloc_n<double>((size_t)2 * (m + 2) + 2);
-  C->ydev = A.alloc_n<double>((size_t)m + 1);
   if (!C->hhost) GDSW_HIP(hipHostMalloc((void**)&C->hhost, sizeof(double) * (2 * 256 + 8), hipHostMallocDefault));
   if (!C->ev_fetch) GDSW_HIP(hipEventCreateWithFlags(&C->ev_fetch, hipEventDisableTiming));
-  C->ws_m = m;
+  C->kH.assign((size_t)(m + 1) * m, 0.0);
+  C->kcs.assign(m, 0.0);
+  C->ksn.assign(m, 0.0);
+  C->kg.assign(m + 1, 0.0);
+  C->ky.assign(m, 0.0);
+}
+
+// The context's own workspace, allocated on its first solve.
+KrylovWs context_workspace(gdsw_ctx* C) {
+  const int m = C->opt.restart;
+  if (C->ws_m != m) {
+    const int64_t n = C->levels[0].n;
+    const std::array<size_t, 6> sz = krylov_ws_sizes(n, m);
+    Arena& A = C->arena;
+    C->V = A.alloc_n<double>(sz[0]);
+    C->Z = A.alloc_n<double>(sz[1]);
+    C->wv = A.alloc_n<double>(sz[2]);
+    C->dpart = A.alloc_n<double>(sz[3]);
+    C->hdev = A.alloc_n<double>(sz[4]);
+    C->ydev = A.alloc_n<double>(sz[5]);
+    C->ws_m = m;
+  }
+  KrylovWs ws;
+  ws.V = C->V;
+  ws.Z = C->Z;
+  ws.w = C->wv;
+  ws.dpart = C->dpart;
+  ws.hdev = C->hdev;
+  ws.ydev = C->ydev;
+  return ws;
 }
 
 // Apply of Krylov column j: eager, or replay of the graph captured for that column.
@@ -1004,11 +1067,13 @@ void column_apply(gdsw_ctx* C, int j, const double* v, double* z, hipStream_t s)
   GDSW_HIP(hipGraphLaunch(C->apply_exec[j], s));
 }
 
-int solve_impl(gdsw_ctx* C, const double* b, double* x, hipStream_t caller, gdsw_solve_info* info) {
+// FGMRES(m) on the workspace ws.  use_graph: applies replay captured graphs
+// (graph = 1 contexts, gdsw_solve only).
+int solve_impl(gdsw_ctx* C, const double* b, double* x, hipStream_t caller, gdsw_solve_info* info,
+               const KrylovWs& ws, bool use_graph) {
   const double t0 = now_ms();
-  ensure_workspace(C);
   hipStream_t s = caller;
-  if (C->opt.graph) {            // captured work needs a stream of its own (not the legacy default stream)
+  if (use_graph) {               // captured work needs a stream of its own (not the legacy default stream)
     if (!C->own) {
       GDSW_HIP(hipStreamCreateWithFlags(&C->own, hipStreamNonBlocking));
       GDSW_HIP(hipEventCreateWithFlags(&C->ev_in, hipEventDisableTiming));
@@ -1021,34 +1086,33 @@ int solve_impl(gdsw_ctx* C, const double* b, double* x, hipStream_t caller, gdsw
   struct Rejoin {
     gdsw_ctx* C;
     hipStream_t caller;
+    bool on;
     ~Rejoin() {
-      if (C->opt.graph && C->own) {
+      if (on && C->own) {
         (void)hipEventRecord(C->ev_out, C->own);
         (void)hipStreamWaitEvent(caller, C->ev_out, 0);
       }
     }
-  } rejoin{C, caller};
+  } rejoin{C, caller, use_graph};
   const int m = C->opt.restart;
   const int64_t n = C->levels[0].n;
   const CsrDev& K = C->levels[0].K;
-  double* V = C->V;
-  double* Z = C->Z;
-  double* w = C->wv;
-  double* h1 = C->hdev;               // [m+1]
-  double* h2 = C->hdev + (m + 1);     // [m+1]
-  double* nr = C->hdev + 2 * (m + 1); // [1]
+  double* V = ws.V;
+  double* Z = ws.Z;
+  double* w = ws.w;
+  double* dpart = ws.dpart;
+  double* h1 = ws.hdev;               // [m+1]
+  double* h2 = ws.hdev + (m + 1);     // [m+1]
+  double* nr = ws.hdev + 2 * (m + 1); // [1]
   double* hh = C->hhost;
   // the host polls an event after the copy (lower wake-up latency than a
   // blocking stream synchronization; the Krylov loop waits here every step)
   auto fetch = [&](int count) {
-    GDSW_HIP(hipMemcpyAsync(hh, C->hdev, count * sizeof(double), hipMemcpyDeviceToHost, s));
+    GDSW_HIP(hipMemcpyAsync(hh, ws.hdev, count * sizeof(double), hipMemcpyDeviceToHost, s));
     GDSW_HIP(hipEventRecord(C->ev_fetch, s));
-    hipError_t q;
-    while ((q = hipEventQuery(C->ev_fetch)) == hipErrorNotReady) {
-    }
-    GDSW_HIP(q);
+    wait_event_polling(C->ev_fetch);
   };
-  multi_dot(n, 1, b, n, b, C->dpart, nr, s);
+  multi_dot(n, 1, b, n, b, dpart, nr, s);
   GDSW_HIP(hipMemcpyAsync(hh, nr, sizeof(double), hipMemcpyDeviceToHost, s));
   GDSW_HIP(hipStreamSynchronize(s));
   const double bnorm = std::sqrt(hh[0]);
@@ -1060,7 +1124,11 @@ int solve_impl(gdsw_ctx* C, const double* b, double* x, hipStream_t caller, gdsw
     if (info) *info = inf;
     return GDSW_OK;
   }
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  std::vector<double>& H = C->kH;
+  std::vector<double>& cs = C->kcs;
+  std::vector<double>& sn = C->ksn;
+  std::vector<double>& g = C->kg;
+  std::vector<double>& y = C->ky;
   int its = 0;
   double ms_apply = 0, ms_spmv = 0, ms_orth = 0;
   const bool timing = std::getenv("GDSW_PHASE_TIMING") != nullptr;
@@ -1074,7 +1142,7 @@ int solve_impl(gdsw_ctx* C, const double* b, double* x, hipStream_t caller, gdsw
   while (true) {
     spmv(K, x, V, s);
     residual_from(n, b, V, s);
-    multi_dot(n, 1, V, n, V, C->dpart, nr, s);
+    multi_dot(n, 1, V, n, V, dpart, nr, s);
     GDSW_HIP(hipMemcpyAsync(hh, nr, sizeof(double), hipMemcpyDeviceToHost, s));
     GDSW_HIP(hipStreamSynchronize(s));
     const double beta = std::sqrt(hh[0]);
@@ -1102,15 +1170,15 @@ int solve_impl(gdsw_ctx* C, const double* b, double* x, hipStream_t caller, gdsw
       spmv(K, zj, w, s);
       tick(ms_spmv, last);
       // classical Gram-Schmidt with one reorthogonalisation (two fused axpy + dot passes)
-      multi_dot(n, j + 1, V, n, w, C->dpart, h1, s);
+      multi_dot(n, j + 1, V, n, w, dpart, h1, s);
       if (j + 1 <= fused_gs_max_cols()) {
-        axpy_dot(n, j + 1, V, n, h1, w, C->dpart, h2, false, s);
-        axpy_dot(n, j + 1, V, n, h2, w, C->dpart, nr, true, s);
+        axpy_dot(n, j + 1, V, n, h1, w, dpart, h2, false, s);
+        axpy_dot(n, j + 1, V, n, h2, w, dpart, nr, true, s);
       } else {
         multi_axpy(n, j + 1, V, n, h1, w, s);
-        multi_dot(n, j + 1, V, n, w, C->dpart, h2, s);
+        multi_dot(n, j + 1, V, n, w, dpart, h2, s);
         multi_axpy(n, j + 1, V, n, h2, w, s);
-        multi_dot(n, 1, w, n, w, C->dpart, nr, s);
+        multi_dot(n, 1, w, n, w, dpart, nr, s);
       }
       scale_by_inv_norm(n, w, nr, V + (int64_t)(j + 1) * n, s);
       fetch(2 * (m + 1) + 1);
@@ -1143,8 +1211,8 @@ int solve_impl(gdsw_ctx* C, const double* b, double* x, hipStream_t caller, gdsw
       y[i] = d != 0.0 ? t / d : 0.0;
     }
     for (int i = 0; i < k; ++i) hh[i] = -y[i];
-    GDSW_HIP(hipMemcpyAsync(C->ydev, hh, k * sizeof(double), hipMemcpyHostToDevice, s));
-    multi_axpy(n, k, Z, n, C->ydev, x, s);
+    GDSW_HIP(hipMemcpyAsync(ws.ydev, hh, k * sizeof(double), hipMemcpyHostToDevice, s));
+    multi_axpy(n, k, Z, n, ws.ydev, x, s);
     GDSW_HIP(hipStreamSynchronize(s));   // the host buffer is reused by the next fetch
     inf.restarts++;
   }
@@ -1232,6 +1300,7 @@ int gdsw_setup(const gdsw_problem* prob, const gdsw_options* opt, void* stream, 
     if (C->mixed) gdsw::setup_impl<float>(C, prob, s);
     else gdsw::setup_impl<double>(C, prob, s);
     for (size_t l = 0; l < C->levels.size() && l < 8; ++l) C->stats.ls_waves[l] = C->levels[l].ls_waves;
+    gdsw::create_solve_host_state(C);
     if (C->opt.tune) {
       if (C->mixed) gdsw::tune_local_solves<float>(C, s);
       else gdsw::tune_local_solves<double>(C, s);
@@ -1268,7 +1337,8 @@ int gdsw_solve(gdsw_ctx* C, const double* b, double* x, void* stream, gdsw_solve
     return GDSW_EINVAL;
   }
   try {
-    return gdsw::solve_impl(C, b, x, static_cast<hipStream_t>(stream), info);
+    const gdsw::KrylovWs ws = gdsw::context_workspace(C);
+    return gdsw::solve_impl(C, b, x, static_cast<hipStream_t>(stream), info, ws, C->opt.graph != 0);
   } catch (const Error& e) {
     return gdsw::fail(e);
   }
