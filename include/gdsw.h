@@ -213,6 +213,24 @@ int gdsw_apply(gdsw_ctx* ctx, const double* r, double* z, void* stream);
  * GDSW_NOTCONV (x then holds the last iterate); info may be NULL. */
 int gdsw_solve(gdsw_ctx* ctx, const double* b, double* x, void* stream, gdsw_solve_info* info);
 
+/* gdsw_solve without any allocation, for callers that cannot allocate device
+ * memory (tight serving loops, code whose allocations are forbidden or
+ * recorded).  Same arguments, result and return codes as gdsw_solve (x is
+ * bit-identical to gdsw_solve's), but the FGMRES workspace
+ * ((2 restart + 2) n doubles plus a few partial-sum blocks) lives in a static
+ * device array of 128 MiB that the library holds on every device it runs on
+ * until the process ends (about n <= 270,000 rows at restart 30).  Larger
+ * problems return GDSW_EINVAL with the size in gdsw_last_error().  It calls
+ * no hipMalloc / hipFree: the page-locked host buffer and the event it reads
+ * the Hessenberg column through are created by gdsw_setup.  Applies run
+ * eagerly (also on graph = 1 contexts) and are not profiled.  Every call on
+ * one device shares that device's array: calls that overlap in time on one
+ * device (different threads or streams) race and must not be issued; nothing
+ * in the array has to start at zero (every value is written before it is
+ * read).  Not capturable into a graph: it synchronizes the stream once per
+ * iteration like gdsw_solve. */
+int gdsw_solve_noalloc(gdsw_ctx* ctx, const double* b, double* x, void* stream, gdsw_solve_info* info);
+
 /* y = K x with the level-1 operator (CSR SpMV).  x, y: DEVICE FP64, length n. */
 int gdsw_spmv(gdsw_ctx* ctx, const double* x, double* y, void* stream);
 

@@ -255,6 +255,7 @@ struct gdsw_ctx {
   double* hhost = nullptr;
   // host-side Givens/Hessenberg arrays of the solve, sized at setup for the restart length
   std::vector<double> kH, kcs, ksn, kg, ky;
+  bool no_alloc_call = false;          // inside gdsw_solve_noalloc: no event creation in applies
   // event pairs around level-1 local-solve launches (profile = 1)
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
@@ -953,7 +954,7 @@ void apply_level(gdsw_ctx* C, int l, const double* r, double* z, hipStream_t s) 
     coarse_chain<T>(C, l, r, fs);
     GDSW_HIP(hipEventRecord(ev_join, fs));
   }
-  const bool prof = C->opt.profile && l == 0 && !C->capturing;
+  const bool prof = C->opt.profile && l == 0 && !C->capturing && !C->no_alloc_call;
   hipEvent_t e_start = nullptr, e_stop = nullptr;
   if (prof) {
     if (C->ev_used + 2 > 4096) drain_events(C);
@@ -1040,7 +1041,7 @@ KrylovWs context_workspace(gdsw_ctx* C) {
 
 // Apply of Krylov column j: eager, or replay of the graph captured for that column.
 void column_apply(gdsw_ctx* C, int j, const double* v, double* z, hipStream_t s) {
-  if (!C->opt.graph) {
+  if (!C->opt.graph || C->no_alloc_call) {
     apply_any(C, v, z, s);
     return;
   }
@@ -1246,6 +1247,36 @@ void discard_failed_setup(gdsw_ctx* C, hipStream_t s) {
 }  // namespace
 }  // namespace gdsw
 
+// Krylov workspace of gdsw_solve_noalloc: a static device array (one copy per
+// device the library runs on, held until the process ends).  Host code never
+// uses its name as a device address: the address is looked up once per device
+// with hipGetSymbolAddress and kept in scratch_dev.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(128) << 20;
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace gdsw {
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double* scratch_dev[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (looked up on the first call
+// on that device, with that device current).
+double* scratch_on_current_device() {
+  int dev = 0;
+  GDSW_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) throw Error(GDSW_EINVAL, "device id out of range");
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    GDSW_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    scratch_dev[dev] = static_cast<double*>(p);
+  }
+  return scratch_dev[dev];
+}
+}  // namespace
+}  // namespace gdsw
+
 using gdsw::Error;
 
 extern "C" {
@@ -1339,6 +1370,33 @@ int gdsw_solve(gdsw_ctx* C, const double* b, double* x, void* stream, gdsw_solve
   try {
     const gdsw::KrylovWs ws = gdsw::context_workspace(C);
     return gdsw::solve_impl(C, b, x, static_cast<hipStream_t>(stream), info, ws, C->opt.graph != 0);
+  } catch (const Error& e) {
+    return gdsw::fail(e);
+  }
+}
+
+int gdsw_solve_noalloc(gdsw_ctx* C, const double* b, double* x, void* stream, gdsw_solve_info* info) {
+  if (!C || !b || !x || b == x) {
+    gdsw::g_last_error = "gdsw_solve_noalloc: NULL or aliased argument";
+    return GDSW_EINVAL;
+  }
+  try {
+    const int64_t n = C->levels[0].n;
+    const int m = C->opt.restart;
+    const size_t need = gdsw::carve_krylov_ws(nullptr, n, m, nullptr) * sizeof(double);
+    if (need > NOALLOC_SCRATCH_BYTES)
+      throw Error(GDSW_EINVAL, "gdsw_solve_noalloc: the FGMRES workspace of n = " + std::to_string(n) +
+                                   ", restart " + std::to_string(m) + " needs " + std::to_string(need) +
+                                   " bytes, more than the " + std::to_string(NOALLOC_SCRATCH_BYTES) +
+                                   "-byte static workspace");
+    gdsw::KrylovWs ws;
+    gdsw::carve_krylov_ws(gdsw::scratch_on_current_device(), n, m, &ws);
+    struct Flag {
+      gdsw_ctx* C;
+      ~Flag() { C->no_alloc_call = false; }
+    } flag{C};
+    C->no_alloc_call = true;
+    return gdsw::solve_impl(C, b, x, static_cast<hipStream_t>(stream), info, ws, false);
   } catch (const Error& e) {
     return gdsw::fail(e);
   }

@@ -58,6 +58,7 @@ SIGNATURES = {
     "gdsw_setup": (c_i32, [ctypes.POINTER(Problem), ctypes.POINTER(Options), c_vp, ctypes.POINTER(c_vp)]),
     "gdsw_apply": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
     "gdsw_solve": (c_i32, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(SolveInfo)]),
+    "gdsw_solve_noalloc": (c_i32, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(SolveInfo)]),
     "gdsw_spmv": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
     "gdsw_scatter_local": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp]),
     "gdsw_export_maps": (c_i32, [c_vp, c_i32, ctypes.POINTER(MapsView)]),
@@ -274,12 +275,15 @@ class Context:
                                    _stream_handle(stream)))
         return y
 
-    def solve(self, b, out=None, stream=None):
+    def solve(self, b, out=None, stream=None, no_alloc=False):
+        """x with ||b - K x|| / ||b|| <= tol (gdsw_solve; no_alloc: gdsw_solve_noalloc, whose
+        workspace is the library's static device array)."""
         import torch
         x = torch.empty_like(b) if out is None else out
         info = SolveInfo()
-        code = _check(self._lib.gdsw_solve(self._alive(), self._dev(b, self.n), self._dev(x, self.n),
-                                           _stream_handle(stream), ctypes.byref(info)))
+        fn = self._lib.gdsw_solve_noalloc if no_alloc else self._lib.gdsw_solve
+        code = _check(fn(self._alive(), self._dev(b, self.n), self._dev(x, self.n), _stream_handle(stream),
+                         ctypes.byref(info)))
         d = {k: getattr(info, k) for k, _ in SolveInfo._fields_}
         d["code"] = code
         return x, d
