@@ -1,11 +1,19 @@
 """Throughput of the whole GDSW hot path on one MI355X.
 
-One step = gdsw_setup (index maps, local LU factorizations, GDSW basis,
-Galerkin recursion, coarsest factorization) + gdsw_solve (FGMRES(30) to a
-relative residual of 1e-8 preconditioned by the three-level method) +
-gdsw_destroy, on a seeded 32x16x16 die-like voxel channel (Q2-P1disc, Carreau
-nu0 = 1, lambda = 1, n = 0.5, 2^3-voxel parts, 2x2x2 subregions).  The matrix
-and the right-hand side are resident in HBM before the timed region.
+Headline: one step = gdsw_setup (index maps, local LU factorizations, GDSW
+basis, Galerkin recursion, coarsest factorization) + gdsw_solve (FGMRES(30) to
+a relative residual of 1e-8) + gdsw_destroy, on the batching workload: a
+seeded 96x48x48 die-like voxel channel (Q2-P1disc, Carreau nu0 = 1, lambda =
+10, n = 0.4; level-1 parts of 2 or 3 voxels per axis, about 21k of them; four
+levels), FP32 local factors and bases, FP64 Krylov / residuals / coarsest
+solve, restricted combination, autotuned local solves.  The matrix and the
+right-hand side are resident in HBM before the timed region.
+
+Further objects on the same JSON line: the level-1 local-solve roofline, the
+whole-apply roofline, the event-timed level-1 LU kernel rate, setup-amortized
+solves (eager against captured graphs) with the SpMV roofline, the precision
+workload (64x32x32 die, three levels, FP64 against FP32 factors), the
+three-level FP64 32x16x16 die, the serving stream, and the oracle on the host.
 
 Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
 """
@@ -19,11 +27,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_TFLOPS = 78.6
+FP32_MFMA_TFLOPS = 157.3
 
-# HBM traffic of one level-1 local-solve launch on this workload, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE runs scaled by a 1 GiB copy (profiles/local_solve_die32x16x16.md), valid only for the
-# local-solve kernel source it was measured on.
-LOCAL_SOLVE_TRAFFIC = {"bytes": 3.993e9, "source_hash": "935223e387098f25", "precision": "fp64"}
+# HBM traffic of one level-1 local-solve launch per workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# runs scaled by a plain 1 GiB device copy (profiles/), valid only for the local-solve kernel source it
+# was measured on (hash of that part of apply.hip) and for the precision and seed it was taken with.
+LOCAL_SOLVE_TRAFFIC = {
+    ("die32x16x16", "fp64"): {"bytes": 3.993e9, "source_hash": "935223e387098f25"},
+}
+
+WORKLOADS = {
+    # batching workload (headline): four levels, uneven 2/3-voxel parts, FP32 factors
+    "die96x48x48": dict(shape=(96, 48, 48), nu0=1.0, lam=10.0, n_exp=0.4, levels=4, frac3=0.1),
+    # precision workload: same operator as the 32x16x16 die on 64x32x32, three levels
+    "die64x32x32": dict(shape=(64, 32, 32), nu0=1.0, lam=1.0, n_exp=0.5, levels=3, frac3=0.0),
+    # three-level FP64 workload
+    "die32x16x16": dict(shape=(32, 16, 16), nu0=1.0, lam=1.0, n_exp=0.5, levels=3, frac3=0.0),
+}
 
 
 def local_solve_source_hash():
@@ -31,50 +52,201 @@ def local_solve_source_hash():
     src = open(os.path.join(ROOT, "paper_2606_01433_amd", "csrc", "apply.hip")).read()
     a, b = src.index("// Local solves w_i"), src.index("__global__ void k_scatter_sum")
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
-FP64_MFMA_TFLOPS = 78.6
-FP32_MFMA_TFLOPS = 157.3
 
 
-def workload(args):
+def say(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def make_problem(name, seed=0):
     from harness import die_problem
-    return die_problem(32, 16, 16, seed=args.seed, nu0=1.0, lam=1.0, n_exp=0.5, levels=3)
+    w = WORKLOADS[name]
+    nx, ny, nz = w["shape"]
+    t0 = time.perf_counter()
+    P = die_problem(nx, ny, nz, seed=seed, nu0=w["nu0"], lam=w["lam"], n_exp=w["n_exp"], levels=w["levels"],
+                    frac3=w["frac3"])
+    say(f"{name}: assembled in {time.perf_counter() - t0:.1f} s, n = {P.n}, nnz = {len(P.col)}, parts {P.n_parts}")
+    return P
 
 
-def cpu_baseline(P, gpu_iterations, budget_its=4):
-    """Oracle (FP64 NumPy/SciPy, single thread): full setup, then a few FGMRES iterations, extrapolated."""
-    from threadpoolctl import threadpool_limits
-    import numpy as np
-    import oracle
-    with threadpool_limits(limits=1):
+def describe(name, precision):
+    w = WORKLOADS[name]
+    nx, ny, nz = w["shape"]
+    parts = "2- or 3-voxel parts per axis (3 with probability 0.1)" if w["frac3"] else "2^3-voxel parts"
+    prec = "FP64" if precision == "fp64" else "FP32 local factors and bases, FP64 Krylov/residuals/coarsest"
+    return (f"{w['levels']}-level monolithic GDSW, restricted (RAS) combination, {prec}, FGMRES(30) to 1e-8; "
+            f"{nx}x{ny}x{nz} seeded voxel die (~20% masked), Q2-P1disc, Carreau nu0={w['nu0']:g} "
+            f"lambda={w['lam']:g} n={w['n_exp']:g}, {parts}, overlap 1")
+
+
+class Runner:
+    """Device copies of one problem and the setup + solve + destroy step on them."""
+
+    def __init__(self, P, stream):
+        import torch
+        dev = torch.device("cuda", 0)
+        self.P = P
+        self.K = (torch.as_tensor(P.rowptr, device=dev), torch.as_tensor(P.col, device=dev),
+                  torch.as_tensor(P.val, device=dev))
+        self.b = torch.as_tensor(P.b, device=dev)
+        self.stream = stream
+        self.Kh = P.K().tocsr()
+
+    def context(self, **opts):
+        from paper_2606_01433_amd import gdsw
+        return gdsw.Context(self.P, K=self.K, tol=1e-8, stream=self.stream, **opts)
+
+    def step(self, **opts):
+        ctx = self.context(**opts)
+        x, info = ctx.solve(self.b, stream=self.stream)
+        st = ctx.stats()
+        ctx.close()
+        return x, info, st
+
+    def true_residual(self, x):
+        import numpy as np
+        xh = x.cpu().numpy()
+        return float(np.linalg.norm(self.P.b - self.Kh @ xh) / np.linalg.norm(self.P.b))
+
+    def timed_steps(self, steps, warmup, **opts):
+        import torch
+        for _ in range(warmup):
+            self.step(**opts)
+        torch.cuda.synchronize()
+        infos, stats = [], []
         t0 = time.perf_counter()
-        H = oracle.setup(P)
-        t1 = time.perf_counter()
-        K = P.K()
-        _, info = oracle.fgmres(lambda v: K @ v, lambda v: oracle.apply(H, v), P.b, tol=1e-8, max_it=budget_its)
-        t2 = time.perf_counter()
-    per_it = (t2 - t1) / max(1, info["iterations"])
-    t_solve = (t1 - t0) + per_it * gpu_iterations
-    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle setup of the full workload ({t1 - t0:.1f} s) + {info['iterations']} FGMRES "
-                       f"iterations ({per_it:.2f} s each), extrapolated to the GPU's {gpu_iterations} iterations")}
+        for _ in range(steps):
+            x, info, st = self.step(**opts)
+            infos.append(info)
+            stats.append(st)
+        torch.cuda.synchronize()
+        T = (time.perf_counter() - t0) / steps
+        return T, x, infos, stats
 
 
-def serving_bench(seed=0, n_requests=24):
-    """Poisson stream of Picard-step solves over a pool of seeded dies: FP32-factor serving with
-    concurrent slots vs. plain FP64 one at a time on the same arrival times."""
+def local_solve_roofline(stats, traffic_key, precision, seed):
+    launches = sum(s["local_solve_launches"] for s in stats)
+    ms_ls = sum(s["ms_local_solve"] for s in stats)
+    bytes_per_launch = stats[0]["local_solve_bytes"]
+    achieved = bytes_per_launch / (ms_ls / launches * 1e-3) / 1e9 if launches else 0.0
+    traffic = None
+    rec = LOCAL_SOLVE_TRAFFIC.get((traffic_key, precision))
+    if rec and rec["source_hash"] == local_solve_source_hash() and seed == 0:
+        traffic = rec["bytes"]
+    return {"kernel": "k_local_solve_wg (level-1 batched pivoted-LU forward/backward substitution, "
+                      + ("FP64" if precision == "fp64" else "FP32") + " factors)",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": bytes_per_launch,
+            "launches": launches, "avg_launch_us": ms_ls / launches * 1e3 if launches else None}
+
+
+def lu_rate(stats, precision):
+    """Level-1 LU flops sum (2/3) n_i^3 over the event-timed level-1 LU kernels (median over steps)."""
+    import numpy as np
+    ms = float(np.median([s["ms_lu"][0] for s in stats]))
+    fl = stats[0]["factor_flops"][0]
+    peak = FP64_MFMA_TFLOPS if precision == "fp64" else FP32_MFMA_TFLOPS
+    tf = fl / (ms * 1e-3) / 1e12
+    return {"flops_level1": fl, "ms_lu_kernels_level1": ms, "achieved_tflops": tf, "peak_tflops": peak,
+            "frac": tf / peak, "bound": "mfma",
+            "note": "events around the level-1 batched LU launches on their stream; the basis / Galerkin / "
+                    "coarse chain runs concurrently on other streams"}
+
+
+def apply_roofline(run, precision, n_apply=10):
+    """Whole apply of eq. (2.2): the library's algorithmic bytes over the event-timed apply (all levels,
+    side streams joined)."""
+    import torch
+    from harness import random_vector
+    ctx = run.context(precision=precision)
+    r = torch.as_tensor(random_vector(run.P.n, 3), device="cuda")
+    z = torch.empty_like(r)
+    with torch.cuda.stream(run.stream):
+        ctx.apply(r, out=z, stream=run.stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(run.stream)
+        for _ in range(n_apply):
+            ctx.apply(r, out=z, stream=run.stream)
+        e1.record(run.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / n_apply
+    A = ctx.stats()["apply_bytes"]
+    ctx.close()
+    return {"bound": "hbm", "achieved": A / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": A / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "bytes_per_apply": A, "ms_per_apply": ms}
+
+
+def spmv_roofline(ctx, P, x, stream, calls=50):
+    """y = K x through the library, timed with HIP events on the launching stream: algorithmic bytes
+    (CSR values and int32 columns, int64 row pointers, x once, y) over the mean duration."""
+    import torch
+    y = torch.empty_like(x)
+    ctx.spmv(x, out=y, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(calls):
+        ctx.spmv(x, out=y, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) / calls * 1e3
+    nbytes = 12.0 * len(P.col) + 8.0 * (P.n + 1) + 16.0 * P.n
+    return {"bound": "hbm", "achieved": nbytes / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_call": nbytes, "us_per_call": us}
+
+
+def solve_only(run, precision, n_solves, tune=False):
+    """Setup amortized: solves on one context, eager applies against captured hipGraph applies."""
+    import torch
+    out = {}
+    for graph in (False, True):
+        ctx = run.context(precision=precision, graph=graph, tune=tune)
+        ctx.solve(run.b, stream=run.stream)                 # warm-up (captures the graphs in graph mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n_solves):
+            x, info = ctx.solve(run.b, stream=run.stream)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / n_solves
+        out["graph" if graph else "eager"] = {"ms_per_solve": dt * 1e3, "solves_per_s": 1.0 / dt,
+                                              "iterations": info["iterations"]}
+        if not graph:
+            out["spmv"] = spmv_roofline(ctx, run.P, run.b, run.stream)
+        ctx.close()
+    return out
+
+
+def workload_leg(name, precision, steps, warmup, stream, seed=0, P=None):
+    """setup + solve + destroy steps of one workload in one precision."""
+    P = make_problem(name, seed) if P is None else P
+    run = Runner(P, stream)
+    T, x, infos, stats = run.timed_steps(steps, warmup, precision=precision, profile=True)
+    st = stats[0]
+    return run, x, {
+        "workload": describe(name, precision), "n_dofs": int(P.n), "nnz": int(len(P.col)),
+        "solves_per_s": 1.0 / T, "ms_per_step": T * 1e3, "steps": steps,
+        "iterations": infos[-1]["iterations"], "true_rel_residual": run.true_residual(x),
+        "parts": st["parts"][:st["levels"]], "level_dofs": st["n"][:st["levels"]],
+        "ms_setup": st["ms_total"], "ms_solve": infos[-1]["ms_total"],
+        "roofline_local_solve": local_solve_roofline(stats, name, precision, seed),
+        "lu_kernels": lu_rate(stats, precision)}
+
+
+def serving_bench(seed=0, n_requests=16, loads=(0.5, 0.8, 0.95)):
+    """Poisson streams of Picard-step solves over seeded dies of 7 sizes (16^3 .. 64x32x32) with Carreau
+    n ~ U[0.3, 0.9] and lambda = 10^U[-1, 1]: FP32-factor serving with 4 slots against FP64 with 4 slots
+    and FP64 one at a time, at arrival rates rho x the FP64 one-at-a-time capacity."""
     import numpy as np
     from harness import die_problem
     from paper_2606_01433_amd.serving import Server, Request, summarize
     rng = np.random.Generator(np.random.PCG64(seed + 7))
     pool = []
-    for nx, ny, nz in [(16, 16, 16), (32, 16, 16), (48, 24, 24), (64, 32, 32)]:
-        for q in range(2):
-            n_exp = float(rng.uniform(0.3, 0.9))
-            lam = float(10.0 ** rng.uniform(-1.0, 1.0))
-            # four levels on the larger dies keep the coarsest dense problem at order ~2k
-            levels = 3 if nx * ny * nz <= 8192 else 4
-            pool.append(die_problem(nx, ny, nz, seed=seed + q, nu0=1.0, lam=lam, n_exp=n_exp, levels=levels))
-    picks = rng.integers(0, len(pool), n_requests)
+    for k, nx in enumerate((16, 24, 32, 40, 48, 56, 64)):
+        ny = max(16, nx // 2)
+        n_exp = float(rng.uniform(0.3, 0.9))
+        lam = float(10.0 ** rng.uniform(-1.0, 1.0))
+        levels = 3 if nx * ny * ny <= 16 * 16 * 16 * 2 else 4
+        pool.append(die_problem(nx, ny, ny, seed=seed + k, nu0=1.0, lam=lam, n_exp=n_exp, levels=levels))
+    say("serving pool assembled:", [p.n for p in pool])
     # service time of the plain FP64 path, one request at a time (also warms every size up)
     srv = Server(max_active=1)
     t0 = time.perf_counter()
@@ -82,14 +254,13 @@ def serving_bench(seed=0, n_requests=24):
         srv.submit(Request(-1 - k, P, tol=1e-8)).wait()
     t_mean = (time.perf_counter() - t0) / len(pool)
     srv.close()
-    rate = 1.5 / t_mean
-    gaps = rng.exponential(1.0 / rate, n_requests)
+    capacity = 1.0 / t_mean
 
-    def stream(server, **opts):
+    def stream(server, picks, gaps, **opts):
         reqs = []
         t_start = time.perf_counter()
         t_next = t_start
-        for k in range(n_requests):
+        for k in range(len(picks)):
             delay = t_next - time.perf_counter()
             if delay > 0:
                 time.sleep(delay)
@@ -100,90 +271,83 @@ def serving_bench(seed=0, n_requests=24):
         server.close()
         return reqs, summarize(reqs, t_start, t_end)
 
-    base_reqs, base = stream(Server(max_active=1), tol=1e-8)
-    srv = Server(budget_bytes=200 * 2 ** 30, max_active=4)
-    mix_reqs, mixed = stream(srv, tol=1e-8, precision="mixed")
-    mixed["peak_active"] = srv.peak_active
-    err = max(float(np.linalg.norm(m.x - b_.x) / np.linalg.norm(b_.x)) for m, b_ in zip(mix_reqs, base_reqs))
-    return {"requests": n_requests, "arrival_rate_hz": rate,
-            "pool": "seeded dies 16x16x16, 32x16x16, 48x24x24, 64x32x32 (two each); Carreau n ~ U[0.3,0.9], "
-                    "lambda = 10^U[-1,1]; three levels up to 32x16x16, four above; FGMRES(30) to 1e-8",
-            "serving_fp32_factors_4_slots": mixed, "fp64_one_at_a_time": base,
-            "max_rel_diff_fp32_vs_fp64_solution": err}
-
-
-def mixed_precision_leg(P, step, x64, t64, n_steps=3):
-    """The same step with FP32 local factors and bases (FP64 Krylov, residuals and coarsest solve),
-    against the FP64 GPU path just timed: step time, iterations, error, FP32 factor rate."""
-    import numpy as np
-    import torch
-    step(False, "mixed")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(n_steps):
-        x, info, st = step(True, "mixed")
-    torch.cuda.synchronize()
-    T = (time.perf_counter() - t0) / n_steps
-    xh, x64h = x.cpu().numpy(), x64.cpu().numpy()
-    launches = st["local_solve_launches"]
-    return {"solves_per_s": 1.0 / T, "ms_per_step": T * 1e3, "speedup_vs_fp64": t64 / T,
-            "ms_setup": st["ms_total"], "ms_solve": info["ms_total"], "iterations": info["iterations"],
-            "true_rel_residual": float(np.linalg.norm(P.K() @ xh - P.b) / np.linalg.norm(P.b)),
-            "rel_diff_vs_fp64_gpu_solution": float(np.linalg.norm(xh - x64h) / np.linalg.norm(x64h)),
-            "level1_local_solve_gbs": (st["local_solve_bytes"] / (st["ms_local_solve"] / launches * 1e-3) / 1e9
-                                       if launches else None),
-            "factor": {"flops_level1": st["factor_flops"][0], "ms_factor_all_levels": st["ms_factor"],
-                       "tflops_level1_lower_bound": st["factor_flops"][0] / (st["ms_factor"] * 1e-3) / 1e12,
-                       "peak_tflops": FP32_MFMA_TFLOPS}}
-
-
-def solve_only_bench(P, Kdev, b, precision, n_solves=5):
-    """Setup amortized: several solves on one context, eager applies vs captured hipGraph applies."""
-    import torch
-    from paper_2606_01433_amd import gdsw
-    out = {}
-    for graph in (False, True):
-        with gdsw.Context(P, K=Kdev, tol=1e-8, precision=precision, graph=graph) as ctx:
-            ctx.solve(b)                     # warm-up (captures the graphs in graph mode)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(n_solves):
-                x, info = ctx.solve(b)
-            torch.cuda.synchronize()
-            out["graph" if graph else "eager"] = {"ms_per_solve": (time.perf_counter() - t0) / n_solves * 1e3,
-                                                  "solves_per_s": n_solves / (time.perf_counter() - t0)}
-            if not graph:
-                out["spmv"] = spmv_roofline(ctx, P, b)
+    out = {"requests_per_load": n_requests, "fp64_one_at_a_time_capacity_hz": capacity,
+           "pool": "seeded dies nx in {16,24,32,40,48,56,64}, ny = nz = max(16, nx/2); Carreau n ~ U[0.3,0.9], "
+                   "lambda = 10^U[-1,1]; three levels up to 32x16x16, four above; FGMRES(30) to 1e-8; "
+                   "FP32 slots admitted against a 200 GB footprint budget",
+           "loads": {}}
+    for rho in loads:
+        picks = rng.integers(0, len(pool), n_requests)
+        gaps = rng.exponential(1.0 / (rho * capacity), n_requests)
+        say(f"serving rho = {rho}")
+        srv32 = Server(budget_bytes=200 * 2 ** 30, max_active=4)
+        r32, s32 = stream(srv32, picks, gaps, tol=1e-8, precision="mixed")
+        s32["peak_active"] = srv32.peak_active
+        srv64 = Server(budget_bytes=200 * 2 ** 30, max_active=4)
+        r64, s64 = stream(srv64, picks, gaps, tol=1e-8)
+        s64["peak_active"] = srv64.peak_active
+        _, s1 = stream(Server(max_active=1), picks, gaps, tol=1e-8)
+        err = max(float(np.linalg.norm(a.x - b_.x) / np.linalg.norm(b_.x)) for a, b_ in zip(r32, r64))
+        out["loads"][str(rho)] = {"arrival_rate_hz": rho * capacity, "fp32_factors_4_slots": s32,
+                                  "fp64_4_slots": s64, "fp64_one_at_a_time": s1,
+                                  "max_rel_diff_fp32_vs_fp64_solution": err}
     return out
 
 
-def spmv_roofline(ctx, P, x, calls=50):
-    """y = K x through the library, timed with HIP events on the launching stream: algorithmic bytes
-    (CSR values and int32 columns, int64 row pointers, x once, y) over the mean duration."""
-    import torch
-    y = torch.empty_like(x)
-    ctx.spmv(x, out=y)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(calls):
-        ctx.spmv(x, out=y)
-    e1.record()
-    e1.synchronize()
-    us = e0.elapsed_time(e1) / calls * 1e3
-    nbytes = 12.0 * len(P.col) + 8.0 * (P.n + 1) + 16.0 * P.n
-    return {"bound": "hbm", "achieved": nbytes / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_call": nbytes, "us_per_call": us}
+def cpu_baseline(P, gpu_iterations_here, scale_to=None, budget_its=None):
+    """The oracle (FP64 NumPy/SciPy) on the host: its full three-level setup and FGMRES solve of the
+    32x16x16 die, with BLAS limited to one thread and with all host cores; optionally extrapolated
+    linearly in the number of dofs (and in the iteration count) to the headline workload."""
+    from threadpoolctl import threadpool_limits, threadpool_info
+    import oracle
+    K = P.K()
+    res = {}
+    for label, limit in (("single", 1), ("all", None)):
+        with threadpool_limits(limits=limit):
+            threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+            t0 = time.perf_counter()
+            H = oracle.setup(P)
+            t1 = time.perf_counter()
+            _, info = oracle.fgmres(lambda v: K @ v, lambda v: oracle.apply(H, v), P.b, tol=1e-8,
+                                    max_it=budget_its or 1000)
+            t2 = time.perf_counter()
+        res[label] = dict(setup=t1 - t0, per_it=(t2 - t1) / max(1, info["iterations"]), its=info["iterations"],
+                          threads=threads)
+        say(f"oracle {label}: setup {t1 - t0:.1f} s, {info['iterations']} its in {t2 - t1:.1f} s ({threads} threads)")
+    out = {"kind": "oracle", "host_cpu_count": os.cpu_count()}
+    for label in ("single", "all"):
+        r = res[label]
+        t_here = r["setup"] + r["per_it"] * gpu_iterations_here
+        entry = {"solves_per_s_32x16x16": 1.0 / t_here, "cores": r["threads"], "ms_setup": r["setup"] * 1e3,
+                 "ms_per_iteration": r["per_it"] * 1e3, "iterations": r["its"]}
+        if scale_to:
+            f = scale_to["n"] / P.n
+            entry["solves_per_s_extrapolated"] = 1.0 / (f * r["setup"] + f * r["per_it"] * scale_to["iterations"])
+        out[label] = entry
+    main = out["single"]
+    out["value"] = main["solves_per_s_extrapolated"] if scale_to else main["solves_per_s_32x16x16"]
+    out["unit"] = "solves/s"
+    out["cores"] = main["cores"]
+    out["sample"] = ("oracle's full three-level setup + complete FGMRES(30) solve to 1e-8 of the 32x16x16 die "
+                     f"({P.n} dofs; {res['single']['its']} iterations)"
+                     + (f", extrapolated linearly in dofs ({scale_to['n']}) and iterations "
+                        f"({scale_to['iterations']}) to the headline workload" if scale_to else ""))
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--headline", default="die96x48x48", choices=list(WORKLOADS))
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
+                    help="headline precision (default: mixed for die96x48x48, fp64 otherwise)")
+    ap.add_argument("--no-legs", action="store_true", help="headline only (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=16)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -191,7 +355,6 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not part of this build",
               file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
     from paper_2606_01433_amd import gdsw
     torch.cuda.set_device(0)
@@ -204,43 +367,16 @@ def main():
         print(json.dumps({"copy_bytes": a.numel() * 8}))
         return
     gdsw.load_library()
-    P = workload(args)
-    dev = torch.device("cuda", 0)
-    Kdev = (torch.as_tensor(P.rowptr, device=dev), torch.as_tensor(P.col, device=dev),
-            torch.as_tensor(P.val, device=dev))
-    b = torch.as_tensor(P.b, device=dev)
     stream = torch.cuda.current_stream()
-
-    def step(profile, precision=args.precision):
-        ctx = gdsw.Context(P, K=Kdev, tol=1e-8, precision=precision, profile=profile, stream=stream)
-        x, info = ctx.solve(b, stream=stream)
-        st = ctx.stats()
-        ctx.close()
-        return x, info, st
-
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    infos, stats = [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        x, info, st = step(True)
-        infos.append(info)
-        stats.append(st)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    T = (t1 - t0) / args.steps
-    res = float(np.linalg.norm(P.K() @ x.cpu().numpy() - P.b) / np.linalg.norm(P.b))
-    launches = sum(s["local_solve_launches"] for s in stats)
-    ms_ls = sum(s["ms_local_solve"] for s in stats)
-    bytes_per_launch = stats[0]["local_solve_bytes"]
-    achieved = bytes_per_launch / (ms_ls / launches * 1e-3) / 1e9 if launches else 0.0
+    name = args.headline
+    precision = args.precision or ("mixed" if name == "die96x48x48" else "fp64")
+    P = make_problem(name, args.seed)
+    run = Runner(P, stream)
+    tune = name == "die96x48x48"
+    say("headline steps")
+    T, x, infos, stats = run.timed_steps(args.steps, args.warmup, precision=precision, profile=True, tune=tune)
     st0 = stats[0]
-    iters = infos[-1]["iterations"]
-    traffic = None
-    if (local_solve_source_hash() == LOCAL_SOLVE_TRAFFIC["source_hash"]
-            and args.precision == LOCAL_SOLVE_TRAFFIC["precision"] and args.seed == 0):
-        traffic = LOCAL_SOLVE_TRAFFIC["bytes"]
+    res = run.true_residual(x)
     out = {
         "metric": "Stokes solves/s to 1e-8 rel. residual",
         "value": 1.0 / T,
@@ -252,39 +388,53 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32 local factors / f64 Krylov",
+        "dtype": "f64" if precision == "fp64" else "f32 local factors / f64 Krylov",
         "data": "synthetic (seeded die-like voxel channel, Carreau viscosity at a seeded linearization point)",
-        "config": {"workload": "three-level FP64 monolithic GDSW + FGMRES(30) to 1e-8, 32x16x16 voxel die "
-                               "(~20% masked), Q2-P1disc, Carreau nu0=1 lambda=1 n=0.5, 2^3-voxel parts, overlap 1",
+        "config": {"workload": describe(name, precision) + (", autotuned local solves" if tune else ""),
                    "n_dofs": int(P.n), "nnz": int(len(P.col)), "parts": st0["parts"][:st0["levels"]],
-                   "level_dofs": st0["n"][:st0["levels"]], "iterations": iters,
+                   "level_dofs": st0["n"][:st0["levels"]], "iterations": infos[-1]["iterations"],
                    "local_solve_waves_per_matrix": st0["ls_waves"][:st0["levels"] - 1],
-                   "true_rel_residual": res, "precision": args.precision,
-                   "ms_setup": st0["ms_total"], "ms_solve": infos[-1]["ms_total"],
+                   "true_rel_residual": res, "precision": precision,
+                   "ms_setup": float(sum(s["ms_total"] for s in stats) / len(stats)),
+                   "ms_solve": float(sum(i["ms_total"] for i in infos) / len(infos)),
                    "ms_setup_phases": {"host_maps": st0["ms_maps"], "host_prep": st0["ms_extract"],
-                                       "factor": st0["ms_factor"],
-                                       "basis_galerkin": st0["ms_basis"], "coarsest": st0["ms_coarse"]},
-                   "setup_timeline_ms": {
-                       "note": "GPU events, ms after the setup's first event: [begin, end]",
-                       "factor": [[round(a, 2), round(b, 2)] for a, b in st0["tl_factor"][:st0["levels"] - 1]],
-                       "basis_galerkin": [[round(a, 2), round(b, 2)] for a, b in st0["tl_basis"][:st0["levels"] - 1]],
-                       "coarsest": [round(x, 2) for x in st0["tl_coarsest"]]}},
-        "roofline": {"kernel": "k_local_solve (level-1 batched pivoted LU forward/backward substitution)",
-                     "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_launch": bytes_per_launch, "launches": launches,
-                     "avg_launch_us": ms_ls / launches * 1e3 if launches else None},
-        "factor": {"flops_level1": st0["factor_flops"][0], "ms_factor_all_levels": st0["ms_factor"],
-                   "tflops_level1_lower_bound": st0["factor_flops"][0] / (st0["ms_factor"] * 1e-3) / 1e12,
-                   "peak_tflops": FP64_MFMA_TFLOPS if args.precision == "fp64" else FP32_MFMA_TFLOPS},
+                                       "factor": st0["ms_factor"], "basis_galerkin": st0["ms_basis"],
+                                       "coarsest": st0["ms_coarse"]},
+                   "factor_bytes": st0["factor_bytes"][:st0["levels"] - 1]},
+        "roofline": local_solve_roofline(stats, name, precision, args.seed),
+        "factor": lu_rate(stats, precision),
     }
-    out["solve_only"] = solve_only_bench(P, Kdev, b, args.precision)
-    if args.precision == "fp64":
-        out["mixed_precision"] = mixed_precision_leg(P, step, x, T)
-    if not args.no_serving:
-        out["serving"] = serving_bench(args.seed)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(P, iters)
+    say(f"headline {1.0 / T:.3f} solves/s, {infos[-1]['iterations']} its, residual {res:.2e}")
+    if not args.no_legs:
+        say("whole-apply roofline")
+        out["apply"] = apply_roofline(run, precision)
+        say("solve only")
+        out["solve_only"] = solve_only(run, precision, n_solves=1, tune=tune)
+        del run, P
+        say("precision workload 64x32x32")
+        P64 = make_problem("die64x32x32", args.seed)
+        r64, x64, leg64 = workload_leg("die64x32x32", "fp64", 2, 1, stream, args.seed, P=P64)
+        _, x32, leg32 = workload_leg("die64x32x32", "mixed", 2, 1, stream, args.seed, P=P64)
+        import numpy as np
+        a, b_ = x32.cpu().numpy(), x64.cpu().numpy()
+        leg32["rel_diff_vs_fp64_solution"] = float(np.linalg.norm(a - b_) / np.linalg.norm(b_))
+        leg32["speedup_vs_fp64"] = leg32["solves_per_s"] / leg64["solves_per_s"]
+        out["precision_64x32x32"] = {"fp64": leg64, "fp32_factors": leg32,
+                                     "apply_fp64": apply_roofline(r64, "fp64"),
+                                     "apply_fp32_factors": apply_roofline(r64, "mixed")}
+        del r64, P64
+        say("three-level FP64 32x16x16")
+        P32 = make_problem("die32x16x16", args.seed)
+        r32, _, leg = workload_leg("die32x16x16", "fp64", 5, 2, stream, args.seed, P=P32)
+        leg["solve_only"] = solve_only(r32, "fp64", n_solves=5)
+        out["fp64_32x16x16"] = leg
+        if not args.no_serving:
+            out["serving"] = serving_bench(args.seed, n_requests=args.serving_requests)
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(P32, leg["iterations"],
+                                               scale_to={"n": out["config"]["n_dofs"],
+                                                         "iterations": out["config"]["iterations"]}
+                                               if name != "die32x16x16" else None)
     print(json.dumps(out), flush=True)
 
 

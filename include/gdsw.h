@@ -168,6 +168,14 @@ typedef struct gdsw_stats {
   double tl_factor[8][2];
   double tl_basis[8][2];
   double tl_coarsest[2];
+  /* GPU time of the batched LU kernels of level l alone (events around them on the
+   * factorization stream; other setup work runs concurrently on other streams) */
+  double ms_lu[8];
+  /* algorithmic bytes of one apply: sum over Schwarz levels and parts of
+   * n_i^2 s + 24 n_i (factor, pivoted index, gathered r, local solution, scattered z),
+   * plus 2 |Phi_I| s (restriction and prolongation), plus 8 n_c^2 (coarsest inverse);
+   * s = 8 (FP64) or 4 (FP32 factors) */
+  double apply_bytes;
 } gdsw_stats;
 
 /* Index maps of one level, host copies owned by the context (valid until

@@ -231,6 +231,8 @@ struct Level {
   double* rc = nullptr;          // restricted residual (n_coarse)
   double* yc = nullptr;          // coarse correction (n_coarse)
   double interior_flops = 0.0;
+  int64_t phi_elems = 0;         // sum_i |I_i| m_i (values of Phi_I)
+  hipEvent_t lu_ev[2] = {nullptr, nullptr};   // around the batched LU of this level (timing)
 };
 
 }  // namespace
@@ -282,6 +284,9 @@ struct gdsw_ctx {
   }
   ~gdsw_ctx() {
     if (own) (void)hipStreamSynchronize(own);
+    for (gdsw::Level& L : levels)
+      for (hipEvent_t e : L.lu_ev)
+        if (e) (void)hipEventDestroy(e);
     for (hipGraphExec_t g : apply_exec)
       if (g) (void)hipGraphExecDestroy(g);
     if (ev_in) (void)hipEventDestroy(ev_in);
@@ -429,7 +434,11 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
   b.wide = true;
   b.ut = A.alloc_n<T>((size_t)128 * L.sum_n);
   C->setup_scratch.push_back(b.ut);
+  GDSW_HIP(hipEventCreate(&L.lu_ev[0]));
+  GDSW_HIP(hipEventCreate(&L.lu_ev[1]));
+  GDSW_HIP(hipEventRecord(L.lu_ev[0], s));
   lu_batched<T>(b, blocks, s);
+  GDSW_HIP(hipEventRecord(L.lu_ev[1], s));
   L.perm = A.alloc_n<int>((size_t)L.sum_n);
   lu_build_perm(b, L.perm, s);
   L.gidx = A.alloc_n<int>((size_t)L.sum_n);
@@ -492,6 +501,7 @@ CsrDev coarse_level(gdsw_ctx* C, Level& L, hipStream_t s, std::vector<int64_t>& 
   L.max_ni = max_ni;
   L.max_m = max_m;
   L.interior_flops = iflops;
+  L.phi_elems = phi_tot;
   std::vector<int> gd;
   for (int64_t g = 0; g < L.n; ++g)
     if (m.dof_gcol[g] >= 0) gd.push_back((int)g);
@@ -862,6 +872,30 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
     st.tl_coarsest[1] = span(e_setup, ec1);
   }
   for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+  for (size_t l = 0; l < C->levels.size(); ++l) {
+    Level& L = C->levels[l];
+    if (L.lu_ev[0] && L.lu_ev[1] && l < 8) {
+      float ms = 0;
+      GDSW_HIP(hipEventElapsedTime(&ms, L.lu_ev[0], L.lu_ev[1]));
+      st.ms_lu[l] = ms;
+    }
+    for (hipEvent_t& e : L.lu_ev)
+      if (e) {
+        (void)hipEventDestroy(e);
+        e = nullptr;
+      }
+  }
+  // algorithmic bytes of one apply: local factors and their gathers/stores on every Schwarz
+  // level, Phi_I read twice (restriction, prolongation), the coarsest dense inverse
+  {
+    double ab = 0;
+    for (const Level& L : C->levels) {
+      for (int d : L.dims) ab += (double)d * d * sizeof(T) + 24.0 * d;
+      if (L.has_coarse) ab += 2.0 * (double)L.phi_elems * sizeof(T);
+    }
+    if (coarsest) ab += 8.0 * (double)C->nc * C->nc;
+    st.apply_bytes = ab;
+  }
   st.ms_maps = host_ms;
   st.ms_total = now_ms() - t0;
 }
@@ -887,8 +921,61 @@ void drain_events(gdsw_ctx* C) {
   C->ev_used = 0;
 }
 
+// Tuning results shared by all contexts of the process, keyed by what decides
+// the choice: the value type, the level and the batch shape (count, total and
+// largest order of the local blocks).  With GDSW_TUNE_CACHE=<file> the table is
+// read from that file on first use and every new entry is appended to it, so
+// later processes skip the timing runs.
+struct TuneCache {
+  std::mutex mu;
+  bool loaded = false;
+  std::map<std::string, int> waves;
+};
+TuneCache& tune_cache() {
+  static TuneCache c;
+  return c;
+}
+std::string tune_key(int value_bytes, int level, int nparts, int64_t sum_n, int max_n) {
+  return "ls " + std::to_string(value_bytes) + " " + std::to_string(level) + " " + std::to_string(nparts) + " " +
+         std::to_string(sum_n) + " " + std::to_string(max_n);
+}
+bool tune_lookup(const std::string& key, int* w) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  if (!c.loaded) {
+    c.loaded = true;
+    if (const char* path = std::getenv("GDSW_TUNE_CACHE")) {
+      if (FILE* f = std::fopen(path, "r")) {
+        char tag[8];
+        int vb, lv, np, mx, wv;
+        long long sn;
+        while (std::fscanf(f, "%7s %d %d %d %lld %d %d", tag, &vb, &lv, &np, &sn, &mx, &wv) == 7)
+          if (std::string(tag) == "ls" && (wv == 2 || wv == 4 || wv == 8)) c.waves[tune_key(vb, lv, np, sn, mx)] = wv;
+        std::fclose(f);
+      }
+    }
+  }
+  auto it = c.waves.find(key);
+  if (it == c.waves.end()) return false;
+  *w = it->second;
+  return true;
+}
+void tune_store(const std::string& key, int w) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  c.waves[key] = w;
+  if (const char* path = std::getenv("GDSW_TUNE_CACHE")) {
+    if (FILE* f = std::fopen(path, "a")) {
+      std::fprintf(f, "%s %d\n", key.c_str(), w);
+      std::fclose(f);
+    }
+  }
+}
+
 // Autotuner: for every level, time the local solves with 2, 4 and 8 wavefronts
-// per matrix (two runs each on a zero right-hand side) and keep the fastest.
+// per matrix (two runs each on a zero right-hand side) and keep the fastest;
+// a batch shape already tuned in this process (or in the cache file) reuses
+// its choice.
 template <typename T>
 void tune_local_solves(gdsw_ctx* C, hipStream_t s) {
   hipEvent_t e0, e1;
@@ -896,6 +983,13 @@ void tune_local_solves(gdsw_ctx* C, hipStream_t s) {
   GDSW_HIP(hipEventCreate(&e1));
   for (size_t l = 0; l < C->levels.size(); ++l) {
     Level& L = C->levels[l];
+    const std::string key = tune_key((int)sizeof(T), L.index, L.nparts, L.sum_n, L.max_n);
+    int cached = 0;
+    if (tune_lookup(key, &cached)) {
+      L.ls_waves = cached;
+      if (l < 8) C->stats.ls_waves[l] = cached;
+      continue;
+    }
     double* r0 = C->arena.alloc_n<double>((size_t)L.n);
     GDSW_HIP(hipMemsetAsync(r0, 0, (size_t)L.n * sizeof(double), s));
     float best = 1e30f;
@@ -917,7 +1011,9 @@ void tune_local_solves(gdsw_ctx* C, hipStream_t s) {
     }
     L.ls_waves = best_w;
     if (l < 8) C->stats.ls_waves[l] = best_w;
+    GDSW_HIP(hipStreamSynchronize(s));   // r0 goes back to the block cache
     C->arena.free_one(r0);
+    tune_store(key, best_w);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -42,7 +42,8 @@ class Stats(ctypes.Structure):
                 ("ms_factor", c_dbl), ("ms_basis", c_dbl), ("ms_galerkin", c_dbl), ("ms_coarse", c_dbl),
                 ("ms_total", c_dbl), ("local_solve_launches", c_i64), ("ms_local_solve", c_dbl),
                 ("local_solve_bytes", c_dbl), ("ls_waves", c_i32 * 8), ("tl_factor", (c_dbl * 2) * 8),
-                ("tl_basis", (c_dbl * 2) * 8), ("tl_coarsest", c_dbl * 2)]
+                ("tl_basis", (c_dbl * 2) * 8), ("tl_coarsest", c_dbl * 2), ("ms_lu", c_dbl * 8),
+                ("apply_bytes", c_dbl)]
 
 
 class MapsView(ctypes.Structure):
