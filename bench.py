@@ -35,6 +35,7 @@ FP32_MFMA_TFLOPS = 157.3
 # was measured on (hash of that part of apply.hip) and for the precision and seed it was taken with.
 LOCAL_SOLVE_TRAFFIC = {
     ("die32x16x16", "fp64"): {"bytes": 3.993e9, "source_hash": "935223e387098f25"},
+    ("die96x48x48", "mixed"): {"bytes": 86.449e9, "source_hash": "935223e387098f25"},
 }
 
 WORKLOADS = {
