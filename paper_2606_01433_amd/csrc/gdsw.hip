@@ -621,6 +621,8 @@ void coarsest_inverse(gdsw_ctx* C, const CsrDev& K, hipStream_t s, double** dens
   b.wide = true;
   b.ut = A.alloc_n<double>((size_t)128 * n);
   C->setup_scratch.push_back(b.ut);
+  b.tall_scratch = A.alloc(lu_tall_scratch_bytes(n, sizeof(double)));
+  C->setup_scratch.push_back(b.tall_scratch);
   lu_batched<double>(b, D, s);
   double* X = A.alloc_n<double>((size_t)n * n);
   // the inverse is kept by rows, so the per-apply GEMV reads rows contiguously
@@ -629,8 +631,9 @@ void coarsest_inverse(gdsw_ctx* C, const CsrDev& K, hipStream_t s, double** dens
   if (lu_inverse_transposed(D, perm, X, n, s)) {
     C->ainv = X;                 // D (the factors) becomes scratch
   } else {
-    set_identity<double>(X, n, s);
-    lu_solve_batched<double>(b, D, X, d_off, d_dim, n, s);
+    int* iscr = A.alloc_n<int>((size_t)2 * n + 64);
+    C->setup_scratch.push_back(iscr);
+    lu_inverse_blocked(b, D, perm, X, iscr, n, s);
     transpose_square(n, X, D, s);
     C->ainv = D;
     D = X;

@@ -36,7 +36,18 @@ struct LuBatch {
   void* ut = nullptr;
   // With ut (R = 128): pairs of 64-column steps share one rank-128 trailing update.
   bool wide = false;
+  // Single-matrix batches (count == 1) only: device scratch of
+  // lu_tall_scratch_bytes(order, sizeof(T)) bytes.  Panels taller than one
+  // workgroup's registers are then factored by many workgroups (one launch per
+  // column) instead of by one.
+  void* tall_scratch = nullptr;
 };
+size_t lu_tall_scratch_bytes(int n, int value_bytes);
+// X = A^{-1} (column-major) of a single LU-factored FP64 matrix (b.count == 1, b.off
+// and b.dim its device offset 0 and order n, perm its row permutation) by blocked
+// forward and backward sweeps on P I; scratch: 2n + 64 ints of device memory.
+void lu_inverse_blocked(const LuBatch& b, const double* LU, const int* perm, double* X, int* scratch, int n,
+                        hipStream_t s);
 
 // Host-built update tile tables of a batch with orders dims[0..count).
 struct LuTiles {

@@ -260,6 +260,163 @@ __global__ __launch_bounds__(256) void k_lu_panel(T* __restrict__ Ab, const int6
   }
 }
 
+// ---- tall panel of a single matrix, spread over many workgroups -------------
+//
+// A panel A[k:n, k:k+jb) of one large matrix (more rows than one workgroup's
+// registers hold) is factored one column per launch by G workgroups of TALL_T
+// threads, thread t of workgroup w owning row k + TALL_T w + t.  Launch j
+// (column j) reads the column's per-workgroup pivot candidates left by the
+// previous launch (value, row and the candidate row's panel values), so every
+// workgroup picks the same pivot (largest magnitude, ties to the lowest row),
+// applies the interchange of rows j and p to the panel columns, scales column j
+// and applies the rank-1 update to its own rows, and leaves the candidates of
+// column j + 1 for the next launch.  Only the owners of rows j and p write
+// those rows; every other workgroup reads the pivot row from the candidate
+// buffer and the displaced row j from a copy the previous launch made, so no
+// workgroup reads a row another one writes in the same launch.  Buffers
+// alternate between two slots by column parity.
+constexpr int TALL_T = 256;
+constexpr int TALL_NB = 32;
+
+template <typename T>
+struct TallBufs {
+  double* val;   // [2][G] candidate magnitudes
+  int* idx;      // [2][G] candidate rows
+  T* cand;       // [2][G][TALL_NB] candidate rows' panel values
+  T* rowj;       // [2][TALL_NB] row j + 1's panel values for the next launch
+};
+
+// Candidates of column c over rows >= c held by this thread (row r, values v[0..jb)):
+// workgroup argmax, then slot `slot`.  The owner of row c also stores that row.
+template <typename T>
+__device__ __forceinline__ void tall_candidates(const TallBufs<T>& B, int G, int slot, int c, int k, int jb, int r,
+                                                bool mine, const T* v, double* s_v, int* s_i, int* s_t) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  if (mine && r >= c) {
+    best = fabs((double)v[c - k]);
+    bi = r;
+  }
+  int bt = tid;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(best, o, WAVE);
+    const int oi = __shfl_xor(bi, o, WAVE);
+    const int ot = __shfl_xor(bt, o, WAVE);
+    if (ov > best || (ov == best && oi < bi)) {
+      best = ov;
+      bi = oi;
+      bt = ot;
+    }
+  }
+  if (lane == 0) {
+    s_v[w] = best;
+    s_i[w] = bi;
+    s_t[w] = bt;
+  }
+  __syncthreads();
+  double b = s_v[0];
+  int p = s_i[0], pt = s_t[0];
+  for (int q = 1; q < TALL_T / 64; ++q)
+    if (s_v[q] > b || (s_v[q] == b && s_i[q] < p)) {
+      b = s_v[q];
+      p = s_i[q];
+      pt = s_t[q];
+    }
+  const int g = blockIdx.x;
+  if (tid == pt && p != 0x7fffffff) {
+    for (int q = 0; q < jb; ++q) B.cand[((size_t)slot * G + g) * TALL_NB + q] = v[q];
+  }
+  if (tid == 0) {
+    B.val[slot * G + g] = b;
+    B.idx[slot * G + g] = p;
+  }
+  if (mine && r == c)
+    for (int q = 0; q < jb; ++q) B.rowj[slot * TALL_NB + q] = v[q];
+}
+
+// Candidates of the panel's first column k.
+template <typename T>
+__global__ __launch_bounds__(TALL_T) void k_tall_first(const T* __restrict__ A, int ld, int n, int k, int jb, int G,
+                                                       TallBufs<T> B) {
+  __shared__ double s_v[TALL_T / 64];
+  __shared__ int s_i[TALL_T / 64], s_t[TALL_T / 64];
+  const int r = k + blockIdx.x * TALL_T + threadIdx.x;
+  const bool mine = r < n;
+  T v[TALL_NB];
+#pragma unroll
+  for (int q = 0; q < TALL_NB; ++q) v[q] = (mine && q < jb) ? A[r + (int64_t)(k + q) * ld] : T(0);
+  tall_candidates<T>(B, G, 0, k, k, jb, r, mine, v, s_v, s_i, s_t);
+}
+
+// Column j of the panel [k, k + jb): pivot, interchange, scaling, rank-1 update,
+// candidates of column j + 1.
+template <typename T>
+__global__ __launch_bounds__(TALL_T) void k_tall_step(T* __restrict__ A, int ld, int n, int k, int jb, int j, int G,
+                                                      TallBufs<T> B, int* __restrict__ piv, int* __restrict__ info) {
+  __shared__ double s_v[TALL_T / 64];
+  __shared__ int s_i[TALL_T / 64], s_t[TALL_T / 64];
+  __shared__ T s_prow[TALL_NB];
+  const int slot = (j - k) & 1;
+  // the pivot: every workgroup reduces the same candidates in the same order
+  double bv = B.val[slot * G];
+  int p = B.idx[slot * G], gw = 0;
+  for (int g = 1; g < G; ++g) {
+    const double v = B.val[slot * G + g];
+    const int i = B.idx[slot * G + g];
+    if (v > bv || (v == bv && i < p)) {
+      bv = v;
+      p = i;
+      gw = g;
+    }
+  }
+  const bool singular = !(bv > 0.0) || p >= n;
+  if (singular) {
+    p = j;
+  }
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && tid == 0) {
+    piv[j] = p;
+    if (singular && info[0] == 0) info[0] = j + 1;
+  }
+  // the pivot row's panel values (row j's own values when the column is singular)
+  for (int q = tid; q < jb; q += TALL_T)
+    s_prow[q] = singular ? B.rowj[slot * TALL_NB + q] : B.cand[((size_t)slot * G + gw) * TALL_NB + q];
+  __syncthreads();
+  const int r = k + blockIdx.x * TALL_T + tid;
+  const bool mine = r < n;
+  T v[TALL_NB];
+  if (mine && r == j) {
+#pragma unroll
+    for (int q = 0; q < TALL_NB; ++q) v[q] = q < jb ? s_prow[q] : T(0);
+  } else if (mine && r == p) {           // p != j: receives row j
+#pragma unroll
+    for (int q = 0; q < TALL_NB; ++q) v[q] = q < jb ? B.rowj[slot * TALL_NB + q] : T(0);
+  } else {
+#pragma unroll
+    for (int q = 0; q < TALL_NB; ++q) v[q] = (mine && q < jb && r > j) ? A[r + (int64_t)(k + q) * ld] : T(0);
+  }
+  const int cj = j - k;
+  if (mine && r > j) {
+    const T pv = s_prow[cj];
+    const T l = (pv != T(0)) ? v[cj] / pv : v[cj];
+    v[cj] = l;
+#pragma unroll
+    for (int q = 0; q < TALL_NB; ++q)
+      if (q > cj && q < jb) v[q] -= l * s_prow[q];
+  }
+  // stores: row j (the pivot row), row p (old row j, updated), and every other row below j
+  if (mine && (r > j || r == j)) {
+    if (r == j || r == p) {
+      for (int q = 0; q < jb; ++q) A[r + (int64_t)(k + q) * ld] = v[q];
+    } else {
+      for (int q = cj; q < jb; ++q) A[r + (int64_t)(k + q) * ld] = v[q];
+    }
+  }
+  if (j + 1 < k + jb) tall_candidates<T>(B, G, slot ^ 1, j + 1, k, jb, r, mine && r > j, v, s_v, s_i, s_t);
+}
+
 // (ov, ol) beats (val, lab): larger value, equal values to the smaller label.
 // Evaluated without short-circuit so it compiles to compares and selects.
 __device__ __forceinline__ bool argmax_beats(double ov, int ol, double val, int lab) {
@@ -833,6 +990,40 @@ __global__ __launch_bounds__(64) void k_getrs_diag(const T* __restrict__ Ab, con
     if (r < jb) col[r] = x[r];
 }
 
+// ---- explicit inverse of one large LU-factored matrix --------------------
+//
+// X = A^{-1} from P A = L U (X starts as P I): forward sweep with L, backward
+// with U, both in 128-row blocks of four 32-row diagonal solves; the rows past
+// a block are updated once per block with inner dimension 128 (a quarter of the
+// passes over X of a 32-row blocking).  In the forward sweep, column c of P I
+// is zero above the row q with perm[q] = c, and stays so: a 64-column tile of X
+// whose columns all start below the block is skipped (lo[tile] = first row of
+// the tile's columns that can be nonzero).
+
+// X[r0 : r0 + M, 0 : n) -= A[r0 : r0 + M, kc : kc + kw) X[kc : kc + kw, 0 : n) (leading dimension n).
+template <typename T, int KMAX>
+__global__ __launch_bounds__(256) void k_inv_update(const T* __restrict__ A, T* __restrict__ X, int n, int r0, int M,
+                                                    int kc, int kw, int tiles_m, const int* __restrict__ lo) {
+  const int w = (int)xcd_remap(blockIdx.x, gridDim.x);
+  const int ty = w % tiles_m, tx = w / tiles_m;
+  if (lo && lo[tx] >= kc + kw) return;
+  gemm_sub_tile_direct<T, KMAX>(X + r0, n, A + r0 + (int64_t)kc * n, n, X + kc, n, M, n, kw, ty, tx);
+}
+
+// lo[t] = min over the columns c of tile t of the position q with perm[q] = c.
+__global__ void k_inv_first_rows(const int* __restrict__ perm, int n, int* __restrict__ pinv, int* __restrict__ lo,
+                                 int phase) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (phase == 0) {
+    if (t < n) pinv[perm[t]] = t;
+  } else {
+    if (t * TILE >= n) return;
+    int m = n;
+    for (int c = t * TILE; c < min(n, (t + 1) * TILE); ++c) m = min(m, pinv[c]);
+    lo[t] = m;
+  }
+}
+
 // perm[r] = original row at position r after the interchanges piv[0..n) of
 // matrix blockIdx.x, applied in order.  The permutation lives in LDS while one
 // thread applies the interchanges (orders up to PERM_LDS; longer ones in global
@@ -1109,6 +1300,27 @@ void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
   auto panel = [&](int k) {
     const int rows = b.max_n - k;
     const bool tall = rows > panel_reg_rows<T>();
+    if (tall && b.count == 1 && b.tall_scratch) {
+      // a single large matrix (the coarsest): the panel is spread over many workgroups
+      const int n = b.max_n;
+      const int jb = std::min(TALL_NB, n - k);
+      const int G = (int)blocks_for(rows, TALL_T);
+      TallBufs<T> B;
+      char* base = static_cast<char*>(b.tall_scratch);
+      const int Gm = (int)blocks_for(n, TALL_T);
+      B.val = reinterpret_cast<double*>(base);
+      B.idx = reinterpret_cast<int*>(base + 2 * Gm * sizeof(double));
+      B.cand = reinterpret_cast<T*>(base + 2 * Gm * (sizeof(double) + sizeof(int)) + 64);
+      B.rowj = B.cand + (size_t)2 * Gm * TALL_NB;
+      const int ld = lead_dim(n, b.pad);
+      hipLaunchKernelGGL((k_tall_first<T>), dim3(G), dim3(TALL_T), 0, s, A, ld, n, k, jb, G, B);
+      GDSW_LAUNCH_CHECK();
+      for (int j = k; j < k + jb; ++j) {
+        hipLaunchKernelGGL((k_tall_step<T>), dim3(G), dim3(TALL_T), 0, s, A, ld, n, k, jb, j, G, B, b.piv, b.info);
+        GDSW_LAUNCH_CHECK();
+      }
+      return;
+    }
     if (tall) {
       hipLaunchKernelGGL((k_lu_panel<T, NB>), dim3(b.count), dim3(256), 0, s, A, b.off, b.dim, b.piv, b.poff,
                          b.info, k, b.pad);
@@ -1266,6 +1478,60 @@ bool lu_inverse_transposed(const double* LU, const int* perm, double* out, int n
 void lu_build_perm(const LuBatch& b, int* perm, hipStream_t s) {
   hipLaunchKernelGGL(k_build_perm, dim3(b.count), dim3(256), 0, s, b.dim, b.piv, b.poff, perm);
   GDSW_LAUNCH_CHECK();
+}
+
+void lu_inverse_blocked(const LuBatch& b, const double* LU, const int* perm, double* X, int* scratch, int n,
+                        hipStream_t s) {
+  constexpr int NB = LU_NB, BB = 4 * LU_NB;
+  const int tn = (int)blocks_for(n, TILE);
+  int* pinv = scratch;
+  int* lo = scratch + n;
+  hipLaunchKernelGGL(k_inv_first_rows, dim3(blocks_for(n, 256)), dim3(256), 0, s, perm, n, pinv, lo, 0);
+  GDSW_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_inv_first_rows, dim3(blocks_for(tn, 256)), dim3(256), 0, s, perm, n, pinv, lo, 1);
+  GDSW_LAUNCH_CHECK();
+  set_identity<double>(X, n, s);
+  const unsigned rhsblocks = blocks_for(n, 64);
+  hipLaunchKernelGGL((k_getrs_swap<double>), dim3(1, rhsblocks), dim3(64), 0, s, b.dim, b.piv, b.poff, X, b.off, b.dim);
+  GDSW_LAUNCH_CHECK();
+  auto update = [&](int r0, int M, int kc, int kw, const int* lo_) {
+    if (M <= 0 || kw <= 0) return;
+    const int tm = (int)blocks_for(M, TILE);
+    if (kw > NB)
+      hipLaunchKernelGGL((k_inv_update<double, BB>), dim3((unsigned)tm * tn), dim3(256), 0, s, LU, X, n, r0, M, kc, kw,
+                         tm, lo_);
+    else
+      hipLaunchKernelGGL((k_inv_update<double, NB>), dim3((unsigned)tm * tn), dim3(256), 0, s, LU, X, n, r0, M, kc, kw,
+                         tm, lo_);
+    GDSW_LAUNCH_CHECK();
+  };
+  auto diag = [&](int k, int upper) {
+    hipLaunchKernelGGL((k_getrs_diag<double, NB>), dim3(1, rhsblocks), dim3(64), 0, s, LU, b.off, b.dim, X, b.off,
+                       b.dim, k, upper);
+    GDSW_LAUNCH_CHECK();
+  };
+  for (int kb = 0; kb < n; kb += BB) {
+    const int e = std::min(kb + BB, n);
+    for (int sb = kb; sb < e; sb += NB) {
+      diag(sb, 0);
+      update(sb + NB, e - (sb + NB), sb, std::min(NB, n - sb), lo);
+    }
+    update(e, n - e, kb, e - kb, lo);
+  }
+  const int last = ((n - 1) / BB) * BB;
+  for (int kb = last; kb >= 0; kb -= BB) {
+    const int e = std::min(kb + BB, n);
+    for (int sb = ((e - 1 - kb) / NB) * NB + kb; sb >= kb; sb -= NB) {
+      diag(sb, 1);
+      update(kb, sb - kb, sb, std::min(NB, n - sb), nullptr);
+    }
+    update(0, kb, kb, e - kb, nullptr);
+  }
+}
+
+size_t lu_tall_scratch_bytes(int n, int value_bytes) {
+  const size_t Gm = blocks_for(n, TALL_T);
+  return 2 * Gm * (sizeof(double) + sizeof(int)) + 64 + (2 * Gm + 2) * TALL_NB * (size_t)value_bytes + 256;
 }
 
 template void lu_batched<double>(const LuBatch&, double*, hipStream_t);

@@ -142,8 +142,10 @@ def _tall():
     return {
         # coarsest order 1943: panels of 1537..2048 rows go through the half-width register panels
         "die20x8x8_L2": (lambda: die_problem(20, 8, 8, seed=0, levels=2), (1537, 2048)),
-        # coarsest order 2273: panels above 2048 rows take the global-memory panel
+        # coarsest order 2273: panels above 2048 rows are spread over many workgroups
         "die18x10x8_L2": (lambda: die_problem(18, 10, 8, seed=0, levels=2), (2049, 4096)),
+        # coarsest order 4333: the explicit inverse takes the blocked sweeps (above 4096)
+        "die22x12x10_L2": (lambda: die_problem(22, 12, 10, seed=0, levels=2), (4097, 8192)),
     }
 
 
