@@ -216,6 +216,57 @@ def solve_only(run, precision, n_solves, tune=False):
     return out
 
 
+def many_solve_leg(run, precision, ks=(1, 8, 32), tol=1e-1, reps=3):
+    """The low-accuracy many-solve regime (section 3: the solver as a coarse solver invoked many times
+    to a 1e-1 reduction): one setup, then batches of k right-hand sides solved in lockstep with one
+    multi-right-hand-side apply per iteration (k = 1: plain gdsw_solve), setup amortized."""
+    import numpy as np
+    import torch
+    from harness import random_vector
+    ctx = run.context(precision=precision, tol=tol)
+    out = {"tol": tol, "workload": "setup once, FGMRES(30) to a 1e-1 relative residual per right-hand side"}
+    kmax = max(ks)
+    B = torch.as_tensor(np.stack([random_vector(run.P.n, 100 + q) for q in range(kmax)]), device="cuda")
+    for k in ks:
+        Bk = B[:k].contiguous()
+        if k == 1:
+            ctx.solve(Bk[0], stream=run.stream)
+        else:
+            ctx.solve_multi(Bk, stream=run.stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            if k == 1:
+                _, info = ctx.solve(Bk[0], stream=run.stream)
+                its = [info["iterations"]]
+            else:
+                _, infos = ctx.solve_multi(Bk, stream=run.stream)
+                its = [i["iterations"] for i in infos]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        # the preconditioner alone on k vectors
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        Z = torch.empty_like(Bk)
+        if k == 1:
+            ctx.apply(Bk[0], out=Z[0], stream=run.stream)
+        else:
+            ctx.apply_multi(Bk, out=Z, stream=run.stream)
+        e0.record(run.stream)
+        for _ in range(5):
+            if k == 1:
+                ctx.apply(Bk[0], out=Z[0], stream=run.stream)
+            else:
+                ctx.apply_multi(Bk, out=Z, stream=run.stream)
+        e1.record(run.stream)
+        e1.synchronize()
+        ms_apply = e0.elapsed_time(e1) / 5
+        out[f"k{k}"] = {"solves_per_s": k / dt, "ms_per_batch": dt * 1e3, "iterations": its,
+                        "ms_apply_batch": ms_apply, "ms_apply_per_rhs": ms_apply / k}
+    ctx.close()
+    out["speedup_k32_vs_k1"] = out[f"k{kmax}"]["solves_per_s"] / out["k1"]["solves_per_s"]
+    return out
+
+
 def workload_leg(name, precision, steps, warmup, stream, seed=0, P=None):
     """setup + solve + destroy steps of one workload in one precision."""
     P = make_problem(name, seed) if P is None else P
@@ -429,6 +480,8 @@ def main():
         r32, _, leg = workload_leg("die32x16x16", "fp64", 5, 2, stream, args.seed, P=P32)
         leg["solve_only"] = solve_only(r32, "fp64", n_solves=5)
         out["fp64_32x16x16"] = leg
+        say("many-solve regime (multi-right-hand-side solves)")
+        out["many_solve_32x16x16"] = many_solve_leg(r32, "fp64")
         if not args.no_serving:
             out["serving"] = serving_bench(args.seed, n_requests=args.serving_requests)
         if not args.no_cpu_baseline:

@@ -3,6 +3,8 @@
 // the prolongation Phi y and the coarsest direct solve.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -166,6 +168,173 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8
   for (int a = tid; a < n; a += NT) w[base + a] = (double)x[a];
 }
 
+// ---------------------------------------------------------------------------
+// Local solves of KC right-hand sides at once (the same factor streamed once
+// for all of them).  Same blocked substitution as k_local_solve_wg, with the
+// gathered right-hand sides in LDS row by row (x[a * KC + s]) and every
+// per-right-hand-side operation in the same order, so each column equals the
+// single-right-hand-side result bit for bit.  Right-hand side s of the chunk is
+// R[s * ldr + g]; the local solutions go to W[s * ldw + position].
+// ---------------------------------------------------------------------------
+template <typename T, int NPH, bool FULL, int KC>
+__device__ __forceinline__ void lsm_row_update(const T* __restrict__ A, int ld, T* x, int row, int q0, int pw) {
+  constexpr int H = PW / NPH;
+  T acc[KC];
+#pragma unroll
+  for (int s = 0; s < KC; ++s) acc[s] = T(0);
+#pragma unroll
+  for (int h = 0; h < NPH; ++h) {
+    int64_t o = row + (int64_t)(q0 + h * H) * ld;
+    if (h > 0) asm volatile("" : "+v"(o) : "v"(acc[0]));
+    T v[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      v[j] = (FULL || h * H + j < pw) ? A[o] : T(0);
+      o += ld;
+      asm volatile("" : "+v"(o));
+    }
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const int q = q0 + (FULL ? h * H + j : min(h * H + j, pw - 1));
+#pragma unroll
+      for (int s = 0; s < KC; ++s) acc[s] += v[j] * x[q * KC + s];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < KC; ++s) x[row * KC + s] -= acc[s];
+}
+
+template <typename T, int NPH, bool FULL, int KC>
+__device__ __forceinline__ void lsm_tri_lower(const T* __restrict__ A, int ld, T* x, int q0, int pw, int lane) {
+  constexpr int H = PW / NPH;
+  const bool ok = FULL || lane < pw;
+  const int row = ok ? q0 + lane : q0;
+  const int lj = ok ? lane : 0;
+  T xv[KC];
+#pragma unroll
+  for (int s = 0; s < KC; ++s) xv[s] = ok ? x[row * KC + s] : T(0);
+#pragma unroll
+  for (int h = 0; h < NPH; ++h) {
+    if (!(FULL || h * H < pw)) continue;
+    int64_t o = row + (int64_t)(q0 + h * H) * ld;
+    if (h > 0) asm volatile("" : "+v"(o) : "v"(xv[0]));
+    T d[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      int l = lj;
+      asm volatile("" : "+v"(l));
+      d[j] = (h * H + j < l) ? A[o] : T(0);
+      o += ld;
+      asm volatile("" : "+v"(o));
+    }
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const int jj = h * H + j;
+      if (FULL || jj < pw) {
+#pragma unroll
+        for (int s = 0; s < KC; ++s) xv[s] -= d[j] * lane_value(xv[s], jj);
+      }
+    }
+  }
+  if (ok) {
+#pragma unroll
+    for (int s = 0; s < KC; ++s) x[row * KC + s] = xv[s];
+  }
+}
+
+template <typename T, int NPH, bool FULL, int KC>
+__device__ __forceinline__ void lsm_tri_upper(const T* __restrict__ A, int ld, T* x, int q0, int pw, int lane) {
+  constexpr int H = PW / NPH;
+  const bool ok = FULL || lane < pw;
+  const int row = ok ? q0 + lane : q0;
+  const T rd = ok ? T(1) / A[row + (int64_t)row * ld] : T(0);
+  const int lj = ok ? lane : PW;
+  T xv[KC];
+#pragma unroll
+  for (int s = 0; s < KC; ++s) xv[s] = ok ? x[row * KC + s] : T(0);
+#pragma unroll
+  for (int h = NPH - 1; h >= 0; --h) {
+    if (!(FULL || h * H < pw)) continue;
+    int64_t o = row + (int64_t)(q0 + h * H) * ld;
+    if (h < NPH - 1) asm volatile("" : "+v"(o) : "v"(xv[0]));
+    T d[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      int l = lj;
+      asm volatile("" : "+v"(l));
+      d[j] = (h * H + j > l && (FULL || h * H + j < pw)) ? A[o] : T(0);
+      o += ld;
+      asm volatile("" : "+v"(o));
+    }
+#pragma unroll
+    for (int j = H - 1; j >= 0; --j) {
+      const int jj = h * H + j;
+      if (FULL || jj < pw) {
+        const T rj = lane_value(rd, jj);
+#pragma unroll
+        for (int s = 0; s < KC; ++s) xv[s] -= d[j] * (lane_value(xv[s], jj) * rj);
+      }
+    }
+  }
+  if (ok) {
+#pragma unroll
+    for (int s = 0; s < KC; ++s) x[row * KC + s] = xv[s] * rd;
+  }
+}
+
+template <typename T, int KC>
+__global__ __launch_bounds__(512) void k_local_solve_multi(const int* __restrict__ order,
+                                                           const int64_t* __restrict__ dom_ptr,
+                                                           const int* __restrict__ gidx,
+                                                           const int64_t* __restrict__ blk_off,
+                                                           const T* __restrict__ blocks, const double* __restrict__ R,
+                                                           int64_t ldr, double* __restrict__ W, int64_t ldw, int kk,
+                                                           int pad) {
+  constexpr int NW = 8, NT = 64 * NW, NPH = 2;
+  extern __shared__ unsigned char smem_raw[];
+  T* x = reinterpret_cast<T*>(smem_raw);
+  const int i = order[blockIdx.x];
+  const int64_t base = dom_ptr[i];
+  const int n = (int)(dom_ptr[i + 1] - base);
+  const T* A = blocks + blk_off[i];
+  const int ld = lead_dim(n, pad);
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int a = tid; a < n; a += NT) {
+    const int g = gidx[base + a];
+#pragma unroll
+    for (int s = 0; s < KC; ++s) x[a * KC + s] = s < kk ? (T)R[s * ldr + g] : T(0);
+  }
+  __syncthreads();
+  for (int p0 = 0; p0 < n; p0 += PW) {
+    const int pw = min(PW, n - p0);
+    if (wid == 0) {
+      if (pw == PW) lsm_tri_lower<T, NPH, true, KC>(A, ld, x, p0, PW, lane);
+      else lsm_tri_lower<T, NPH, false, KC>(A, ld, x, p0, pw, lane);
+    }
+    __syncthreads();
+    for (int rr = p0 + pw + tid; rr < n; rr += NT) lsm_row_update<T, NPH, true, KC>(A, ld, x, rr, p0, PW);
+    __syncthreads();
+  }
+  for (int p0 = ((n - 1) / PW) * PW; p0 >= 0; p0 -= PW) {
+    const int pw = min(PW, n - p0);
+    if (wid == 0) {
+      if (pw == PW) lsm_tri_upper<T, NPH, true, KC>(A, ld, x, p0, PW, lane);
+      else lsm_tri_upper<T, NPH, false, KC>(A, ld, x, p0, pw, lane);
+    }
+    __syncthreads();
+    if (pw == PW)
+      for (int rr = tid; rr < p0; rr += NT) lsm_row_update<T, NPH, true, KC>(A, ld, x, rr, p0, PW);
+    else
+      for (int rr = tid; rr < p0; rr += NT) lsm_row_update<T, NPH, false, KC>(A, ld, x, rr, p0, pw);
+    __syncthreads();
+  }
+  for (int a = tid; a < n; a += NT) {
+#pragma unroll
+    for (int s = 0; s < KC; ++s)
+      if (s < kk) W[s * ldw + base + a] = (double)x[a * KC + s];
+  }
+}
+
 __global__ void k_scatter_sum(int64_t n, const int64_t* __restrict__ sc_ptr, const int* __restrict__ sc_pos,
                               const double* __restrict__ w, double* __restrict__ z) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -313,6 +482,38 @@ void local_solves(int nparts, int max_n, const int* order, const int64_t* dom_pt
   GDSW_LAUNCH_CHECK();
 }
 
+int local_solves_multi_chunk(int max_n, int value_bytes) {
+  const size_t per = (size_t)max_n * value_bytes;   // LDS bytes per right-hand side (at most 64 KiB in all)
+  if (per * 8 <= 64 * 1024) return 8;
+  if (per * 4 <= 64 * 1024) return 4;
+  if (per * 2 <= 64 * 1024) return 2;
+  return 1;
+}
+
+template <typename T>
+void local_solves_multi(int nparts, int max_n, const int* order, const int64_t* dom_ptr, const int* gidx,
+                        const int64_t* blk_off, const T* blocks, int pad, const double* R, int64_t ldr, double* W,
+                        int64_t ldw, int k, hipStream_t s) {
+  if (nparts == 0 || k <= 0) return;
+  const int kc = local_solves_multi_chunk(max_n, sizeof(T));
+  if ((size_t)max_n * sizeof(T) > 64 * 1024) throw Error(-1, "local block too large for the LDS-resident right-hand sides");
+  for (int s0 = 0; s0 < k; s0 += kc) {
+    const int kk = std::min(kc, k - s0);
+    const double* Rs = R + (int64_t)s0 * ldr;
+    double* Ws = W + (int64_t)s0 * ldw;
+    const size_t lds = (size_t)max_n * sizeof(T) * kc;
+#define GDSW_LSM(KC)                                                                                              \
+  hipLaunchKernelGGL((k_local_solve_multi<T, KC>), dim3(nparts), dim3(512), lds, s, order, dom_ptr, gidx, blk_off, \
+                     blocks, Rs, ldr, Ws, ldw, kk, pad)
+    if (kc == 8) GDSW_LSM(8);
+    else if (kc == 4) GDSW_LSM(4);
+    else if (kc == 2) GDSW_LSM(2);
+    else GDSW_LSM(1);
+#undef GDSW_LSM
+    GDSW_LAUNCH_CHECK();
+  }
+}
+
 void scatter_sum(int64_t n, const int64_t* sc_ptr, const int* sc_pos, const double* w, double* z, hipStream_t s) {
   hipLaunchKernelGGL(k_scatter_sum, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, sc_ptr, sc_pos, w, z);
   GDSW_LAUNCH_CHECK();
@@ -356,6 +557,11 @@ void dense_gemv_rows(int n, const double* AT, const double* x, double* y, hipStr
 template void local_solves<double>(int, int, const int*, const int64_t*, const int*, const int64_t*,
                                    const double*, int, const double*, double*, bool, int, hipStream_t, hipEvent_t,
                                    hipEvent_t);
+template void local_solves_multi<double>(int, int, const int*, const int64_t*, const int*, const int64_t*,
+                                         const double*, int, const double*, int64_t, double*, int64_t, int,
+                                         hipStream_t);
+template void local_solves_multi<float>(int, int, const int*, const int64_t*, const int*, const int64_t*,
+                                        const float*, int, const double*, int64_t, double*, int64_t, int, hipStream_t);
 template void local_solves<float>(int, int, const int*, const int64_t*, const int*, const int64_t*, const float*, int,
                                   const double*, double*, bool, int, hipStream_t, hipEvent_t, hipEvent_t);
 template void restrict_phi<double>(int, const int64_t*, const int*, const int64_t*, const int*, const int*,

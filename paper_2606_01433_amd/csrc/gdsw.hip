@@ -232,6 +232,11 @@ struct Level {
   double* yc = nullptr;          // coarse correction (n_coarse)
   double interior_flops = 0.0;
   int64_t phi_elems = 0;         // sum_i |I_i| m_i (values of Phi_I)
+  // several right-hand sides (gdsw_apply_multi): local solutions [s][sum_n], coarse vectors [s][n_coarse]
+  int multi_cap = 0;
+  double* wm = nullptr;
+  double* rcm = nullptr;
+  double* ycm = nullptr;
   hipEvent_t lu_ev[2] = {nullptr, nullptr};   // around the batched LU of this level (timing)
 };
 
@@ -258,6 +263,10 @@ struct gdsw_ctx {
   // host-side Givens/Hessenberg arrays of the solve, sized at setup for the restart length
   std::vector<double> kH, kcs, ksn, kg, ky;
   bool no_alloc_call = false;          // inside gdsw_solve_noalloc: no event creation in applies
+  // gdsw_solve_multi: workspaces of up to multi_cap systems, page-locked Hessenberg columns
+  int multi_cap = 0, multi_m = -1;
+  double *mV = nullptr, *mZ = nullptr, *mW = nullptr, *mH = nullptr, *mY = nullptr, *mP = nullptr;
+  double* mhost = nullptr;
   // event pairs around level-1 local-solve launches (profile = 1)
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
@@ -310,6 +319,8 @@ struct gdsw_ctx {
       (void)hipStreamDestroy(up);
     }
     release_pinned();
+    if (hhost) (void)hipHostFree(hhost);
+    if (mhost) (void)hipHostFree(mhost);
     if (ev_up) (void)hipEventDestroy(ev_up);
     if (ev_fetch) (void)hipEventDestroy(ev_fetch);
   }
@@ -1076,6 +1087,72 @@ void apply_any(gdsw_ctx* C, const double* r, double* z, hipStream_t s) {
   else apply_level<double>(C, 0, r, z, s);
 }
 
+// ---- several right-hand sides ----------------------------------------------
+// Z[:, s] = B_l R[:, s] for s < k: the local solves of each level stream every
+// factor once per chunk of right-hand sides; everything else runs per
+// right-hand side with the single-vector kernels.  Every column is bit-identical
+// to the single apply of that column.
+void ensure_multi_level(gdsw_ctx* C, int k) {
+  for (Level& L : C->levels) {
+    if (L.multi_cap >= k) continue;
+    L.wm = C->arena.alloc_n<double>((size_t)L.sum_n * k);
+    if (L.has_coarse) {
+      L.rcm = C->arena.alloc_n<double>((size_t)L.n_coarse * k);
+      L.ycm = C->arena.alloc_n<double>((size_t)L.n_coarse * k);
+    }
+    L.multi_cap = k;
+  }
+}
+
+template <typename T>
+void apply_level_multi(gdsw_ctx* C, int l, const double* R, int64_t ldr, double* Z, int64_t ldz, int k,
+                       hipStream_t s);
+
+template <typename T>
+void coarse_chain_multi(gdsw_ctx* C, int l, const double* R, int64_t ldr, int k, hipStream_t s) {
+  Level& L = C->levels[l];
+  const T* phi = static_cast<const T*>(L.phi);
+  const int64_t nc = L.n_coarse;
+  for (int q = 0; q < k; ++q)
+    restrict_phi<T>(L.n_coarse, L.col_ptr, L.col_dofs, L.cp_ptr, L.cp_part, L.cp_lc, L.int_ptr, L.inter, L.phi_off,
+                    phi, R + q * ldr, L.rcm + q * nc, s);
+  if (l + 1 < (int)C->levels.size()) {
+    apply_level_multi<T>(C, l + 1, L.rcm, nc, L.ycm, nc, k, s);
+  } else {
+    for (int q = 0; q < k; ++q) dense_gemv_rows(C->nc, C->ainv, L.rcm + q * nc, L.ycm + q * nc, s);
+  }
+}
+
+template <typename T>
+void apply_level_multi(gdsw_ctx* C, int l, const double* R, int64_t ldr, double* Z, int64_t ldz, int k,
+                       hipStream_t s) {
+  Level& L = C->levels[l];
+  const bool fork = L.has_coarse && l == 0;
+  if (fork) {
+    GDSW_HIP(hipEventRecord(C->ev_fork, s));
+    GDSW_HIP(hipStreamWaitEvent(C->side, C->ev_fork, 0));
+    coarse_chain_multi<T>(C, l, R, ldr, k, C->side);
+    GDSW_HIP(hipEventRecord(C->ev_join, C->side));
+  }
+  local_solves_multi<T>(L.nparts, L.max_n, L.order, L.dom_ptr, L.gidx, L.blk_off, static_cast<const T*>(L.blocks),
+                        L.pad, R, ldr, L.wm, L.sum_n, k, s);
+  for (int q = 0; q < k; ++q) scatter_sum(L.n, L.sc_ptr, L.sc_pos, L.wm + q * L.sum_n, Z + q * ldz, s);
+  if (!L.has_coarse) return;
+  if (fork) GDSW_HIP(hipStreamWaitEvent(s, C->ev_join, 0));
+  else coarse_chain_multi<T>(C, l, R, ldr, k, s);
+  const T* phi = static_cast<const T*>(L.phi);
+  const int64_t nc = L.n_coarse;
+  for (int q = 0; q < k; ++q)
+    prolong_add<T>(L.nparts, L.max_m, L.n_gdofs, L.gdofs, L.dof_gcol, L.int_ptr, L.inter, L.pc_ptr, L.pcols,
+                   L.phi_off, phi, L.ycm + q * nc, Z + q * ldz, s);
+}
+
+void apply_multi_any(gdsw_ctx* C, const double* R, int64_t ldr, double* Z, int64_t ldz, int k, hipStream_t s) {
+  ensure_multi_level(C, k);
+  if (C->mixed) apply_level_multi<float>(C, 0, R, ldr, Z, ldz, k, s);
+  else apply_level_multi<double>(C, 0, R, ldr, Z, ldz, k, s);
+}
+
 // Device workspace of one FGMRES(m) solve on n rows.
 struct KrylovWs {
   double *V = nullptr, *Z = nullptr, *w = nullptr, *dpart = nullptr, *hdev = nullptr, *ydev = nullptr;
@@ -1325,6 +1402,197 @@ int solve_impl(gdsw_ctx* C, const double* b, double* x, hipStream_t caller, gdsw
   return inf.converged ? GDSW_OK : GDSW_NOTCONV;
 }
 
+// k FGMRES(m) solves in lockstep on one context: every inner iteration applies
+// the preconditioner to the current Krylov vectors of all k systems at once
+// (one pass over the local factors per chunk of systems); SpMV, Gram-Schmidt,
+// Givens rotations, restarts and convergence are those of solve_impl, per
+// system, so each x_s equals gdsw_solve's for b_s bit for bit.  A system that
+// has converged (or reached max_it) keeps its iterate; its columns of the
+// shared apply are computed and ignored.
+int solve_multi_impl(gdsw_ctx* C, int k, const double* B, int64_t ldb, double* X, int64_t ldx, hipStream_t s,
+                     gdsw_solve_info* infos) {
+  const double t0 = now_ms();
+  const int m = C->opt.restart;
+  const int64_t n = C->levels[0].n;
+  const CsrDev& K = C->levels[0].K;
+  const int hs = 2 * (m + 1) + 2;             // per-system Hessenberg slots (h1, h2, norm, pad)
+  if (C->multi_cap < k || C->multi_m != m) {
+    Arena& A = C->arena;
+    C->mV = A.alloc_n<double>((size_t)k * n * (m + 1));
+    C->mZ = A.alloc_n<double>((size_t)k * n * m);
+    C->mW = A.alloc_n<double>((size_t)k * n);
+    C->mH = A.alloc_n<double>((size_t)k * hs);
+    C->mY = A.alloc_n<double>((size_t)k * (m + 1));
+    C->mP = A.alloc_n<double>((size_t)multi_dot_blocks(n) * (m + 2));
+    if (C->mhost) (void)hipHostFree(C->mhost);
+    C->mhost = nullptr;
+    GDSW_HIP(hipHostMalloc((void**)&C->mhost, sizeof(double) * ((size_t)k * hs + (size_t)k * (m + 1) + 8),
+                           hipHostMallocDefault));
+    C->multi_cap = k;
+    C->multi_m = m;
+  }
+  const int64_t ldv = n * (m + 1), ldzz = n * m;
+  double* hh = C->mhost;
+  double* hy = C->mhost + (size_t)k * hs;
+  auto Vs = [&](int q) { return C->mV + q * ldv; };
+  auto Zs = [&](int q) { return C->mZ + q * ldzz; };
+  auto Hs = [&](int q) { return C->mH + (int64_t)q * hs; };
+  auto fetch_all = [&]() {
+    GDSW_HIP(hipMemcpyAsync(hh, C->mH, (size_t)k * hs * sizeof(double), hipMemcpyDeviceToHost, s));
+    GDSW_HIP(hipEventRecord(C->ev_fetch, s));
+    wait_event_polling(C->ev_fetch);
+  };
+  struct Sys {
+    double bnorm = 0, beta = 0;
+    int its = 0, k = 0, restarts = 0;
+    bool done = false, conv = false, running = false;
+    std::vector<double> H, cs, sn, g, y;
+  };
+  std::vector<Sys> sy(k);
+  for (int q = 0; q < k; ++q) {
+    Sys& S = sy[q];
+    S.H.assign((size_t)(m + 1) * m, 0.0);
+    S.cs.assign(m, 0.0);
+    S.sn.assign(m, 0.0);
+    S.g.assign(m + 1, 0.0);
+    S.y.assign(m, 0.0);
+    multi_dot(n, 1, B + q * ldb, n, B + q * ldb, C->mP, Hs(q) + 2 * (m + 1), s);
+    GDSW_HIP(hipMemsetAsync(X + q * ldx, 0, n * sizeof(double), s));
+  }
+  fetch_all();
+  for (int q = 0; q < k; ++q) {
+    sy[q].bnorm = std::sqrt(hh[(size_t)q * hs + 2 * (m + 1)]);
+    if (sy[q].bnorm == 0.0) {
+      sy[q].done = true;
+      sy[q].conv = true;
+    }
+  }
+  std::vector<double> rel(k, 0.0);
+  while (true) {
+    // true residuals of the systems still going
+    bool any = false;
+    for (int q = 0; q < k; ++q) {
+      if (sy[q].done) continue;
+      spmv(K, X + q * ldx, Vs(q), s);
+      residual_from(n, B + q * ldb, Vs(q), s);
+      multi_dot(n, 1, Vs(q), n, Vs(q), C->mP, Hs(q) + 2 * (m + 1), s);
+      any = true;
+    }
+    if (!any) break;
+    fetch_all();
+    bool cycle = false;
+    for (int q = 0; q < k; ++q) {
+      Sys& S = sy[q];
+      S.running = false;
+      if (S.done) continue;
+      S.beta = std::sqrt(hh[(size_t)q * hs + 2 * (m + 1)]);
+      rel[q] = S.beta / S.bnorm;
+      if (rel[q] <= C->opt.tol) {
+        S.done = S.conv = true;
+        continue;
+      }
+      if (S.its >= C->opt.max_it) {
+        S.done = true;
+        continue;
+      }
+      scale_by_inv_norm(n, Vs(q), Hs(q) + 2 * (m + 1), Vs(q), s);
+      std::fill(S.H.begin(), S.H.end(), 0.0);
+      std::fill(S.g.begin(), S.g.end(), 0.0);
+      S.g[0] = S.beta;
+      S.k = 0;
+      S.running = true;
+      cycle = true;
+    }
+    if (!cycle) break;          // every remaining system converged or stopped at this check
+    for (int j = 0; j < m; ++j) {
+      bool run = false;
+      for (const Sys& S : sy) run |= S.running;
+      if (!run) break;
+      // the preconditioner on column j of every system (stride n (m + 1) between systems)
+      apply_multi_any(C, C->mV + (int64_t)j * n, ldv, C->mZ + (int64_t)j * n, ldzz, k, s);
+      for (int q = 0; q < k; ++q) {
+        if (!sy[q].running) continue;
+        double* V = Vs(q);
+        double* zj = Zs(q) + (int64_t)j * n;
+        double* w = C->mW + q * n;
+        double* h1 = Hs(q);
+        double* h2 = Hs(q) + (m + 1);
+        double* nr = Hs(q) + 2 * (m + 1);
+        spmv(K, zj, w, s);
+        multi_dot(n, j + 1, V, n, w, C->mP, h1, s);
+        if (j + 1 <= fused_gs_max_cols()) {
+          axpy_dot(n, j + 1, V, n, h1, w, C->mP, h2, false, s);
+          axpy_dot(n, j + 1, V, n, h2, w, C->mP, nr, true, s);
+        } else {
+          multi_axpy(n, j + 1, V, n, h1, w, s);
+          multi_dot(n, j + 1, V, n, w, C->mP, h2, s);
+          multi_axpy(n, j + 1, V, n, h2, w, s);
+          multi_dot(n, 1, w, n, w, C->mP, nr, s);
+        }
+        scale_by_inv_norm(n, w, nr, V + (int64_t)(j + 1) * n, s);
+      }
+      fetch_all();
+      for (int q = 0; q < k; ++q) {
+        Sys& S = sy[q];
+        if (!S.running) continue;
+        const double* hq = hh + (size_t)q * hs;
+        double* Hj = S.H.data() + (size_t)j * (m + 1);
+        for (int i = 0; i <= j; ++i) Hj[i] = hq[i] + hq[(m + 1) + i];
+        Hj[j + 1] = std::sqrt(hq[2 * (m + 1)]);
+        const bool breakdown = Hj[j + 1] == 0.0;
+        for (int i = 0; i < j; ++i) {
+          const double t = S.cs[i] * Hj[i] + S.sn[i] * Hj[i + 1];
+          Hj[i + 1] = -S.sn[i] * Hj[i] + S.cs[i] * Hj[i + 1];
+          Hj[i] = t;
+        }
+        const double den = std::hypot(Hj[j], Hj[j + 1]);
+        S.cs[j] = den > 0 ? Hj[j] / den : 1.0;
+        S.sn[j] = den > 0 ? Hj[j + 1] / den : 0.0;
+        Hj[j] = den;
+        Hj[j + 1] = 0.0;
+        S.g[j + 1] = -S.sn[j] * S.g[j];
+        S.g[j] = S.cs[j] * S.g[j];
+        ++S.its;
+        S.k = j + 1;
+        if (std::fabs(S.g[j + 1]) / S.bnorm <= C->opt.tol || S.its >= C->opt.max_it || breakdown) S.running = false;
+      }
+    }
+    // x += Z y for every system of this cycle
+    for (int q = 0; q < k; ++q) {
+      Sys& S = sy[q];
+      if (S.done || S.k == 0) continue;
+      const int kq = S.k;
+      for (int i = kq - 1; i >= 0; --i) {
+        double t = S.g[i];
+        for (int c = i + 1; c < kq; ++c) t -= S.H[(size_t)c * (m + 1) + i] * S.y[c];
+        const double d = S.H[(size_t)i * (m + 1) + i];
+        S.y[i] = d != 0.0 ? t / d : 0.0;
+      }
+      for (int i = 0; i < kq; ++i) hy[(size_t)q * (m + 1) + i] = -S.y[i];
+      GDSW_HIP(hipMemcpyAsync(C->mY + (int64_t)q * (m + 1), hy + (size_t)q * (m + 1), kq * sizeof(double),
+                              hipMemcpyHostToDevice, s));
+      multi_axpy(n, kq, Zs(q), n, C->mY + (int64_t)q * (m + 1), X + q * ldx, s);
+      S.restarts++;
+      S.k = 0;
+    }
+    GDSW_HIP(hipStreamSynchronize(s));   // the host buffers are reused by the next fetch
+  }
+  int code = GDSW_OK;
+  const double total = now_ms() - t0;
+  for (int q = 0; q < k; ++q) {
+    gdsw_solve_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    inf.iterations = sy[q].its;
+    inf.restarts = sy[q].restarts;
+    inf.converged = sy[q].conv ? 1 : 0;
+    inf.rel_residual = rel[q];
+    inf.ms_total = total;
+    if (infos) infos[q] = inf;
+    if (!sy[q].conv) code = GDSW_NOTCONV;
+  }
+  return code;
+}
+
 int fail(const Error& e) {
   g_last_error = e.what();
   return e.code;
@@ -1501,6 +1769,32 @@ int gdsw_solve_noalloc(gdsw_ctx* C, const double* b, double* x, void* stream, gd
   }
 }
 
+int gdsw_apply_multi(gdsw_ctx* C, int32_t k, const double* R, int64_t ldr, double* Z, int64_t ldz, void* stream) {
+  if (!C || !R || !Z || k < 1 || k > GDSW_MAX_RHS || ldr < C->levels[0].n || ldz < C->levels[0].n || R == Z) {
+    gdsw::g_last_error = "gdsw_apply_multi: NULL, aliased or out-of-range argument";
+    return GDSW_EINVAL;
+  }
+  try {
+    gdsw::apply_multi_any(C, R, ldr, Z, ldz, k, static_cast<hipStream_t>(stream));
+  } catch (const Error& e) {
+    return gdsw::fail(e);
+  }
+  return GDSW_OK;
+}
+
+int gdsw_solve_multi(gdsw_ctx* C, int32_t k, const double* B, int64_t ldb, double* X, int64_t ldx, void* stream,
+                     gdsw_solve_info* info) {
+  if (!C || !B || !X || k < 1 || k > GDSW_MAX_RHS || ldb < C->levels[0].n || ldx < C->levels[0].n || B == X) {
+    gdsw::g_last_error = "gdsw_solve_multi: NULL, aliased or out-of-range argument";
+    return GDSW_EINVAL;
+  }
+  try {
+    return gdsw::solve_multi_impl(C, k, B, ldb, X, ldx, static_cast<hipStream_t>(stream), info);
+  } catch (const Error& e) {
+    return gdsw::fail(e);
+  }
+}
+
 int gdsw_spmv(gdsw_ctx* C, const double* x, double* y, void* stream) {
   if (!C || !x || !y) {
     gdsw::g_last_error = "gdsw_spmv: NULL argument";
@@ -1664,7 +1958,6 @@ void gdsw_destroy(gdsw_ctx* C) {
   // the device blocks go back to the process cache: drain the device first
   // (the same wait hipFree implies), so no queued work still uses them
   (void)hipDeviceSynchronize();
-  if (C->hhost) (void)hipHostFree(C->hhost);
   delete C;
 }
 

@@ -124,6 +124,14 @@ template <typename T>
 void local_solves(int nparts, int max_n, const int* order, const int64_t* dom_ptr, const int* gidx,
                   const int64_t* blk_off, const T* blocks, int pad, const double* r, double* w, bool first_level,
                   int waves, hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// The local solves of k right-hand sides (R[s * ldr + g], s < k) into W[s * ldw + position], in chunks
+// of local_solves_multi_chunk(max_n, sizeof(T)) right-hand sides per pass over the factors; each column
+// equals local_solves' result for that right-hand side bit for bit.
+template <typename T>
+void local_solves_multi(int nparts, int max_n, const int* order, const int64_t* dom_ptr, const int* gidx,
+                        const int64_t* blk_off, const T* blocks, int pad, const double* R, int64_t ldr, double* W,
+                        int64_t ldw, int k, hipStream_t s);
+int local_solves_multi_chunk(int max_n, int value_bytes);
 // z[g] = 0.0 + sum_k w[pos[k]] over sc_ptr[g]..sc_ptr[g+1]; with sc_ptr == nullptr, z[g] = 0.0 + w[pos[g]]
 void scatter_sum(int64_t n, const int64_t* sc_ptr, const int* sc_pos, const double* w, double* z, hipStream_t s);
 // rc = Phi^T r

@@ -13,6 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgdsw.so")
 
 OK, NOTCONV, EINVAL, ESINGULAR, ENOMEM, EHIP = 0, 1, -1, -2, -3, -4
+MAX_RHS = 32          # GDSW_MAX_RHS
 _CODE_NAMES = {EINVAL: "EINVAL", ESINGULAR: "ESINGULAR", ENOMEM: "ENOMEM", EHIP: "EHIP", NOTCONV: "NOTCONV"}
 
 c_i32, c_i64, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
@@ -60,6 +61,8 @@ SIGNATURES = {
     "gdsw_apply": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
     "gdsw_solve": (c_i32, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(SolveInfo)]),
     "gdsw_solve_noalloc": (c_i32, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(SolveInfo)]),
+    "gdsw_apply_multi": (c_i32, [c_vp, c_i32, c_vp, c_i64, c_vp, c_i64, c_vp]),
+    "gdsw_solve_multi": (c_i32, [c_vp, c_i32, c_vp, c_i64, c_vp, c_i64, c_vp, ctypes.POINTER(SolveInfo)]),
     "gdsw_spmv": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
     "gdsw_scatter_local": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp]),
     "gdsw_export_maps": (c_i32, [c_vp, c_i32, ctypes.POINTER(MapsView)]),
@@ -268,6 +271,39 @@ class Context:
         _check(self._lib.gdsw_apply(self._alive(), self._dev(r, self.n), self._dev(z, self.n),
                                     _stream_handle(stream)))
         return z
+
+    @staticmethod
+    def _dev_block(t, n):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                and t.dim() == 2 and t.shape[1] == n):
+            raise TypeError(f"expected a contiguous CUDA float64 tensor of shape (k, {n})")
+        if not 1 <= t.shape[0] <= MAX_RHS:
+            raise ValueError(f"k = {t.shape[0]} right-hand sides, expected 1..{MAX_RHS}")
+        return t.data_ptr()
+
+    def apply_multi(self, R, out=None, stream=None):
+        """Z[s] = B R[s] for the k rows of R (shape (k, n)): gdsw_apply_multi."""
+        import torch
+        Z = torch.empty_like(R) if out is None else out
+        _check(self._lib.gdsw_apply_multi(self._alive(), int(R.shape[0]), self._dev_block(R, self.n), self.n,
+                                          self._dev_block(Z, self.n), self.n, _stream_handle(stream)))
+        return Z
+
+    def solve_multi(self, B, out=None, stream=None):
+        """k FGMRES solves in lockstep (gdsw_solve_multi); B of shape (k, n). Returns (X, list of infos)."""
+        import torch
+        X = torch.empty_like(B) if out is None else out
+        k = int(B.shape[0])
+        infos = (SolveInfo * k)()
+        code = _check(self._lib.gdsw_solve_multi(self._alive(), k, self._dev_block(B, self.n), self.n,
+                                                 self._dev_block(X, self.n), self.n, _stream_handle(stream), infos))
+        out_infos = []
+        for q in range(k):
+            d = {f: getattr(infos[q], f) for f, _ in SolveInfo._fields_}
+            d["code"] = code
+            out_infos.append(d)
+        return X, out_infos
 
     def spmv(self, x, out=None, stream=None):
         import torch
