@@ -52,11 +52,23 @@ def gauss_gradients(mesh, nodal_u):
 ASSEMBLY_CHUNK = 65536
 
 
-def assemble(mesh, nu_q, form, f=(0.0, 0.0, 0.0)):
+def newton_vectors(mesh, D_q):
+    """t[e, q, 3a + i] = (D_q G_a)_i: the derivative of D(u_k):D(v) at Gauss point q of element e with
+    respect to the velocity dof (a, i) of v, up to the factor 2/h (D_q: (E, 27, 3, 3) symmetric
+    gradients of the linearization point in physical units, G_a: reference gradients of node a)."""
+    return np.einsum("eqik,qak->eqai", D_q, _DPHI).reshape(D_q.shape[0], 27, 81)
+
+
+def assemble(mesh, nu_q, form, f=(0.0, 0.0, 0.0), newton=None):
     """Full (unconstrained) K in COO-summed CSR over all dofs and the load vector.
 
     Full dof numbering: velocity 3*node + i, then pressure 3*n_nodes + 4*e + m.
     nu_q: (E, 27) viscosity at Gauss points.
+    newton: None (Picard: the viscosity frozen at the linearization point), or
+    (c_q, D_q) adding the derivative of the viscosity to the velocity block,
+    (h/2) sum_q w_q c_q t_q t_q^T per element with t from newton_vectors (the
+    Newton term of section 3's alternating Picard-Newton iteration; c_q =
+    4 nu'(gamma_dot) / gamma_dot at the Gauss points).
     """
     h = mesh.h
     E = mesh.n_elem
@@ -74,6 +86,10 @@ def assemble(mesh, nu_q, form, f=(0.0, 0.0, 0.0)):
     def block(e0, e1):
         En = e1 - e0
         Ae = (0.5 * h) * (nu_q[e0:e1] @ M.reshape(27, 81 * 81)).reshape(En, 81, 81)
+        if newton is not None:
+            c_q, D_q = newton
+            t = newton_vectors(mesh, D_q[e0:e1])
+            Ae = Ae + (0.5 * h) * np.einsum("eq,eqx,eqy->exy", c_q[e0:e1] * _WTS[None, :], t, t)
         vd = (3 * mesh.elem_node[e0:e1, :, None] + np.arange(3)[None, None, :]).reshape(En, 81)
         pd = nv + 4 * np.arange(e0, e1)[:, None] + np.arange(4)[None, :]
         rows = [vd[:, ii].ravel(), pd[:, :, None].repeat(81, 2).ravel(), vd[:, None, :].repeat(4, 1).ravel()]

@@ -67,8 +67,10 @@ def _number_dofs(mesh, dir_node, pinned_p):
 
 
 def _build(name, mesh, nu_q, form, f, dir_node, dir_values, pinned_p, pin_values,
-           elem_part, n_parts, part_parent, levels, x_full=None, meta=None):
-    K, F = assemble(mesh, nu_q, form, f)
+           elem_part, n_parts, part_parent, levels, x_full=None, meta=None, newton=None, rhs_extra=None):
+    K, F = assemble(mesh, nu_q, form, f, newton=newton)
+    if rhs_extra is not None:
+        F = F + rhs_extra
     free, node_dof, elem_pdof = _number_dofs(mesh, dir_node, pinned_p)
     fixed_vals = np.zeros(free.shape[0])
     nv = 3 * mesh.n_nodes
@@ -151,12 +153,27 @@ def linearization_field(mesh, rng, lam, target=10.0):
     return u
 
 
+def carreau_slope(gamma_dot, nu0, lam, n_exp):
+    """nu'(gamma_dot) / gamma_dot = nu0 (n - 1) lam^2 (1 + (lam gamma_dot)^2)^((n-3)/2), finite at 0."""
+    return nu0 * (n_exp - 1.0) * lam * lam * (1.0 + (lam * gamma_dot) ** 2) ** ((n_exp - 3.0) / 2.0)
+
+
+def symmetric_gradients(grad):
+    return 0.5 * (grad + np.swapaxes(grad, -1, -2))
+
+
 def die_problem(nx=32, ny=16, nz=16, seed=0, nu0=1.0, lam=1.0, n_exp=0.5, levels=3,
-                frac3=0.0, masked=0.20, inflow_speed=1.0):
+                frac3=0.0, masked=0.20, inflow_speed=1.0, linearization="picard"):
     """Seeded die-like voxel channel with Carreau viscosity linearized at a smooth field.
 
     Inflow: two rectangular windows on x = 0 with a parabolic x-velocity;
     outflow: the x = x_max face (do-nothing); all other boundary faces no-slip.
+    linearization: "picard" freezes the viscosity at the linearization point
+    u_k (K = the Stokes operator with nu(u_k)); "newton" is the Newton step of
+    the same nonlinear operator at u_k: the velocity block gains the
+    derivative of nu, and the right-hand side is the one of the Newton update
+    J(u_k) u_{k+1} = (J(u_k) - A(u_k)) u_k + f, i.e. the Newton term applied to
+    u_k (with the same Dirichlet data).
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     active = die_voxels(nx, ny, nz, rng, target=masked)
@@ -192,11 +209,23 @@ def die_problem(nx=32, ny=16, nz=16, seed=0, nu0=1.0, lam=1.0, n_exp=0.5, levels
     sz = axis_segments(nz, seg_rng, frac3)
     elem_part, n_parts, part_parent = part_hierarchy(mesh, sx, sy, sz, levels)
     uk = linearization_field(mesh, rng, lam)
-    gd = shear_rate(gauss_gradients(mesh, uk))                # (E, 27)
+    grad = gauss_gradients(mesh, uk)
+    gd = shear_rate(grad)                                     # (E, 27)
     nu_q = carreau(gd, nu0, lam, n_exp)
-    return _build(f"die{nx}x{ny}x{nz}_s{seed}_L{levels}", mesh, nu_q, "sym", (0.0, 0.0, 0.0), dir_node, g,
-                  [], [], elem_part, n_parts, part_parent, levels,
+    newton = rhs_extra = None
+    if linearization == "newton":
+        newton = (4.0 * carreau_slope(gd, nu0, lam, n_exp), symmetric_gradients(grad))
+        N = assemble(mesh, np.zeros_like(nu_q), "sym", (0.0, 0.0, 0.0), newton=newton)[0]
+        u_full = np.concatenate([uk.ravel(), np.zeros(4 * mesh.n_elem)])
+        rhs_extra = N @ u_full
+        rhs_extra[3 * mesh.n_nodes:] = 0.0         # N holds the divergence blocks too: velocity rows only
+    elif linearization != "picard":
+        raise ValueError(linearization)
+    tag = "" if linearization == "picard" else "_newton"
+    return _build(f"die{nx}x{ny}x{nz}_s{seed}_L{levels}{tag}", mesh, nu_q, "sym", (0.0, 0.0, 0.0), dir_node, g,
+                  [], [], elem_part, n_parts, part_parent, levels, newton=newton, rhs_extra=rhs_extra,
                   meta=dict(kind="die", nx=nx, ny=ny, nz=nz, h=h, seed=seed, nu0=nu0, lam=lam, n_exp=n_exp,
+                            linearization=linearization,
                             masked=float(1.0 - active.mean()), windows=wins, frac3=frac3,
                             nu_min=float(nu_q.min()), nu_max=float(nu_q.max())))
 

@@ -83,3 +83,44 @@ def test_chunked_assembly_keeps_pattern_and_values(monkeypatch):
     assert np.array_equal(P0.rowptr, P1.rowptr) and np.array_equal(P0.col, P1.col)
     assert np.abs(P0.val - P1.val).max() <= 8 * np.finfo(np.float64).eps * np.abs(P0.val).max()
     assert np.array_equal(P0.b, P1.b)
+
+
+def test_newton_term_is_the_derivative_of_the_carreau_operator():
+    """Finite-difference check of the Newton linearization (section 3's Picard-Newton iteration): with
+    A(w) the velocity block assembled with nu(w) at the Gauss points, the Newton matrix J(u) = A(u) + N(u)
+    satisfies J(u) d = (A(u + e d)(u + e d) - A(u - e d)(u - e d)) / (2 e) + O(e^2).  Also J = J^T (the
+    operator is the gradient of a dissipation potential) and N differs from zero."""
+    import numpy as np
+    from harness.mesh import VoxelMesh
+    from harness.assemble import assemble, gauss_gradients
+    from harness.problems import carreau, carreau_slope, shear_rate, symmetric_gradients
+    rng = np.random.Generator(np.random.PCG64(5))
+    mesh = VoxelMesh(np.ones((2, 2, 1), dtype=bool), 0.5)
+    nu0, lam, n_exp = 2.0, 3.0, 0.4
+    u = rng.standard_normal((mesh.n_nodes, 3))
+    d = rng.standard_normal((mesh.n_nodes, 3))
+    nv = 3 * mesh.n_nodes
+
+    def A_of(w):
+        gdw = shear_rate(gauss_gradients(mesh, w))
+        return assemble(mesh, carreau(gdw, nu0, lam, n_exp), "sym")[0].toarray()[:nv, :nv]
+
+    grad = gauss_gradients(mesh, u)
+    gd = shear_rate(grad)
+    newton = (4.0 * carreau_slope(gd, nu0, lam, n_exp), symmetric_gradients(grad))
+    J = assemble(mesh, carreau(gd, nu0, lam, n_exp), "sym", newton=newton)[0].toarray()[:nv, :nv]
+    eps = 1e-5
+    fd = (A_of(u + eps * d) @ (u + eps * d).ravel() - A_of(u - eps * d) @ (u - eps * d).ravel()) / (2 * eps)
+    jd = J @ d.ravel()
+    assert np.linalg.norm(jd - fd) <= 1e-7 * np.linalg.norm(jd)
+    assert np.abs(J - J.T).max() <= 1e-12 * np.abs(J).max()
+    assert np.linalg.norm(J - A_of(u)) >= 1e-3 * np.linalg.norm(J)
+
+
+def test_carreau_slope_closed_form():
+    import numpy as np
+    from harness.problems import carreau, carreau_slope
+    g = np.array([0.3, 1.7, 4.0])
+    h = 1e-6
+    fd = (carreau(g + h, 2.0, 3.0, 0.4) - carreau(g - h, 2.0, 3.0, 0.4)) / (2 * h) / g
+    assert np.allclose(carreau_slope(g, 2.0, 3.0, 0.4), fd, rtol=1e-7)
