@@ -95,7 +95,9 @@ class Runner:
 
     def context(self, **opts):
         from paper_2606_01433_amd import gdsw
-        return gdsw.Context(self.P, K=self.K, tol=1e-8, stream=self.stream, **opts)
+        o = dict(tol=1e-8)
+        o.update(opts)
+        return gdsw.Context(self.P, K=self.K, stream=self.stream, **o)
 
     def step(self, **opts):
         ctx = self.context(**opts)
@@ -267,6 +269,50 @@ def many_solve_leg(run, precision, ks=(1, 8, 32), tol=1e-1, reps=3):
     return out
 
 
+def ablation(stream, seed=0, steps=2):
+    """Mirror of Table 1 on seeded dies: 2, 3 and 4 levels at two part counts, FGMRES to 1e-8 (the
+    preconditioner role) and to a 1e-1 reduction (the coarse-solver role); Effic_rel as the paper defines
+    it (one GPU for every run, so the rank ratio is 1), T0 = three levels on the smaller die.  Also the
+    overlap of two node layers and the additive combination of eq. (2.2)."""
+    import numpy as np
+    from harness import die_problem
+    from paper_2606_01433_amd.metrics import effic_rel
+    rows = []
+    for shape in ((24, 12, 12), (32, 16, 16)):
+        for levels in (2, 3, 4):
+            P = die_problem(*shape, seed=seed, nu0=1.0, lam=1.0, n_exp=0.5, levels=levels)
+            run = Runner(P, stream)
+            for tol in (1e-8, 1e-1):
+                T, x, infos, stats = run.timed_steps(steps, 1, tol=tol)
+                st = stats[0]
+                rows.append({"die": "x".join(map(str, shape)), "n_dofs": int(P.n), "levels": levels, "tol": tol,
+                             "parts": st["parts"][:st["levels"]], "coarsest": st["n"][st["levels"] - 1],
+                             "ms_per_step": T * 1e3, "ms_setup": st["ms_total"], "ms_solve": infos[-1]["ms_total"],
+                             "iterations": infos[-1]["iterations"], "converged": bool(infos[-1]["converged"])})
+                say("ablation", rows[-1]["die"], levels, tol, rows[-1]["iterations"], f"{T * 1e3:.1f} ms")
+            del run
+    for tol in (1e-8, 1e-1):
+        base = [r for r in rows if r["die"] == "24x12x12" and r["levels"] == 3 and r["tol"] == tol][0]
+        for r in rows:
+            if r["tol"] == tol:
+                r["effic_rel"] = effic_rel(r["ms_per_step"], r["n_dofs"], 1, base["ms_per_step"], base["n_dofs"], 1)
+    extra = []
+    P = die_problem(32, 16, 16, seed=seed, nu0=1.0, lam=1.0, n_exp=0.5, levels=3)
+    run = Runner(P, stream)
+    T, x, infos, stats = run.timed_steps(steps, 1, overlap=2)
+    extra.append({"variant": "overlap 2 node layers, 3 levels, 32x16x16", "ms_per_step": T * 1e3,
+                  "iterations": infos[-1]["iterations"], "max_local_order": stats[0]["max_ni"][0],
+                  "converged": bool(infos[-1]["converged"])})
+    for levels in (2, 3):
+        Pl = P if levels == 3 else die_problem(32, 16, 16, seed=seed, nu0=1.0, lam=1.0, n_exp=0.5, levels=2)
+        runl = Runner(Pl, stream)
+        T, x, infos, stats = runl.timed_steps(1, 0, combine="additive", max_it=400)
+        extra.append({"variant": f"additive combination, {levels} levels, 32x16x16", "ms_per_step": T * 1e3,
+                      "iterations": infos[-1]["iterations"], "converged": bool(infos[-1]["converged"]),
+                      "rel_residual": infos[-1]["rel_residual"]})
+    return {"table1_mirror": rows, "variants": extra}
+
+
 def workload_leg(name, precision, steps, warmup, stream, seed=0, P=None):
     """setup + solve + destroy steps of one workload in one precision."""
     P = make_problem(name, seed) if P is None else P
@@ -400,6 +446,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=16)
+    ap.add_argument("--ablation", action="store_true", help="only the Table 1 mirror (levels, overlap, combination)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -420,6 +467,9 @@ def main():
         return
     gdsw.load_library()
     stream = torch.cuda.current_stream()
+    if args.ablation:
+        print(json.dumps(ablation(stream, args.seed)), flush=True)
+        return
     name = args.headline
     precision = args.precision or ("mixed" if name == "die96x48x48" else "fp64")
     P = make_problem(name, args.seed)

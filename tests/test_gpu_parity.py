@@ -396,3 +396,23 @@ def test_context_rejects_mistyped_csr(gd):
          torch.as_tensor(P.val, device=dev))
     with pytest.raises(ValueError):
         gd.Context(P, K=K)
+
+
+def test_apply_parity_two_node_layers(gd):
+    """Overlap of two node layers (about one element layer, the literal reading of section 2.1): local
+    blocks of order up to about 2200 (FP64 panels taller than the register panel), apply against the
+    oracle built with delta = 2, and the solve converges."""
+    P = _problem("die16_L3")
+    H = cached(("orc-d2", "die16_L3"), lambda: oracle.setup(P, delta=2))
+    r = random_vector(P.n, 31)
+    _say("apply overlap 2")
+    with gd.Context(P, overlap=2, tol=1e-8) as ctx:
+        assert ctx.stats()["max_ni"][0] > 2048
+        z = ctx.apply(_dev(r)).cpu().numpy()
+        x, info = ctx.solve(_dev(P.b))
+    zo = oracle.apply(H, r)
+    err, emax = _errs(z, zo)
+    _say("  rel err", err, "max err", emax, "iterations", info["iterations"])
+    assert err <= 1e-10 and emax <= 1e-10
+    assert info["converged"]
+    assert np.linalg.norm(P.K() @ x.cpu().numpy() - P.b) <= 1e-8 * np.linalg.norm(P.b) * 1.0001
