@@ -422,15 +422,27 @@ __global__ __launch_bounds__(128) void k_prolong_interior(const int64_t* __restr
   }
 }
 
-// y[r] = sum_c Ainv[r, c] x[c] with the inverse stored transposed (row r contiguous): one wave per row.
+// y[r] = sum_c Ainv[r, c] x[c] with the inverse stored transposed (row r contiguous): one wave per row,
+// four independent partial sums per lane (columns c, c + 64, c + 128, c + 192 of each 256-column
+// stretch) so that four loads per lane are in flight, combined in a fixed order.
 __global__ __launch_bounds__(256) void k_gemv_rows(int n, const double* __restrict__ AT, const double* __restrict__ x,
                                                    double* __restrict__ y) {
   const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= n) return;
   const int lane = threadIdx.x & 63;
   const double* row = AT + (int64_t)r * n;
-  double s = 0.0;
-  for (int c = lane; c < n; c += 64) s += row[c] * x[c];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int c = lane;
+  for (; c + 192 < n; c += 256) {
+    const double a0 = row[c], a1 = row[c + 64], a2 = row[c + 128], a3 = row[c + 192];
+    const double x0 = x[c], x1 = x[c + 64], x2 = x[c + 128], x3 = x[c + 192];
+    s0 += a0 * x0;
+    s1 += a1 * x1;
+    s2 += a2 * x2;
+    s3 += a3 * x3;
+  }
+  for (; c < n; c += 64) s0 += row[c] * x[c];
+  double s = (s0 + s1) + (s2 + s3);
   s = wave_sum(s);
   if (lane == 0) y[r] = s;
 }
