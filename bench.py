@@ -446,6 +446,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=16)
+    ap.add_argument("--serving-only", action="store_true", help="only the serving streams")
+    ap.add_argument("--serving-loads", default="0.5,0.8,0.95", help="comma-separated rho values")
     ap.add_argument("--ablation", action="store_true", help="only the Table 1 mirror (levels, overlap, combination)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
@@ -469,6 +471,10 @@ def main():
     stream = torch.cuda.current_stream()
     if args.ablation:
         print(json.dumps(ablation(stream, args.seed)), flush=True)
+        return
+    if args.serving_only:
+        loads = tuple(float(x) for x in args.serving_loads.split(","))
+        print(json.dumps(serving_bench(args.seed, n_requests=args.serving_requests, loads=loads)), flush=True)
         return
     name = args.headline
     precision = args.precision or ("mixed" if name == "die96x48x48" else "fp64")
