@@ -364,7 +364,12 @@ def serving_bench(seed=0, n_requests=16, loads=(0.5, 0.8, 0.95)):
                 time.sleep(delay)
             reqs.append(server.submit(Request(k, pool[int(picks[k])], arrival=time.perf_counter(), **opts)))
             t_next += gaps[k]
-        server.drain(reqs)
+            if (k + 1) % 20 == 0:
+                say(f"  submitted {k + 1}/{len(picks)}")
+        for k, r in enumerate(reqs):          # progress while the backlog drains
+            r.wait()
+            if (k + 1) % 20 == 0:
+                say(f"  completed {k + 1}/{len(reqs)}")
         t_end = time.perf_counter()
         server.close()
         return reqs, summarize(reqs, t_start, t_end)

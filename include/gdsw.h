@@ -113,9 +113,18 @@ typedef struct gdsw_problem {
  *             (one per Krylov column, captured on first use and replayed by
  *             later solves on the same context); the solve then runs on a
  *             stream of the context, ordered after and before `stream`.
- * tune      : 1 = at the end of setup, time the local solves of every level
- *             with 2, 4 and 8 wavefronts per matrix and keep the fastest
- *             (reported in gdsw_stats.ls_waves); 0 = ls_waves.
+ * tune      : bit 0 (1): at the end of setup, time the local solves of every
+ *             level with 2, 4 and 8 wavefronts per matrix and keep the fastest
+ *             (gdsw_stats.ls_waves; results bit-identical to any fixed choice);
+ *             bit 1 (2): time the batched LU variants of every level (paired
+ *             64-column steps with rank-128 trailing updates or single steps
+ *             with rank-64 updates; FP64 only: half- or full-width register
+ *             panels for panels of 769..2048 rows) and keep the fastest
+ *             (gdsw_stats.lu_variant; the variants agree up to rounding).
+ *             Choices are kept per batch shape for the process and, with the
+ *             environment variable GDSW_TUNE_CACHE=<file>, in that file; a
+ *             shape found there is not timed again.  0 = ls_waves, paired
+ *             steps, half-width panels.
  * ls_waves  : wavefronts per matrix of the local solves on every level when
  *             tune = 0: 0 = default (8), or 2, 4, 8.  Every choice gives
  *             bit-identical results (only the scheduling differs).
@@ -133,6 +142,12 @@ typedef struct gdsw_options {
   int32_t graph;
   int32_t tune;
   int32_t ls_waves;
+  int32_t lu_variant;   /* batched LU variant when tune bit 1 is clear: bit 0 = single 64-column steps
+                           with rank-64 updates (else paired, rank 128), bit 1 = full-width FP64 panels */
+  int32_t pressure_gamma; /* P1disc pressure in the coarse space (section 2.1): 0 = the constant mode of
+                             every element is an interface dof and the linear modes are interior
+                             (saddle-point extension); 1 = every pressure mode is an interface dof
+                             (velocity-only extension; the coarse columns are the same) */
 } gdsw_options;
 
 typedef struct gdsw_solve_info {
@@ -177,6 +192,7 @@ typedef struct gdsw_stats {
    * plus 2 |Phi_I| s (restriction and prolongation), plus 8 n_c^2 (coarsest inverse);
    * s = 8 (FP64) or 4 (FP32 factors) */
   double apply_bytes;
+  int32_t lu_variant[8];          /* batched LU variant of level l (see tune) */
 } gdsw_stats;
 
 /* Index maps of one level, host copies owned by the context (valid until

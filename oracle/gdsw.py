@@ -82,13 +82,14 @@ class Hierarchy:
         self.no_coarse = False
 
 
-def setup(problem, delta=1, levels=None, no_coarse=False, combine="RAS"):
+def setup(problem, delta=1, levels=None, no_coarse=False, combine="RAS", pressure_gamma="constants"):
     """Build the L-level hierarchy of eq. (2.2) for a harness Problem.
 
     combine="AS" sums every local solution over its whole overlapping set
     (R_i^T as printed in eq. (2.2)); combine="RAS" (default) keeps, for every
     dof, only the solution of the part that owns it.  no_coarse drops the
-    coarsest correction (one-level Schwarz when L = 2).
+    coarsest correction (one-level Schwarz when L = 2).  pressure_gamma: see
+    levels.build_level ("all": the extension of the coarse basis is velocity-only).
     """
     L = problem.levels if levels is None else levels
     H = Hierarchy()
@@ -100,7 +101,7 @@ def setup(problem, delta=1, levels=None, no_coarse=False, combine="RAS"):
         lev = Level()
         lev.K = K
         lev.mesh = mesh
-        lev.maps = build_level(mesh, delta)
+        lev.maps = build_level(mesh, delta, pressure_gamma)
         lev.lu = [spl.splu(K[D][:, D].tocsc()) for D in lev.maps.dom]
         lev.owner = ras_owner(mesh, lev.maps) if combine == "RAS" else None
         H.levels.append(lev)

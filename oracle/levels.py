@@ -59,8 +59,14 @@ class LevelMaps:
     pass
 
 
-def build_level(mesh, delta=1):
-    """All index maps of one level, straight from the definitions."""
+def build_level(mesh, delta=1, pressure_gamma="constants"):
+    """All index maps of one level, straight from the definitions.
+
+    pressure_gamma="constants": the constant pressure mode of every element is an
+    interface dof, the linear modes are interior dofs of their part (saddle-point
+    extension); "all": every pressure mode is an interface dof (the linear modes
+    belong to no coarse column), so the extension into the interior is
+    velocity-only.  The coarse columns are the same either way."""
     m = LevelMaps()
     N = mesh.n_parts
     part_elems = [[] for _ in range(N)]
@@ -156,8 +162,9 @@ def build_level(mesh, delta=1):
         for v in closure:
             if S[v] == {i}:
                 idofs.update(int(x) for x in mesh.node_dof[v] if x >= 0)
-        for e in part_elems[i]:
-            idofs.update(int(x) for x in mesh.elem_pdof[e, 1:] if x >= 0)
+        if pressure_gamma == "constants":
+            for e in part_elems[i]:
+                idofs.update(int(x) for x in mesh.elem_pdof[e, 1:] if x >= 0)
         inter.append(np.array(sorted(idofs), dtype=np.int64))
     m.dom = dom
     m.inter = inter
@@ -166,8 +173,8 @@ def build_level(mesh, delta=1):
     for v in gamma:
         gdofs.update(int(x) for x in mesh.node_dof[v] if x >= 0)
     for e in range(len(mesh.elem_nodes)):
-        if mesh.elem_pdof[e, 0] >= 0:
-            gdofs.add(int(mesh.elem_pdof[e, 0]))
+        modes = mesh.elem_pdof[e] if pressure_gamma == "all" else mesh.elem_pdof[e, :1]
+        gdofs.update(int(x) for x in modes if x >= 0)
     m.gamma_dofs = np.array(sorted(gdofs), dtype=np.int64)
     return m
 

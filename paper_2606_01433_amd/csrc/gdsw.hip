@@ -238,6 +238,7 @@ struct Level {
   double* rcm = nullptr;
   double* ycm = nullptr;
   hipEvent_t lu_ev[2] = {nullptr, nullptr};   // around the batched LU of this level (timing)
+  int lu_variant = 0;            // LU autotuner choice: bit 0 = single steps, bit 1 = full-width panels
 };
 
 }  // namespace
@@ -379,6 +380,60 @@ int64_t checked_i32(int64_t v, const char* what) {
   return v;
 }
 
+// Tuning results shared by all contexts of the process, keyed by what decides
+// the choice: the value type, the level and the batch shape (count, total and
+// largest order of the local blocks).  With GDSW_TUNE_CACHE=<file> the table is
+// read from that file on first use and every new entry is appended to it, so
+// later processes skip the timing runs.
+struct TuneCache {
+  std::mutex mu;
+  bool loaded = false;
+  std::map<std::string, int> waves;
+};
+TuneCache& tune_cache() {
+  static TuneCache c;
+  return c;
+}
+std::string tune_key(const char* tag, int value_bytes, int level, int nparts, int64_t sum_n, int max_n) {
+  return std::string(tag) + " " + std::to_string(value_bytes) + " " + std::to_string(level) + " " +
+         std::to_string(nparts) + " " + std::to_string(sum_n) + " " + std::to_string(max_n);
+}
+bool tune_lookup(const std::string& key, int* w) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  if (!c.loaded) {
+    c.loaded = true;
+    if (const char* path = std::getenv("GDSW_TUNE_CACHE")) {
+      if (FILE* f = std::fopen(path, "r")) {
+        char tag[8];
+        int vb, lv, np, mx, wv;
+        long long sn;
+        while (std::fscanf(f, "%7s %d %d %d %lld %d %d", tag, &vb, &lv, &np, &sn, &mx, &wv) == 7) {
+          const std::string t(tag);
+          if ((t == "ls" && (wv == 2 || wv == 4 || wv == 8)) || (t == "lu" && wv >= 0 && wv <= 3))
+            c.waves[tune_key(tag, vb, lv, np, sn, mx)] = wv;
+        }
+        std::fclose(f);
+      }
+    }
+  }
+  auto it = c.waves.find(key);
+  if (it == c.waves.end()) return false;
+  *w = it->second;
+  return true;
+}
+void tune_store(const std::string& key, int w) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  c.waves[key] = w;
+  if (const char* path = std::getenv("GDSW_TUNE_CACHE")) {
+    if (FILE* f = std::fopen(path, "a")) {
+      std::fprintf(f, "%s %d\n", key.c_str(), w);
+      std::fclose(f);
+    }
+  }
+}
+
 template <typename T>
 void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
   const double th = now_ms();
@@ -445,6 +500,50 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
   b.wide = true;
   b.ut = A.alloc_n<T>((size_t)128 * L.sum_n);
   C->setup_scratch.push_back(b.ut);
+  if (C->opt.tune & 2) {
+    // LU autotuner: paired 64-column steps with rank-128 trailing updates or single steps with
+    // rank-64 updates, half-width or full-width register panels for FP64 panels of 769..2048
+    // rows; each variant factors the level's blocks once (re-extracted before each trial), the
+    // fastest is kept for this batch shape (process-wide, and in GDSW_TUNE_CACHE if set).
+    const std::string key = tune_key("lu", (int)sizeof(T), L.index, N, L.sum_n, L.max_n);
+    int variant = 0;
+    if (!tune_lookup(key, &variant)) {
+      hipEvent_t t0, t1;
+      GDSW_HIP(hipEventCreate(&t0));
+      GDSW_HIP(hipEventCreate(&t1));
+      float best = 1e30f;
+      const int nvar = sizeof(T) == 8 ? 4 : 2;
+      for (int v = 0; v < nvar; ++v) {
+        b.wide = (v & 1) == 0;
+        b.full_panels = (v >> 1) & 1;
+        GDSW_HIP(hipMemsetAsync(blocks, 0, (size_t)L.sum_n2 * sizeof(T), s));
+        extract_blocks<T>(L.K, N, L.max_n, L.order, L.dom_ptr, L.dom, L.blk_off, blocks, L.pad, s);
+        GDSW_HIP(hipEventRecord(t0, s));
+        lu_batched<T>(b, blocks, s);
+        GDSW_HIP(hipEventRecord(t1, s));
+        GDSW_HIP(hipEventSynchronize(t1));
+        float ms = 0;
+        GDSW_HIP(hipEventElapsedTime(&ms, t0, t1));
+        if (ms < best) {
+          best = ms;
+          variant = v;
+        }
+      }
+      (void)hipEventDestroy(t0);
+      (void)hipEventDestroy(t1);
+      tune_store(key, variant);
+      GDSW_HIP(hipMemsetAsync(blocks, 0, (size_t)L.sum_n2 * sizeof(T), s));
+      extract_blocks<T>(L.K, N, L.max_n, L.order, L.dom_ptr, L.dom, L.blk_off, blocks, L.pad, s);
+      GDSW_HIP(hipMemsetAsync(L.info, 0, N * sizeof(int), s));
+    }
+    b.wide = (variant & 1) == 0;
+    b.full_panels = (variant >> 1) & 1;
+    L.lu_variant = variant;
+  } else {
+    b.wide = (C->opt.lu_variant & 1) == 0;
+    b.full_panels = (C->opt.lu_variant >> 1) & 1;
+    L.lu_variant = C->opt.lu_variant & 3;
+  }
   GDSW_HIP(hipEventCreate(&L.lu_ev[0]));
   GDSW_HIP(hipEventCreate(&L.lu_ev[1]));
   GDSW_HIP(hipEventRecord(L.lu_ev[0], s));
@@ -687,7 +786,7 @@ Plan plan_levels(const gdsw_problem* p, const gdsw_options& o) {
   const int L = p->levels;
   for (int l = 1; l < L; ++l) {
     P.maps.emplace_back();
-    build_maps(P.meshes[l - 1], o.overlap, P.maps.back());
+    build_maps(P.meshes[l - 1], o.overlap, P.maps.back(), o.pressure_gamma == 0);
     P.schwarz = l;
     const bool last = (l == L - 1);
     if (last) {
@@ -783,7 +882,7 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
     const int e0 = mark(fs);
     factor_level<T>(C, L, fs);
     ev_factor.push_back({e0, mark(fs)});
-    host([&] { build_maps(meshes[l], C->opt.overlap, L.maps); });
+    host([&] { build_maps(meshes[l], C->opt.overlap, L.maps, C->opt.pressure_gamma == 0); });
     st.n[l] = L.n;
     st.parts[l] = L.nparts;
     st.sum_ni[l] = L.sum_n;
@@ -935,57 +1034,6 @@ void drain_events(gdsw_ctx* C) {
   C->ev_used = 0;
 }
 
-// Tuning results shared by all contexts of the process, keyed by what decides
-// the choice: the value type, the level and the batch shape (count, total and
-// largest order of the local blocks).  With GDSW_TUNE_CACHE=<file> the table is
-// read from that file on first use and every new entry is appended to it, so
-// later processes skip the timing runs.
-struct TuneCache {
-  std::mutex mu;
-  bool loaded = false;
-  std::map<std::string, int> waves;
-};
-TuneCache& tune_cache() {
-  static TuneCache c;
-  return c;
-}
-std::string tune_key(int value_bytes, int level, int nparts, int64_t sum_n, int max_n) {
-  return "ls " + std::to_string(value_bytes) + " " + std::to_string(level) + " " + std::to_string(nparts) + " " +
-         std::to_string(sum_n) + " " + std::to_string(max_n);
-}
-bool tune_lookup(const std::string& key, int* w) {
-  TuneCache& c = tune_cache();
-  std::lock_guard<std::mutex> lk(c.mu);
-  if (!c.loaded) {
-    c.loaded = true;
-    if (const char* path = std::getenv("GDSW_TUNE_CACHE")) {
-      if (FILE* f = std::fopen(path, "r")) {
-        char tag[8];
-        int vb, lv, np, mx, wv;
-        long long sn;
-        while (std::fscanf(f, "%7s %d %d %d %lld %d %d", tag, &vb, &lv, &np, &sn, &mx, &wv) == 7)
-          if (std::string(tag) == "ls" && (wv == 2 || wv == 4 || wv == 8)) c.waves[tune_key(vb, lv, np, sn, mx)] = wv;
-        std::fclose(f);
-      }
-    }
-  }
-  auto it = c.waves.find(key);
-  if (it == c.waves.end()) return false;
-  *w = it->second;
-  return true;
-}
-void tune_store(const std::string& key, int w) {
-  TuneCache& c = tune_cache();
-  std::lock_guard<std::mutex> lk(c.mu);
-  c.waves[key] = w;
-  if (const char* path = std::getenv("GDSW_TUNE_CACHE")) {
-    if (FILE* f = std::fopen(path, "a")) {
-      std::fprintf(f, "%s %d\n", key.c_str(), w);
-      std::fclose(f);
-    }
-  }
-}
-
 // Autotuner: for every level, time the local solves with 2, 4 and 8 wavefronts
 // per matrix (two runs each on a zero right-hand side) and keep the fastest;
 // a batch shape already tuned in this process (or in the cache file) reuses
@@ -997,7 +1045,7 @@ void tune_local_solves(gdsw_ctx* C, hipStream_t s) {
   GDSW_HIP(hipEventCreate(&e1));
   for (size_t l = 0; l < C->levels.size(); ++l) {
     Level& L = C->levels[l];
-    const std::string key = tune_key((int)sizeof(T), L.index, L.nparts, L.sum_n, L.max_n);
+    const std::string key = tune_key("ls", (int)sizeof(T), L.index, L.nparts, L.sum_n, L.max_n);
     int cached = 0;
     if (tune_lookup(key, &cached)) {
       L.ls_waves = cached;
@@ -1662,6 +1710,8 @@ void gdsw_default_options(gdsw_options* o) {
   o->graph = 0;
   o->tune = 0;
   o->ls_waves = 0;
+  o->lu_variant = 0;
+  o->pressure_gamma = 0;
 }
 
 const char* gdsw_last_error(void) { return gdsw::g_last_error.c_str(); }
@@ -1683,7 +1733,9 @@ int gdsw_setup(const gdsw_problem* prob, const gdsw_options* opt, void* stream, 
     if (C->opt.overlap < 0 || C->opt.restart < 1 || C->opt.restart > 250 || C->opt.max_it < 0 ||
         !(C->opt.tol >= 0.0) || (C->opt.combine != 0 && C->opt.combine != 1) ||
         (C->opt.precision != 0 && C->opt.precision != 1) ||
-        (C->opt.ls_waves != 0 && C->opt.ls_waves != 2 && C->opt.ls_waves != 4 && C->opt.ls_waves != 8))
+        (C->opt.ls_waves != 0 && C->opt.ls_waves != 2 && C->opt.ls_waves != 4 && C->opt.ls_waves != 8) ||
+        C->opt.tune < 0 || C->opt.tune > 3 || C->opt.lu_variant < 0 || C->opt.lu_variant > 3 ||
+        (C->opt.pressure_gamma != 0 && C->opt.pressure_gamma != 1))
       throw Error(GDSW_EINVAL, "invalid options");
     C->mixed = C->opt.precision == GDSW_MIXED;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1697,9 +1749,12 @@ int gdsw_setup(const gdsw_problem* prob, const gdsw_options* opt, void* stream, 
     GDSW_HIP(hipEventCreateWithFlags(&C->ev_join2, hipEventDisableTiming));
     if (C->mixed) gdsw::setup_impl<float>(C, prob, s);
     else gdsw::setup_impl<double>(C, prob, s);
-    for (size_t l = 0; l < C->levels.size() && l < 8; ++l) C->stats.ls_waves[l] = C->levels[l].ls_waves;
+    for (size_t l = 0; l < C->levels.size() && l < 8; ++l) {
+      C->stats.ls_waves[l] = C->levels[l].ls_waves;
+      C->stats.lu_variant[l] = C->levels[l].lu_variant;
+    }
     gdsw::create_solve_host_state(C);
-    if (C->opt.tune) {
+    if (C->opt.tune & 1) {
       if (C->mixed) gdsw::tune_local_solves<float>(C, s);
       else gdsw::tune_local_solves<double>(C, s);
     }

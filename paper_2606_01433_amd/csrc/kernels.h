@@ -41,6 +41,9 @@ struct LuBatch {
   // workgroup's registers are then factored by many workgroups (one launch per
   // column) instead of by one.
   void* tall_scratch = nullptr;
+  // FP64 panels of 769..2048 rows: 0 = two half-width (16-column) register panels, 1 = one
+  // full-width panel whenever it fits the registers (an autotuner choice; same pivots and results).
+  int full_panels = 0;
 };
 size_t lu_tall_scratch_bytes(int n, int value_bytes);
 // X = A^{-1} (column-major) of a single LU-factored FP64 matrix (b.count == 1, b.off

@@ -1326,7 +1326,7 @@ void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
                          b.info, k, b.pad);
       GDSW_LAUNCH_CHECK();
     }
-    launch_panel_rot<T>(b, A, k, std::min(rows, panel_reg_rows<T>()), !tall, s);
+    launch_panel_rot<T>(b, A, k, std::min(rows, panel_reg_rows<T>()), !tall && !b.full_panels, s);
   };
   // columns [k, k + 2NB): both sub-panels (the second brought up to date by the first), then the
   // interchanges of the step on the columns to their left

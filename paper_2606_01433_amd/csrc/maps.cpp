@@ -356,7 +356,7 @@ void build_domains(const LevelMesh& mesh, int delta, LevelMaps& m) {
   });
 }
 
-void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m) {
+void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m, bool linear_interior) {
   const int N = mesh.n_parts;
   const int nn = mesh.n_nodes;
   if ((int)m.dom_ptr.size() != N + 1) build_domains(mesh, delta, m);
@@ -500,8 +500,11 @@ void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m) {
         for (int q = 0; q < 4; ++q) {
           const int g = mesh.elem_pdof[4 * e + q];
           if (g < 0) continue;
-          if (q > 0) o.idofs.push_back(g);
-          else zs.push_back({m.dof_gcol[g], g});
+          if (q > 0) {
+            if (linear_interior) o.idofs.push_back(g);
+          } else {
+            zs.push_back({m.dof_gcol[g], g});
+          }
         }
       std::sort(o.idofs.begin(), o.idofs.end());
       for (size_t a = 0; a < o.idofs.size(); ++a) {   // interior dofs belong to one part only

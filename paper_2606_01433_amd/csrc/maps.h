@@ -81,7 +81,10 @@ std::string build_level1_mesh(int64_t n, int n_nodes, const int* node_dof, int n
 void build_domains(const LevelMesh& mesh, int delta, LevelMaps& m);
 
 // All maps of the level; reuses D_i (and S, owner) when build_domains ran on m.
-void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m);
+// linear_interior: the linear pressure modes (1..3) of a part's elements are
+// interior dofs of the part (a saddle-point extension); false: they are
+// interface dofs that no coarse column touches (a velocity-only extension).
+void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m, bool linear_interior = true);
 
 // Mesh of the next level: entities become nodes, parts become elements.
 std::string build_next_mesh(const LevelMesh& mesh, const LevelMaps& m, const int* parent,

@@ -28,7 +28,8 @@ class Problem(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("overlap", c_i32), ("combine", c_i32), ("precision", c_i32), ("restart", c_i32),
                 ("max_it", c_i32), ("tol", c_dbl), ("no_coarse", c_i32), ("panel", c_i32), ("profile", c_i32),
-                ("graph", c_i32), ("tune", c_i32), ("ls_waves", c_i32)]
+                ("graph", c_i32), ("tune", c_i32), ("ls_waves", c_i32), ("lu_variant", c_i32),
+                ("pressure_gamma", c_i32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -44,7 +45,7 @@ class Stats(ctypes.Structure):
                 ("ms_total", c_dbl), ("local_solve_launches", c_i64), ("ms_local_solve", c_dbl),
                 ("local_solve_bytes", c_dbl), ("ls_waves", c_i32 * 8), ("tl_factor", (c_dbl * 2) * 8),
                 ("tl_basis", (c_dbl * 2) * 8), ("tl_coarsest", c_dbl * 2), ("ms_lu", c_dbl * 8),
-                ("apply_bytes", c_dbl)]
+                ("apply_bytes", c_dbl), ("lu_variant", c_i32 * 8)]
 
 
 class MapsView(ctypes.Structure):
@@ -108,7 +109,8 @@ def _check(code):
 
 
 def make_options(overlap=1, combine="restricted", precision="fp64", restart=30, max_it=1000, tol=1e-8,
-                 no_coarse=False, panel=0, profile=False, graph=False, tune=False, ls_waves=0):
+                 no_coarse=False, panel=0, profile=False, graph=False, tune=False, ls_waves=0, lu_variant=0,
+                 pressure_gamma="constants"):
     o = Options()
     load_library().gdsw_default_options(ctypes.byref(o))
     o.overlap = overlap
@@ -121,8 +123,10 @@ def make_options(overlap=1, combine="restricted", precision="fp64", restart=30, 
     o.panel = panel
     o.profile = int(bool(profile))
     o.graph = int(bool(graph))
-    o.tune = int(bool(tune))
+    o.tune = {False: 0, True: 1, "solves": 1, "lu": 2, "all": 3}[tune] if not isinstance(tune, int) or isinstance(tune, bool) else int(tune)
     o.ls_waves = int(ls_waves)
+    o.lu_variant = int(lu_variant)
+    o.pressure_gamma = {"constants": 0, "all": 1}[pressure_gamma]
     return o
 
 

@@ -416,3 +416,53 @@ def test_apply_parity_two_node_layers(gd):
     assert err <= 1e-10 and emax <= 1e-10
     assert info["converged"]
     assert np.linalg.norm(P.K() @ x.cpu().numpy() - P.b) <= 1e-8 * np.linalg.norm(P.b) * 1.0001
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-3)])
+def test_lu_autotuner_variants_match_oracle(gd, precision, tol):
+    """tune = all also times the batched LU variants per level (rank-128 paired steps or rank-64 single
+    steps; FP64 half- or full-width panels); whatever is chosen, the apply matches the oracle, and a
+    second context of the same shape reuses the choice (bit-identical apply)."""
+    name = "die16_L4_uneven"
+    P = _problem(name)
+    r = random_vector(P.n, 17)
+    zo = oracle.apply(_orc(name), r)
+    _say("LU autotuner", precision)
+    with gd.Context(P, precision=precision, tune="all") as ctx:
+        z1 = ctx.apply(_dev(r)).cpu().numpy()
+        st = ctx.stats()
+    with gd.Context(P, precision=precision, tune="all") as ctx:
+        z2 = ctx.apply(_dev(r)).cpu().numpy()
+        st2 = ctx.stats()
+    _say("  variants", st["lu_variant"][:3], "waves", st["ls_waves"][:3])
+    assert all(0 <= v <= 3 for v in st["lu_variant"][:3])
+    assert list(st["lu_variant"][:3]) == list(st2["lu_variant"][:3])
+    assert np.array_equal(z1, z2)
+    err, emax = _errs(z1, zo)
+    assert err <= tol and emax <= tol
+    for v in range(4 if precision == "fp64" else 2):
+        with gd.Context(P, precision=precision, lu_variant=v) as ctx:
+            zv = ctx.apply(_dev(r)).cpu().numpy()
+            assert list(ctx.stats()["lu_variant"][:3]) == [v] * 3
+        err, emax = _errs(zv, zo)
+        _say("  variant", v, "rel err", err, "max err", emax)
+        assert err <= tol and emax <= tol
+
+
+@pytest.mark.parametrize("name", ["cube4_L2", "die16_L3"])
+def test_apply_parity_all_pressure_modes_on_the_interface(gd, name):
+    """pressure_gamma = all (velocity-only extension of the coarse basis): apply against the oracle built
+    with the same reading, and the solve converges."""
+    P = _problem(name)
+    H = cached(("orc-pg", name), lambda: oracle.setup(P, pressure_gamma="all"))
+    r = random_vector(P.n, 41)
+    _say("apply pressure_gamma=all", name)
+    tol = 1e-10 if name == "cube4_L2" else 1e-8
+    with gd.Context(P, pressure_gamma="all", tol=tol) as ctx:
+        z = ctx.apply(_dev(r)).cpu().numpy()
+        x, info = ctx.solve(_dev(P.b))
+    zo = oracle.apply(H, r)
+    err, emax = _errs(z, zo)
+    _say("  rel err", err, "max err", emax, "iterations", info["iterations"])
+    assert err <= 1e-10 and emax <= 1e-10
+    assert info["converged"]

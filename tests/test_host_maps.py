@@ -111,3 +111,15 @@ def test_invalid_inputs_are_rejected(cube4):
     with pytest.raises(gdsw.GdswError, match="EINVAL"):
         gdsw.plan_maps(dup)
     assert gdsw.footprint_bytes(bad) == 0
+
+
+def test_maps_all_pressure_modes_on_the_interface():
+    """pressure_gamma = all: the library's host maps equal the oracle's for that reading."""
+    from harness import die_problem
+    P = die_problem(16, 8, 8, seed=0, levels=3)
+    H = oracle.setup(P, pressure_gamma="all")
+    maps, _ = gdsw.plan_maps(P, pressure_gamma="all")
+    for k, lev in enumerate(H.levels):
+        assert np.array_equal(maps[k]["inter"], np.concatenate([np.asarray(i, np.int64) for i in lev.maps.inter]))
+        assert np.array_equal(maps[k]["dom"], np.concatenate(lev.maps.dom))
+        assert np.array_equal(maps[k]["col_entity"], lev.maps.col_entity)

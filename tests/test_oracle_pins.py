@@ -159,3 +159,35 @@ def test_restricted_default_converges_where_additive_stalls():
     P2 = cached(("die16", 2), lambda: die_problem(16, 8, 8, seed=0, levels=2))
     add2 = _fgmres(P2, oracle.setup(P2, combine="AS"), 200)
     assert add2["converged"], add2
+
+
+def test_all_pressure_modes_on_the_interface_reading():
+    """The alternative reading of the P1disc coarse space: every pressure mode on the interface.  The
+    coarse columns are unchanged, the interior sets hold velocity dofs only (the 4^3 cube: 27 nodes x 3
+    = 81 per part instead of 105), the linear pressure modes get no coarse value (Phi = 0 there), the
+    basis is still a partition of unity on the interface, and it is discrete-harmonic in the velocity
+    interior: (K Phi)_I = 0 on the interior (velocity) rows."""
+    P = cached("cube4", unit_cube_problem)
+    H = oracle.setup(P, pressure_gamma="all")
+    H0 = cached("cube4_h", lambda: oracle.setup(P))
+    m, m0 = H.levels[0].maps, H0.levels[0].maps
+    assert m.n_coarse == m0.n_coarse == 65
+    assert [len(i) for i in m.inter] == [81] * 8
+    Phi = H.levels[0].Phi.toarray()
+    ep = P.elem_pdof.reshape(-1, 4)
+    lin = ep[:, 1:][ep[:, 1:] >= 0]
+    assert np.all(Phi[lin] == 0.0)
+    vel_cols = [c for c in range(m.n_coarse) if m.col_dir[c] < 3]
+    G = np.asarray(m.gamma_nodes)
+    nd = P.node_dof.reshape(-1, 3)
+    for d in range(3):
+        cols = [c for c in vel_cols if m.col_dir[c] == d]
+        rows = nd[G, d][nd[G, d] >= 0]
+        assert np.allclose(Phi[np.ix_(rows, cols)].sum(axis=1), 1.0)
+    KPhi = P.K() @ Phi
+    I = np.concatenate(m.inter)
+    assert np.abs(KPhi[I]).max() <= 1e-11 * np.abs(KPhi).max()
+    # and it converges as a preconditioner
+    K = P.K()
+    x, info = oracle.fgmres(lambda v: K @ v, lambda v: oracle.apply(H, v), P.b, tol=1e-10)
+    assert info["converged"] and np.abs(x - P.x_exact).max() <= 1e-7
