@@ -87,7 +87,9 @@ __global__ __launch_bounds__(256) void k_extract_interior(CsrDev K, int nparts, 
           const int gc = dof_gcol[h];
           const int p = gc >= 0 ? lower_bound_i32(pc, m, gc) : m;
           if (p < m && pc[p] == gc) lc = p;
-          else *bad = 1;                  // K couples an interior dof outside its part's closure
+          else if (gc >= 0 || dof_ipart[h] >= 0) *bad = 1;   // K couples an interior dof outside its
+                                                             // part's closure (an interface dof without
+                                                             // a coarse column has Phi = 0: no term)
         }
       }
       const int cnt = (int)min((int64_t)64, e_end - e0);
@@ -149,7 +151,7 @@ __global__ __launch_bounds__(256) void k_galerkin_w(CsrDev K, int nparts, int64_
           const int gc = dof_gcol[h];
           const int p = gc >= 0 ? lower_bound_i32(pc, m, gc) : m;
           if (p < m && pc[p] == gc) lc = p;
-          else *bad = 1;            // K couples an interior dof outside its part's closure
+          else if (gc >= 0 || dof_ipart[h] >= 0) *bad = 1;   // as in k_extract_interior
         }
       }
       const int cnt = (int)min((int64_t)64, e_end - e0);
