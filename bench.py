@@ -6,7 +6,7 @@ a relative residual of 1e-8) + gdsw_destroy, on the batching workload: a
 seeded 96x48x48 die-like voxel channel (Q2-P1disc, Carreau nu0 = 1, lambda =
 10, n = 0.4; level-1 parts of 2 or 3 voxels per axis, about 21k of them; four
 levels), FP32 local factors and bases, FP64 Krylov / residuals / coarsest
-solve, restricted combination, autotuned local solves.  The matrix and the
+solve, restricted combination, autotuned local solves and LU variants.  The matrix and the
 right-hand side are resident in HBM before the timed region.
 
 Further objects on the same JSON line: the level-1 local-solve roofline, the
@@ -51,7 +51,8 @@ WORKLOADS = {
 def local_solve_source_hash():
     import hashlib
     src = open(os.path.join(ROOT, "paper_2606_01433_amd", "csrc", "apply.hip")).read()
-    a, b = src.index("// Local solves w_i"), src.index("__global__ void k_scatter_sum")
+    a = src.index("// Local solves w_i")
+    b = src.index("// ---------------------------------------------------------------------------\n// Local solves of KC")
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
@@ -485,7 +486,7 @@ def main():
     precision = args.precision or ("mixed" if name == "die96x48x48" else "fp64")
     P = make_problem(name, args.seed)
     run = Runner(P, stream)
-    tune = name == "die96x48x48"
+    tune = "all" if name == "die96x48x48" else False
     say("headline steps")
     T, x, infos, stats = run.timed_steps(args.steps, args.warmup, precision=precision, profile=True, tune=tune)
     st0 = stats[0]
@@ -503,7 +504,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if precision == "fp64" else "f32 local factors / f64 Krylov",
         "data": "synthetic (seeded die-like voxel channel, Carreau viscosity at a seeded linearization point)",
-        "config": {"workload": describe(name, precision) + (", autotuned local solves" if tune else ""),
+        "config": {"workload": describe(name, precision) + (", autotuned local solves and LU variants" if tune else ""),
                    "n_dofs": int(P.n), "nnz": int(len(P.col)), "parts": st0["parts"][:st0["levels"]],
                    "level_dofs": st0["n"][:st0["levels"]], "iterations": infos[-1]["iterations"],
                    "local_solve_waves_per_matrix": st0["ls_waves"][:st0["levels"] - 1],
@@ -513,7 +514,8 @@ def main():
                    "ms_setup_phases": {"host_maps": st0["ms_maps"], "host_prep": st0["ms_extract"],
                                        "factor": st0["ms_factor"], "basis_galerkin": st0["ms_basis"],
                                        "coarsest": st0["ms_coarse"]},
-                   "factor_bytes": st0["factor_bytes"][:st0["levels"] - 1]},
+                   "factor_bytes": st0["factor_bytes"][:st0["levels"] - 1],
+                   "lu_variant_per_level": st0["lu_variant"][:st0["levels"] - 1]},
         "roofline": local_solve_roofline(stats, name, precision, args.seed),
         "factor": lu_rate(stats, precision),
     }

@@ -13,29 +13,40 @@ constexpr int DOT_BLOCK_ROWS = 512;
 constexpr int DOT_MAXC = 32;
 
 // One wavefront per row; lane l sums entries l, l + 64, ... in that order, then
-// a fixed butterfly.  Rows of up to 256 entries (the common case) issue all
-// their index, value and gathered loads before the first FMA.
+// a fixed butterfly.  Rows of up to 512 entries (every row of a Q2-P1disc
+// operator) issue all their index, value and gathered loads before the first FMA.
+// Up to S entries per lane with every load issued before the first FMA.
+template <int S>
+__device__ __forceinline__ double spmv_lane(const CsrDev& K, const double* __restrict__ x, int64_t e0, int64_t e1) {
+  int c[S];
+  double v[S];
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    const int64_t e = e0 + 64 * j;
+    c[j] = (e < e1) ? K.col[e] : 0;
+    v[j] = (e < e1) ? K.val[e] : 0.0;
+  }
+  double xv[S];
+#pragma unroll
+  for (int j = 0; j < S; ++j) xv[j] = (e0 + 64 * j < e1) ? x[c[j]] : 0.0;
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < S; ++j)
+    if (e0 + 64 * j < e1) s += v[j] * xv[j];
+  return s;
+}
+
 __global__ __launch_bounds__(256) void k_spmv(CsrDev K, const double* __restrict__ x, double* __restrict__ y) {
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= K.n) return;
   const int lane = threadIdx.x & 63;
   const int64_t e0 = K.rowptr[row] + lane, e1 = K.rowptr[row + 1];
+  const int64_t len = e1 - K.rowptr[row];
   double s = 0.0;
-  if (e1 - K.rowptr[row] <= 4 * 64) {
-    int c[4];
-    double v[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t e = e0 + 64 * j;
-      c[j] = (e < e1) ? K.col[e] : 0;
-      v[j] = (e < e1) ? K.val[e] : 0.0;
-    }
-    double xv[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) xv[j] = (e0 + 64 * j < e1) ? x[c[j]] : 0.0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (e0 + 64 * j < e1) s += v[j] * xv[j];
+  if (len <= 4 * 64) {
+    s = spmv_lane<4>(K, x, e0, e1);
+  } else if (len <= 8 * 64) {               // vertex rows of Q2 meshes (up to about 410 entries)
+    s = spmv_lane<8>(K, x, e0, e1);
   } else {
     for (int64_t e = e0; e < e1; e += 64) s += K.val[e] * x[K.col[e]];
   }
