@@ -139,18 +139,31 @@ def shear_rate(grad):
     return np.sqrt(2.0 * np.sum(D * D, axis=(-1, -2)))
 
 
-def linearization_field(mesh, rng, lam, target=10.0):
-    """Seeded smooth velocity u_k = sum_q a_q sin(pi k_q . x + phi_q), scaled so max lam*gamma_dot = target."""
-    x = mesh.node_xyz
-    u = np.zeros((mesh.n_nodes, 3))
+def _field_terms(rng):
+    terms = []
     for _ in range(4):
         a = rng.standard_normal(3)
         k = rng.integers(1, 4, size=3)
         ph = rng.uniform(0.0, 2.0 * np.pi)
+        terms.append((a, k, ph))
+    return terms
+
+
+def _field_at(terms, x):
+    u = np.zeros((x.shape[0], 3))
+    for a, k, ph in terms:
         u += a[None, :] * np.sin(np.pi * (x @ k) + ph)[:, None]
-    gd = shear_rate(gauss_gradients(mesh, u))
-    u *= target / (lam * gd.max())
     return u
+
+
+def linearization_field(mesh, rng, lam, target=10.0, scale_mesh=None):
+    """Seeded smooth velocity u_k = sum_q a_q sin(pi k_q . x + phi_q), scaled so max lam*gamma_dot = target
+    (the maximum taken over the Gauss points of scale_mesh, default mesh: a refined mesh given its
+    coarse mesh here carries the same function)."""
+    terms = _field_terms(rng)
+    ref = mesh if scale_mesh is None else scale_mesh
+    gd = shear_rate(gauss_gradients(ref, _field_at(terms, ref.node_xyz)))
+    return _field_at(terms, mesh.node_xyz) * (target / (lam * gd.max()))
 
 
 def carreau_slope(gamma_dot, nu0, lam, n_exp):
@@ -163,7 +176,7 @@ def symmetric_gradients(grad):
 
 
 def die_problem(nx=32, ny=16, nz=16, seed=0, nu0=1.0, lam=1.0, n_exp=0.5, levels=3,
-                frac3=0.0, masked=0.20, inflow_speed=1.0, linearization="picard"):
+                frac3=0.0, masked=0.20, inflow_speed=1.0, linearization="picard", refine=1):
     """Seeded die-like voxel channel with Carreau viscosity linearized at a smooth field.
 
     Inflow: two rectangular windows on x = 0 with a parabolic x-velocity;
@@ -174,10 +187,22 @@ def die_problem(nx=32, ny=16, nz=16, seed=0, nu0=1.0, lam=1.0, n_exp=0.5, levels
     derivative of nu, and the right-hand side is the one of the Newton update
     J(u_k) u_{k+1} = (J(u_k) - A(u_k)) u_k + f, i.e. the Newton term applied to
     u_k (with the same Dirichlet data).
+    refine = 2: the same die with every voxel split into 2x2x2 (h halved; same
+    obstacles, inflow windows and linearization field u_k(x)); its parts are
+    2-voxel segments of the refined grid.  The pair (refine 1, refine 2) is a
+    nested hierarchy for geometric multigrid (prolongation()).
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     active = die_voxels(nx, ny, nz, rng, target=masked)
     h = 1.0 / ny
+    coarse_mesh = None
+    if refine == 2:
+        coarse_mesh = VoxelMesh(active, h)
+        active = active.repeat(2, 0).repeat(2, 1).repeat(2, 2)
+        h = 0.5 * h
+        nx, ny, nz = 2 * nx, 2 * ny, 2 * nz
+    elif refine != 1:
+        raise ValueError(refine)
     mesh = VoxelMesh(active, h)
     # boundary classification
     dir_node = np.zeros(mesh.n_nodes, dtype=bool)
@@ -188,13 +213,15 @@ def die_problem(nx=32, ny=16, nz=16, seed=0, nu0=1.0, lam=1.0, n_exp=0.5, levels
         dir_node[mesh.face_nodes(e, fc)] = True
     # two inflow windows on x = 0 (voxel-aligned), one in each half of y
     wins = []
+    cny, cnz = ny // refine, nz // refine
     for half in range(2):
-        wy = int(rng.integers(max(1, ny // 5), max(2, ny // 3) + 1))
-        wz = int(rng.integers(max(1, nz // 5), max(2, nz // 3) + 1))
-        ylo, yhi = (1, ny // 2 - wy) if half == 0 else (ny // 2, ny - 1 - wy)
+        wy = int(rng.integers(max(1, cny // 5), max(2, cny // 3) + 1))
+        wz = int(rng.integers(max(1, cnz // 5), max(2, cnz // 3) + 1))
+        ylo, yhi = (1, cny // 2 - wy) if half == 0 else (cny // 2, cny - 1 - wy)
         y0 = int(rng.integers(ylo, max(ylo, yhi) + 1))
-        z0 = int(rng.integers(1, max(1, nz - 1 - wz) + 1))
-        wins.append((y0 * h, (y0 + wy) * h, z0 * h, (z0 + wz) * h))
+        z0 = int(rng.integers(1, max(1, cnz - 1 - wz) + 1))
+        hc = h * refine
+        wins.append((y0 * hc, (y0 + wy) * hc, z0 * hc, (z0 + wz) * hc))
     g = np.zeros((mesh.n_nodes, 3))
     xyz = mesh.node_xyz
     on_in = dir_node & (mesh.node_lat[:, 0] == 0)
@@ -208,7 +235,7 @@ def die_problem(nx=32, ny=16, nz=16, seed=0, nu0=1.0, lam=1.0, n_exp=0.5, levels
     sy = axis_segments(ny, seg_rng, frac3)
     sz = axis_segments(nz, seg_rng, frac3)
     elem_part, n_parts, part_parent = part_hierarchy(mesh, sx, sy, sz, levels)
-    uk = linearization_field(mesh, rng, lam)
+    uk = linearization_field(mesh, rng, lam, scale_mesh=coarse_mesh)
     grad = gauss_gradients(mesh, uk)
     gd = shear_rate(grad)                                     # (E, 27)
     nu_q = carreau(gd, nu0, lam, n_exp)
@@ -221,11 +248,12 @@ def die_problem(nx=32, ny=16, nz=16, seed=0, nu0=1.0, lam=1.0, n_exp=0.5, levels
         rhs_extra[3 * mesh.n_nodes:] = 0.0         # N holds the divergence blocks too: velocity rows only
     elif linearization != "picard":
         raise ValueError(linearization)
-    tag = "" if linearization == "picard" else "_newton"
+    tag = ("" if linearization == "picard" else "_newton") + ("" if refine == 1 else "_refined")
     return _build(f"die{nx}x{ny}x{nz}_s{seed}_L{levels}{tag}", mesh, nu_q, "sym", (0.0, 0.0, 0.0), dir_node, g,
                   [], [], elem_part, n_parts, part_parent, levels, newton=newton, rhs_extra=rhs_extra,
                   meta=dict(kind="die", nx=nx, ny=ny, nz=nz, h=h, seed=seed, nu0=nu0, lam=lam, n_exp=n_exp,
-                            linearization=linearization,
+                            linearization=linearization, refine=refine,
+                            elem_ijk=mesh.elem_ijk.copy(),
                             masked=float(1.0 - active.mean()), windows=wins, frac3=frac3,
                             nu_min=float(nu_q.min()), nu_max=float(nu_q.max())))
 
@@ -233,3 +261,86 @@ def die_problem(nx=32, ny=16, nz=16, seed=0, nu0=1.0, lam=1.0, n_exp=0.5, levels
 def random_vector(n, seed):
     """Seeded N(0, 1) vector (PCG64)."""
     return np.random.Generator(np.random.PCG64(seed)).standard_normal(n)
+
+
+def prolongation_full(coarse, fine):
+    """Prolongation of the nested Q2 / P1disc spaces from a die to its refinement (die_problem with
+    refine = 2 of the same arguments), over all dofs before Dirichlet elimination: velocity 3 node + d,
+    then pressure 4 elem + m (fine rows, coarse columns).  P u_c is the coarse finite element function
+    evaluated on the fine dofs.  Velocity: every fine node takes the Q2 interpolant of a coarse element
+    that contains it (the values agree on shared faces); pressure: every fine element takes the linear
+    function of its parent element (constant mode c0 + (o . c) / 2 with o = +-1 the child's offset
+    per axis, linear modes halved)."""
+    import scipy.sparse as sp
+    from .q2 import lagrange_1d
+    hc, hf = coarse.meta["h"], fine.meta["h"]
+    assert abs(hf - 0.5 * hc) < 1e-15 * hc
+    cijk = coarse.meta["elem_ijk"]
+    fijk = fine.meta["elem_ijk"]
+    grid = -np.ones((coarse.meta["nx"], coarse.meta["ny"], coarse.meta["nz"]), dtype=np.int64)
+    grid[cijk[:, 0], cijk[:, 1], cijk[:, 2]] = np.arange(cijk.shape[0])
+    cen = coarse.elem_node.reshape(-1, 27).astype(np.int64)
+    nvf, nvc = 3 * fine.n_nodes, 3 * coarse.n_nodes
+    # velocity: a coarse element holding each fine node
+    xf = fine.node_xyz / hc                                  # in coarse voxel units
+    base = np.floor(xf + 1e-12).astype(np.int64)
+    shape = np.array(grid.shape)
+    elem = -np.ones(xf.shape[0], dtype=np.int64)
+    cell = np.zeros_like(base)
+    for ox in (0, -1):
+        for oy in (0, -1):
+            for oz in (0, -1):
+                c = base + np.array([ox, oy, oz])
+                ok = (elem < 0) & np.all((c >= 0) & (c < shape), axis=1) & np.all(xf - c <= 1.0 + 1e-12, axis=1)
+                e = np.full(xf.shape[0], -1, dtype=np.int64)
+                e[ok] = grid[c[ok, 0], c[ok, 1], c[ok, 2]]
+                take = ok & (e >= 0)
+                elem[take] = e[take]
+                cell[take] = c[take]
+    assert np.all(elem >= 0), "a fine node lies in no active coarse element"
+    xi = 2.0 * (xf - cell) - 1.0
+    phi = [lagrange_1d(xi[:, d])[0] for d in range(3)]
+    k = np.arange(27)
+    w = phi[0][:, k % 3] * phi[1][:, (k // 3) % 3] * phi[2][:, k // 9]      # (fine nodes, 27)
+    cn = cen[elem]                                                          # (fine nodes, 27)
+    keep = np.abs(w) > 1e-14
+    vi, ai = np.nonzero(keep)
+    rows = [3 * vi + d for d in range(3)]
+    cols = [3 * cn[vi, ai] + d for d in range(3)]
+    vals = [w[vi, ai]] * 3
+    # pressure
+    par = grid[fijk[:, 0] // 2, fijk[:, 1] // 2, fijk[:, 2] // 2]
+    assert np.all(par >= 0)
+    o = 2 * (fijk % 2) - 1
+    ef = np.arange(fijk.shape[0])
+    rows.append(nvf + 4 * ef)
+    cols.append(nvc + 4 * par)
+    vals.append(np.ones(ef.shape[0]))
+    for m in range(3):
+        rows.append(nvf + 4 * ef)
+        cols.append(nvc + 4 * par + m + 1)
+        vals.append(0.5 * o[:, m].astype(np.float64))
+        rows.append(nvf + 4 * ef + m + 1)
+        cols.append(nvc + 4 * par + m + 1)
+        vals.append(np.full(ef.shape[0], 0.5))
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    v = np.concatenate(vals)
+    return sp.csr_matrix((v, (r, c)), shape=(nvf + 4 * fine.n_elem, nvc + 4 * coarse.n_elem))
+
+
+def free_dof_index(P):
+    """Full dof id (velocity 3 node + d, then pressure 4 elem + m) of every free dof, in free-dof order."""
+    full = np.concatenate([np.asarray(P.node_dof, np.int64), np.asarray(P.elem_pdof, np.int64)])
+    idx = np.full(P.n, -1, dtype=np.int64)
+    ids = np.nonzero(full >= 0)[0]
+    idx[full[ids]] = ids
+    return idx
+
+
+def prolongation(coarse, fine):
+    """The prolongation between the free dofs (fine free x coarse free): the rows and columns of
+    prolongation_full at the free dofs.  Coarse Dirichlet dofs contribute nothing (a coarse correction
+    vanishes there); fine Dirichlet dofs have no row."""
+    Pf = prolongation_full(coarse, fine)
+    return Pf[free_dof_index(fine)][:, free_dof_index(coarse)].tocsr()

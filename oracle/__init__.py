@@ -15,3 +15,4 @@ invariants, special cases or brute force; see the docstrings.
 from .levels import Mesh, LevelMaps, level1_mesh, build_level, next_mesh  # noqa: F401
 from .gdsw import Hierarchy, setup, apply, solve_direct  # noqa: F401
 from .fgmres import fgmres  # noqa: F401
+from .mg import two_grid_setup, two_grid_cycle, two_grid_solve  # noqa: F401

@@ -124,3 +124,38 @@ def test_carreau_slope_closed_form():
     h = 1e-6
     fd = (carreau(g + h, 2.0, 3.0, 0.4) - carreau(g - h, 2.0, 3.0, 0.4)) / (2 * h) / g
     assert np.allclose(carreau_slope(g, 2.0, 3.0, 0.4), fd, rtol=1e-7)
+
+
+def _quadratic_fields(xyz):
+    import numpy as np
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    return np.stack([x * x - 3 * y * z + 2 * x, x * y + z * z - 1.0, 4 * x * z - y * y + y], axis=1)
+
+
+def test_prolongation_reproduces_quadratic_velocity_and_linear_pressure():
+    """Nested Q2 / P1disc spaces: P u_c equals the fine interpolant of any coarse Q2 velocity and P1disc
+    pressure exactly; here a global quadratic velocity and linear pressure (both in the coarse space),
+    sampled on the coarse dofs, must come out as the same functions sampled on the fine dofs.  The free-dof
+    prolongation is the sub-block of the full one at the free dofs."""
+    import numpy as np
+    from harness import die_problem
+    from harness.problems import prolongation_full, prolongation, free_dof_index
+    Pc = die_problem(8, 4, 4, seed=0, levels=2)
+    Pf = die_problem(8, 4, 4, seed=0, levels=2, refine=2)
+    assert abs(Pf.meta["h"] - Pc.meta["h"] / 2) < 1e-15
+    F = prolongation_full(Pc, Pf)
+
+    def sample(P):
+        u = _quadratic_fields(P.node_xyz)
+        h = P.meta["h"]
+        cen = (P.meta["elem_ijk"] + 0.5) * h
+        gp = np.array([1.5, -2.0, 0.75])
+        modes = np.stack([cen @ gp + 0.25] + [np.full(cen.shape[0], 0.5 * h * gp[m]) for m in range(3)], axis=1)
+        return np.concatenate([u.ravel(), modes.ravel()])
+
+    xc, xf = sample(Pc), sample(Pf)
+    assert np.abs(F @ xc - xf).max() <= 1e-12 * np.abs(xf).max()
+    P = prolongation(Pc, Pf)
+    assert P.shape == (Pf.n, Pc.n)
+    sub = F[free_dof_index(Pf)][:, free_dof_index(Pc)]
+    assert np.abs((P - sub)).max() == 0.0
