@@ -276,6 +276,38 @@ int gdsw_apply_multi(gdsw_ctx* ctx, int32_t k, const double* R, int64_t ldr, dou
 int gdsw_solve_multi(gdsw_ctx* ctx, int32_t k, const double* B, int64_t ldb, double* X, int64_t ldx, void* stream,
                      gdsw_solve_info* info);
 
+/* ---- two-grid geometric multigrid with the GDSW solver as coarse solver ----
+ * Section 3's second role: the linearized system of a refined mesh is solved
+ * by geometric multigrid whose coarse problem (one uniform coarsening) is
+ * solved by FGMRES preconditioned by the multilevel GDSW method, only to a
+ * relative reduction of 1e-1.  One cycle z = M r (z starts at 0):
+ *   nu_pre times  z <- z + omega S (r - K_f z)
+ *   then          z <- z + P x_c, x_c = FGMRES(K_c, B, P^T (r - K_f z)) to the coarse context's tol
+ *   nu_post times z <- z + omega S (r - K_f z)
+ * fine   : a context on the fine problem; its operator is K_f, its apply is the
+ *          smoother S (set it up with no_coarse = 1 and levels = 2 for a damped
+ *          one-level restricted Schwarz smoother), its options (restart, tol,
+ *          max_it) govern gdsw_mg_solve.
+ * coarse : a context on the coarse problem (its tol is the coarse reduction).
+ * P      : n_fine x n_coarse prolongation, PT = P^T (n_coarse x n_fine), both
+ *          DEVICE CSR (int64 row pointers, int32 columns, FP64 values), copied.
+ * Both contexts must outlive the multigrid object and must not be used for
+ * anything else while one of its calls runs.  Returns GDSW_EINVAL when sizes
+ * do not match the contexts. */
+typedef struct gdsw_mg gdsw_mg;   /* opaque */
+int gdsw_mg_create(gdsw_ctx* fine, gdsw_ctx* coarse, int64_t n_fine, int64_t n_coarse, const int64_t* p_rowptr,
+                   const int32_t* p_col, const double* p_val, const int64_t* pt_rowptr, const int32_t* pt_col,
+                   const double* pt_val, int32_t nu_pre, int32_t nu_post, double omega, void* stream,
+                   gdsw_mg** out);
+/* z = M r, one cycle.  r, z: DEVICE FP64 of length n_fine (no aliasing). */
+int gdsw_mg_apply(gdsw_mg* mg, const double* r, double* z, void* stream);
+/* FGMRES on K_f x = b (the fine context's restart, tol and max_it) with the
+ * cycle as preconditioner; same return codes and info as gdsw_solve. */
+int gdsw_mg_solve(gdsw_mg* mg, const double* b, double* x, void* stream, gdsw_solve_info* info);
+/* Cycles run and coarse FGMRES iterations summed over them since creation. */
+int gdsw_mg_counts(gdsw_mg* mg, int64_t* cycles, int64_t* coarse_iterations);
+void gdsw_mg_destroy(gdsw_mg* mg);
+
 /* y = K x with the level-1 operator (CSR SpMV).  x, y: DEVICE FP64, length n. */
 int gdsw_spmv(gdsw_ctx* ctx, const double* x, double* y, void* stream);
 

@@ -7,6 +7,7 @@
 #include <array>
 #include <atomic>
 #include <chrono>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -1293,9 +1294,12 @@ void column_apply(gdsw_ctx* C, int j, const double* v, double* z, hipStream_t s)
 }
 
 // FGMRES(m) on the workspace ws.  use_graph: applies replay captured graphs
-// (graph = 1 contexts, gdsw_solve only).
+// (graph = 1 contexts, gdsw_solve only).  precond: another preconditioner in
+// place of the context's apply (the multigrid cycle).
+using Precond = std::function<void(const double*, double*, hipStream_t)>;
+
 int solve_impl(gdsw_ctx* C, const double* b, double* x, hipStream_t caller, gdsw_solve_info* info,
-               const KrylovWs& ws, bool use_graph) {
+               const KrylovWs& ws, bool use_graph, const Precond* precond = nullptr) {
   const double t0 = now_ms();
   hipStream_t s = caller;
   if (use_graph) {               // captured work needs a stream of its own (not the legacy default stream)
@@ -1390,7 +1394,8 @@ int solve_impl(gdsw_ctx* C, const double* b, double* x, hipStream_t caller, gdsw
       }
       double* vj = V + (int64_t)j * n;
       double* zj = Z + (int64_t)j * n;
-      column_apply(C, j, vj, zj, s);
+      if (precond) (*precond)(vj, zj, s);
+      else column_apply(C, j, vj, zj, s);
       tick(ms_apply, last);
       spmv(K, zj, w, s);
       tick(ms_spmv, last);
@@ -1646,6 +1651,85 @@ int fail(const Error& e) {
   return e.code;
 }
 
+}  // namespace
+}  // namespace gdsw
+
+// Two-grid geometric multigrid whose coarse problem is solved by FGMRES
+// preconditioned by a GDSW hierarchy (section 3, second role): the fine
+// operator and the smoother come from a one-level context on the fine problem,
+// the coarse solver from a context on the coarse problem (its tol is the
+// coarse reduction), P / P^T are the grid transfers.
+struct gdsw_mg {
+  gdsw_ctx* fine = nullptr;
+  gdsw_ctx* coarse = nullptr;
+  gdsw::Arena arena;
+  gdsw::CsrDev P, PT;
+  double *d = nullptr, *t = nullptr, *dc = nullptr, *ec = nullptr;
+  int nu_pre = 2, nu_post = 2;
+  double omega = 1.0;
+  int64_t cycles = 0, coarse_its = 0;
+};
+
+namespace gdsw {
+namespace {
+
+CsrDev copy_csr(Arena& A, int64_t rows, const int64_t* rowptr, const int* col, const double* val, hipStream_t s) {
+  int64_t nnz = 0;
+  GDSW_HIP(hipMemcpyAsync(&nnz, rowptr + rows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  GDSW_HIP(hipStreamSynchronize(s));
+  if (nnz < 0) throw Error(GDSW_EINVAL, "negative nonzero count");
+  CsrDev M;
+  M.n = rows;
+  M.nnz = nnz;
+  int64_t* rp = A.alloc_n<int64_t>(rows + 1);
+  int* cl = A.alloc_n<int>((size_t)std::max<int64_t>(nnz, 1));
+  double* vl = A.alloc_n<double>((size_t)std::max<int64_t>(nnz, 1));
+  GDSW_HIP(hipMemcpyAsync(rp, rowptr, (rows + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+  if (nnz) {
+    GDSW_HIP(hipMemcpyAsync(cl, col, nnz * sizeof(int), hipMemcpyDeviceToDevice, s));
+    GDSW_HIP(hipMemcpyAsync(vl, val, nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  M.rowptr = rp;
+  M.col = cl;
+  M.val = vl;
+  return M;
+}
+
+// One cycle z = M r (z starts at 0): pre-smoothing, coarse-grid correction by the inexact
+// coarse solve, post-smoothing; every step in the oracle's order.
+void mg_cycle(gdsw_mg* M, const double* r, double* z, hipStream_t s) {
+  const CsrDev& Kf = M->fine->levels[0].K;
+  const int64_t n = Kf.n;
+  auto smooth = [&](bool first) {
+    if (first) {
+      apply_any(M->fine, r, M->t, s);                 // S (r - K 0)
+      axpby(n, M->omega, M->t, 0.0, z, s);
+    } else {
+      spmv(Kf, z, M->d, s);
+      residual_from(n, r, M->d, s);
+      apply_any(M->fine, M->d, M->t, s);
+      axpby(n, M->omega, M->t, 1.0, z, s);
+    }
+  };
+  for (int k = 0; k < M->nu_pre; ++k) smooth(k == 0);
+  const double* d = r;
+  if (M->nu_pre > 0) {
+    spmv(Kf, z, M->d, s);
+    residual_from(n, r, M->d, s);
+    d = M->d;
+  }
+  spmv(M->PT, d, M->dc, s);
+  gdsw_solve_info inf;
+  const KrylovWs ws = context_workspace(M->coarse);
+  solve_impl(M->coarse, M->dc, M->ec, s, &inf, ws, false);
+  M->coarse_its += inf.iterations;
+  M->cycles++;
+  spmv(M->P, M->ec, M->t, s);
+  if (M->nu_pre > 0) axpby(n, 1.0, M->t, 1.0, z, s);
+  else axpby(n, 1.0, M->t, 0.0, z, s);
+  for (int k = 0; k < M->nu_post; ++k) smooth(false);
+}
+
 // A setup that fails part way may already have queued kernels on the caller's
 // stream that write blocks of the context's arena.  Those blocks go back to the
 // process-wide cache when the context is deleted, where a concurrent setup on
@@ -1848,6 +1932,92 @@ int gdsw_solve_multi(gdsw_ctx* C, int32_t k, const double* B, int64_t ldb, doubl
   } catch (const Error& e) {
     return gdsw::fail(e);
   }
+}
+
+int gdsw_mg_create(gdsw_ctx* fine, gdsw_ctx* coarse, int64_t n_fine, int64_t n_coarse, const int64_t* p_rowptr,
+                   const int32_t* p_col, const double* p_val, const int64_t* pt_rowptr, const int32_t* pt_col,
+                   const double* pt_val, int32_t nu_pre, int32_t nu_post, double omega, void* stream,
+                   gdsw_mg** out) {
+  if (!out) {
+    gdsw::g_last_error = "gdsw_mg_create: out is NULL";
+    return GDSW_EINVAL;
+  }
+  *out = nullptr;
+  if (!fine || !coarse || fine == coarse || !p_rowptr || !p_col || !p_val || !pt_rowptr || !pt_col || !pt_val ||
+      nu_pre < 0 || nu_post < 0 || nu_pre + nu_post > 64 || !(omega > 0.0) || fine->levels[0].n != n_fine ||
+      coarse->levels[0].n != n_coarse) {
+    gdsw::g_last_error = "gdsw_mg_create: NULL, inconsistent or out-of-range argument";
+    return GDSW_EINVAL;
+  }
+  gdsw_mg* M = new (std::nothrow) gdsw_mg();
+  if (!M) {
+    gdsw::g_last_error = "host allocation failed";
+    return GDSW_ENOMEM;
+  }
+  try {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    M->fine = fine;
+    M->coarse = coarse;
+    M->P = gdsw::copy_csr(M->arena, n_fine, p_rowptr, p_col, p_val, s);
+    M->PT = gdsw::copy_csr(M->arena, n_coarse, pt_rowptr, pt_col, pt_val, s);
+    M->d = M->arena.alloc_n<double>((size_t)n_fine);
+    M->t = M->arena.alloc_n<double>((size_t)n_fine);
+    M->dc = M->arena.alloc_n<double>((size_t)n_coarse);
+    M->ec = M->arena.alloc_n<double>((size_t)n_coarse);
+    M->nu_pre = nu_pre;
+    M->nu_post = nu_post;
+    M->omega = omega;
+    GDSW_HIP(hipStreamSynchronize(s));
+  } catch (const Error& e) {
+    (void)hipDeviceSynchronize();
+    delete M;
+    return gdsw::fail(e);
+  }
+  *out = M;
+  return GDSW_OK;
+}
+
+int gdsw_mg_apply(gdsw_mg* M, const double* r, double* z, void* stream) {
+  if (!M || !r || !z || r == z) {
+    gdsw::g_last_error = "gdsw_mg_apply: NULL or aliased argument";
+    return GDSW_EINVAL;
+  }
+  try {
+    gdsw::mg_cycle(M, r, z, static_cast<hipStream_t>(stream));
+  } catch (const Error& e) {
+    return gdsw::fail(e);
+  }
+  return GDSW_OK;
+}
+
+int gdsw_mg_solve(gdsw_mg* M, const double* b, double* x, void* stream, gdsw_solve_info* info) {
+  if (!M || !b || !x || b == x) {
+    gdsw::g_last_error = "gdsw_mg_solve: NULL or aliased argument";
+    return GDSW_EINVAL;
+  }
+  try {
+    const gdsw::KrylovWs ws = gdsw::context_workspace(M->fine);
+    const gdsw::Precond pc = [M](const double* v, double* z, hipStream_t s) { gdsw::mg_cycle(M, v, z, s); };
+    return gdsw::solve_impl(M->fine, b, x, static_cast<hipStream_t>(stream), info, ws, false, &pc);
+  } catch (const Error& e) {
+    return gdsw::fail(e);
+  }
+}
+
+int gdsw_mg_counts(gdsw_mg* M, int64_t* cycles, int64_t* coarse_iterations) {
+  if (!M) {
+    gdsw::g_last_error = "gdsw_mg_counts: NULL argument";
+    return GDSW_EINVAL;
+  }
+  if (cycles) *cycles = M->cycles;
+  if (coarse_iterations) *coarse_iterations = M->coarse_its;
+  return GDSW_OK;
+}
+
+void gdsw_mg_destroy(gdsw_mg* M) {
+  if (!M) return;
+  (void)hipDeviceSynchronize();
+  delete M;
 }
 
 int gdsw_spmv(gdsw_ctx* C, const double* x, double* y, void* stream) {

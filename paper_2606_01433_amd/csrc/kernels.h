@@ -170,5 +170,7 @@ void multi_axpy(int64_t n, int ncols, const double* V, int64_t ldv, const double
 void scale_by_inv_norm(int64_t n, const double* x, const double* nrm2, double* y, hipStream_t s);
 // y = b - y
 void residual_from(int64_t n, const double* b, double* y, hipStream_t s);
+// y = a x + b y (y is not read when b == 0)
+void axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
 
 }  // namespace gdsw

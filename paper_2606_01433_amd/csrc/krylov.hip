@@ -190,7 +190,18 @@ __global__ void k_residual_from(int64_t n, const double* __restrict__ b, double*
   if (r < n) y[r] = b[r] - y[r];
 }
 
+// y = a x + b y (y not read when b == 0).
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) y[r] = (b == 0.0) ? a * x[r] : a * x[r] + b * y[r];
+}
+
 }  // namespace
+
+void axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, a, x, b, y);
+  GDSW_LAUNCH_CHECK();
+}
 
 void spmv(const CsrDev& K, const double* x, double* y, hipStream_t s) {
   hipLaunchKernelGGL(k_spmv, dim3(blocks_for(K.n, 4)), dim3(256), 0, s, K, x, y);

@@ -64,6 +64,12 @@ SIGNATURES = {
     "gdsw_solve_noalloc": (c_i32, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(SolveInfo)]),
     "gdsw_apply_multi": (c_i32, [c_vp, c_i32, c_vp, c_i64, c_vp, c_i64, c_vp]),
     "gdsw_solve_multi": (c_i32, [c_vp, c_i32, c_vp, c_i64, c_vp, c_i64, c_vp, ctypes.POINTER(SolveInfo)]),
+    "gdsw_mg_create": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_dbl,
+                                c_vp, ctypes.POINTER(c_vp)]),
+    "gdsw_mg_apply": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
+    "gdsw_mg_solve": (c_i32, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(SolveInfo)]),
+    "gdsw_mg_counts": (c_i32, [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
+    "gdsw_mg_destroy": (None, [c_vp]),
     "gdsw_spmv": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
     "gdsw_scatter_local": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp]),
     "gdsw_export_maps": (c_i32, [c_vp, c_i32, ctypes.POINTER(MapsView)]),
@@ -357,6 +363,77 @@ class Context:
         if getattr(self, "_ctx", None) is not None:
             self._lib.gdsw_destroy(self._ctx)
             self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class MultiGrid:
+    """Two-grid geometric multigrid with the GDSW solver as coarse solver (gdsw_mg_*).
+
+    fine: Context on the fine problem (its apply is the smoother, its operator K_f);
+    coarse: Context on the coarse problem (its tol is the coarse reduction);
+    P: scipy sparse prolongation (fine free dofs x coarse free dofs)."""
+
+    def __init__(self, fine, coarse, P, nu_pre=2, nu_post=2, omega=1.0, stream=None):
+        import torch
+        lib = load_library()
+        self._lib = lib
+        self.fine, self.coarse = fine, coarse
+        self.n = fine.n
+        dev = torch.device("cuda", torch.cuda.current_device())
+        P = P.tocsr()
+        PT = P.T.tocsr()
+        P.sort_indices()
+        PT.sort_indices()
+        self._arrays = []
+        ptrs = []
+        for M in (P, PT):
+            t = (torch.as_tensor(M.indptr.astype(np.int64), device=dev),
+                 torch.as_tensor(M.indices.astype(np.int32), device=dev),
+                 torch.as_tensor(M.data.astype(np.float64), device=dev))
+            self._arrays.append(t)
+            ptrs.extend(x.data_ptr() for x in t)
+        out = c_vp()
+        _check(lib.gdsw_mg_create(fine._alive(), coarse._alive(), fine.n, coarse.n, *ptrs, int(nu_pre), int(nu_post),
+                                  float(omega), _stream_handle(stream), ctypes.byref(out)))
+        self._mg = out
+
+    def apply(self, r, out=None, stream=None):
+        import torch
+        z = torch.empty_like(r) if out is None else out
+        _check(self._lib.gdsw_mg_apply(self._mg, Context._dev(r, self.n), Context._dev(z, self.n),
+                                       _stream_handle(stream)))
+        return z
+
+    def solve(self, b, out=None, stream=None):
+        import torch
+        x = torch.empty_like(b) if out is None else out
+        info = SolveInfo()
+        code = _check(self._lib.gdsw_mg_solve(self._mg, Context._dev(b, self.n), Context._dev(x, self.n),
+                                              _stream_handle(stream), ctypes.byref(info)))
+        d = {k: getattr(info, k) for k, _ in SolveInfo._fields_}
+        d["code"] = code
+        return x, d
+
+    def counts(self):
+        c, k = c_i64(), c_i64()
+        _check(self._lib.gdsw_mg_counts(self._mg, ctypes.byref(c), ctypes.byref(k)))
+        return {"cycles": c.value, "coarse_iterations": k.value}
+
+    def close(self):
+        if getattr(self, "_mg", None) is not None:
+            self._lib.gdsw_mg_destroy(self._mg)
+            self._mg = None
 
     def __del__(self):
         try:
