@@ -73,7 +73,29 @@ void* device_take(size_t bytes, size_t& cap, int& dev) {
   }
   cap = (bytes + 255) & ~size_t(255);
   void* p = nullptr;
-  GDSW_HIP(hipMalloc(&p, cap));
+  hipError_t e = hipMalloc(&p, cap);
+  if (e == hipErrorOutOfMemory) {
+    // blocks cached for reuse may be what fills the device: release this device's cache (no
+    // context holds them) and try once more
+    (void)hipGetLastError();
+    std::vector<void*> drop;
+    {
+      std::lock_guard<std::mutex> g(g_dev_mu);
+      auto& m = g_dev_free[dev];
+      for (auto& kv : m) {
+        drop.push_back(kv.second);
+        g_dev_cached -= kv.first;
+      }
+      m.clear();
+    }
+    for (void* q : drop) (void)hipFree(q);
+    e = hipMalloc(&p, cap);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(e == hipErrorOutOfMemory ? GDSW_ENOMEM : GDSW_EHIP,
+                std::string("hipMalloc of ") + std::to_string(cap) + " bytes: " + hipGetErrorString(e));
+  }
   return p;
 }
 

@@ -70,7 +70,8 @@ class Server:
             fp = gdsw.footprint_bytes(req.problem, **req.options)
             if fp == 0:
                 raise gdsw.GdswError(gdsw.EINVAL, gdsw.load_library().gdsw_last_error().decode())
-            fp += 12 * len(req.problem.col) + 8 * (req.problem.n + 1) + 16 * req.problem.n   # K, b, x
+            # the request's K, b and x, and the library's private copy of K
+            fp += 2 * (12 * len(req.problem.col) + 8 * (req.problem.n + 1)) + 16 * req.problem.n
             self._footprints[key] = fp
         return self._footprints[key]
 
@@ -165,6 +166,7 @@ def run_stream(server, problems, n_requests, rate_hz, seed=0, **options):
 def summarize(reqs, t0, t1):
     lat = [r.latency * 1e3 for r in reqs if r.error is None]
     return {"requests": len(reqs), "failed": sum(r.error is not None for r in reqs),
+            "errors": sorted({str(r.error)[:160] for r in reqs if r.error is not None}),
             "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
             "solves_per_s": len(lat) / (t1 - t0),
             "iterations_mean": float(np.mean([r.info["iterations"] for r in reqs if r.error is None]))}
