@@ -377,7 +377,7 @@ def workload_leg(name, precision, steps, warmup, stream, seed=0, P=None):
         "lu_kernels": lu_rate(stats, precision)}
 
 
-def serving_bench(seed=0, n_requests=16, loads=(0.5, 0.8, 0.95)):
+def serving_bench(seed=0, n_requests=16, loads=(0.5, 0.8, 0.95), partial_path=None):
     """Poisson streams of Picard-step solves over seeded dies of 7 sizes (16^3 .. 64x32x32) with Carreau
     n ~ U[0.3, 0.9] and lambda = 10^U[-1, 1]: FP32-factor serving with 4 slots against FP64 with 4 slots
     and FP64 one at a time, at arrival rates rho x the FP64 one-at-a-time capacity."""
@@ -416,8 +416,7 @@ def serving_bench(seed=0, n_requests=16, loads=(0.5, 0.8, 0.95)):
                 say(f"  submitted {k + 1}/{len(picks)}")
         for k, r in enumerate(reqs):          # progress while the backlog drains
             r.wait()
-            if (k + 1) % 20 == 0:
-                say(f"  completed {k + 1}/{len(reqs)}")
+            say(f"  completed {k + 1}/{len(reqs)} ({(r.latency or 0) * 1e3:.0f} ms)")
         t_end = time.perf_counter()
         server.close()
         return reqs, summarize(reqs, t_start, t_end)
@@ -447,6 +446,9 @@ def serving_bench(seed=0, n_requests=16, loads=(0.5, 0.8, 0.95)):
         out["loads"][str(rho)] = {"arrival_rate_hz": rho * capacity, "fp32_factors_4_slots": s32,
                                   "fp64_4_slots": s64, "fp64_one_at_a_time": s1,
                                   "max_rel_diff_fp32_vs_fp64_solution": err}
+        if partial_path:
+            with open(partial_path, "a") as f:
+                f.write(json.dumps({"rho": rho, **out["loads"][str(rho)]}) + "\n")
     return out
 
 
@@ -506,6 +508,7 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=16)
     ap.add_argument("--serving-only", action="store_true", help="only the serving streams")
     ap.add_argument("--serving-loads", default="0.5,0.8,0.95", help="comma-separated rho values")
+    ap.add_argument("--serving-partial", default=None, help="append each load's result to this file")
     ap.add_argument("--ablation", action="store_true", help="only the Table 1 mirror (levels, overlap, combination)")
     ap.add_argument("--multigrid-only", action="store_true", help="only the multigrid-role leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -536,7 +539,8 @@ def main():
         return
     if args.serving_only:
         loads = tuple(float(x) for x in args.serving_loads.split(","))
-        print(json.dumps(serving_bench(args.seed, n_requests=args.serving_requests, loads=loads)), flush=True)
+        print(json.dumps(serving_bench(args.seed, n_requests=args.serving_requests, loads=loads,
+                                       partial_path=args.serving_partial)), flush=True)
         return
     name = args.headline
     precision = args.precision or ("mixed" if name == "die96x48x48" else "fp64")

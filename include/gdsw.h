@@ -22,7 +22,7 @@
  *
  * Ownership: the library copies everything it keeps during gdsw_setup; the
  * caller may free every input after it returns.  A context owns its device
- * memory until gdsw_destroy, which waits for the device to drain and hands
+ * memory until gdsw_destroy, which waits for the context's work and hands
  * the blocks to a process-wide cache (per device, at most 64 GiB) that later
  * setups reuse; cached blocks are released when the process exits (scratch
  * needed only during setup goes back to that cache when gdsw_setup returns).
@@ -118,8 +118,9 @@ typedef struct gdsw_problem {
  *             (gdsw_stats.ls_waves; results bit-identical to any fixed choice);
  *             bit 1 (2): time the batched LU variants of every level (paired
  *             64-column steps with rank-128 trailing updates or single steps
- *             with rank-64 updates; FP64 only: half- or full-width register
- *             panels for panels of 769..2048 rows) and keep the fastest
+ *             with rank-64 updates; size-classed or batch-wide register
+ *             panels; FP64 only: half- or full-width register panels for
+ *             panels of 769..2048 rows) and keep the fastest
  *             (gdsw_stats.lu_variant; the variants agree up to rounding).
  *             Choices are kept per batch shape for the process and, with the
  *             environment variable GDSW_TUNE_CACHE=<file>, in that file; a
@@ -143,7 +144,9 @@ typedef struct gdsw_options {
   int32_t tune;
   int32_t ls_waves;
   int32_t lu_variant;   /* batched LU variant when tune bit 1 is clear: bit 0 = single 64-column steps
-                           with rank-64 updates (else paired, rank 128), bit 1 = full-width FP64 panels */
+                           with rank-64 updates (else paired, rank 128), bit 1 = full-width FP64 panels,
+                           bit 2 = each matrix's panel in the smallest register panel that holds it
+                           (one launch per size class) */
   int32_t pressure_gamma; /* P1disc pressure in the coarse space (section 2.1): 0 = the constant mode of
                              every element is an interface dof and the linear modes are interior
                              (saddle-point extension); 1 = every pressure mode is an interface dof
@@ -348,8 +351,9 @@ void gdsw_plan_destroy(gdsw_plan* plan);
 size_t gdsw_footprint_bytes(const gdsw_problem* prob, const gdsw_options* opt);
 
 /* Release every resource of the context (NULL is a no-op): waits for the
- * device to drain, returns the device blocks to the process-wide cache and
- * frees the host memory. */
+ * work of the context's calls (on the streams they were given and on its own
+ * streams; other work on the device is not waited for), returns the device
+ * blocks to the process-wide cache and frees the host memory. */
 void gdsw_destroy(gdsw_ctx* ctx);
 
 /* Message of the calling thread's last failure ("" if none). */

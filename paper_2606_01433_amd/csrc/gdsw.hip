@@ -261,7 +261,8 @@ struct Level {
   double* rcm = nullptr;
   double* ycm = nullptr;
   hipEvent_t lu_ev[2] = {nullptr, nullptr};   // around the batched LU of this level (timing)
-  int lu_variant = 0;            // LU autotuner choice: bit 0 = single steps, bit 1 = full-width panels
+  int lu_variant = 0;            // LU variant: bit 0 = single steps, bit 1 = full-width panels,
+                                 // bit 2 = size-classed register panels
 };
 
 }  // namespace
@@ -311,6 +312,9 @@ struct gdsw_ctx {
   std::vector<void*> setup_scratch;
   // page-locked staging buffers held while uploads may be in flight
   std::vector<std::pair<void*, size_t>> pinned;
+  // an event recorded on every caller stream after each call: gdsw_destroy waits for these (and
+  // the context's own streams) instead of the whole device
+  std::map<hipStream_t, hipEvent_t> stream_marks;
   void release_pinned() {
     for (auto& pc : pinned) gdsw::pinned_give(pc.first, pc.second);
     pinned.clear();
@@ -343,6 +347,10 @@ struct gdsw_ctx {
       (void)hipStreamDestroy(up);
     }
     release_pinned();
+    for (auto& kv : stream_marks) {
+      (void)hipEventSynchronize(kv.second);
+      (void)hipEventDestroy(kv.second);
+    }
     if (hhost) (void)hipHostFree(hhost);
     if (mhost) (void)hipHostFree(mhost);
     if (ev_up) (void)hipEventDestroy(ev_up);
@@ -433,7 +441,7 @@ bool tune_lookup(const std::string& key, int* w) {
         long long sn;
         while (std::fscanf(f, "%7s %d %d %d %lld %d %d", tag, &vb, &lv, &np, &sn, &mx, &wv) == 7) {
           const std::string t(tag);
-          if ((t == "ls" && (wv == 2 || wv == 4 || wv == 8)) || (t == "lu" && wv >= 0 && wv <= 3))
+          if ((t == "ls" && (wv == 2 || wv == 4 || wv == 8)) || (t == "lu" && wv >= 0 && wv <= 7))
             c.waves[tune_key(tag, vb, lv, np, sn, mx)] = wv;
         }
         std::fclose(f);
@@ -523,6 +531,15 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
   b.wide = true;
   b.ut = A.alloc_n<T>((size_t)128 * L.sum_n);
   C->setup_scratch.push_back(b.ut);
+  std::vector<int> sorted_dims(N);
+  for (int q = 0; q < N; ++q) sorted_dims[q] = L.dims[L.order_h[q]];
+  b.order = L.order;
+  b.order_dims = sorted_dims.data();
+  auto set_variant = [&](int v) {
+    b.wide = (v & 1) == 0;
+    b.full_panels = (v >> 1) & 1;
+    b.panel_classes = (v >> 2) & 1;
+  };
   if (C->opt.tune & 2) {
     // LU autotuner: paired 64-column steps with rank-128 trailing updates or single steps with
     // rank-64 updates, half-width or full-width register panels for FP64 panels of 769..2048
@@ -535,10 +552,9 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
       GDSW_HIP(hipEventCreate(&t0));
       GDSW_HIP(hipEventCreate(&t1));
       float best = 1e30f;
-      const int nvar = sizeof(T) == 8 ? 4 : 2;
-      for (int v = 0; v < nvar; ++v) {
-        b.wide = (v & 1) == 0;
-        b.full_panels = (v >> 1) & 1;
+      for (int v = 0; v < 8; ++v) {
+        if (sizeof(T) == 4 && (v & 2)) continue;     // full-width panels: an FP64 choice only
+        set_variant(v);
         GDSW_HIP(hipMemsetAsync(blocks, 0, (size_t)L.sum_n2 * sizeof(T), s));
         extract_blocks<T>(L.K, N, L.max_n, L.order, L.dom_ptr, L.dom, L.blk_off, blocks, L.pad, s);
         GDSW_HIP(hipEventRecord(t0, s));
@@ -559,13 +575,11 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
       extract_blocks<T>(L.K, N, L.max_n, L.order, L.dom_ptr, L.dom, L.blk_off, blocks, L.pad, s);
       GDSW_HIP(hipMemsetAsync(L.info, 0, N * sizeof(int), s));
     }
-    b.wide = (variant & 1) == 0;
-    b.full_panels = (variant >> 1) & 1;
+    set_variant(variant);
     L.lu_variant = variant;
   } else {
-    b.wide = (C->opt.lu_variant & 1) == 0;
-    b.full_panels = (C->opt.lu_variant >> 1) & 1;
-    L.lu_variant = C->opt.lu_variant & 3;
+    set_variant(C->opt.lu_variant);
+    L.lu_variant = C->opt.lu_variant;
   }
   GDSW_HIP(hipEventCreate(&L.lu_ev[0]));
   GDSW_HIP(hipEventCreate(&L.lu_ev[1]));
@@ -1690,6 +1704,13 @@ struct gdsw_mg {
   int nu_pre = 2, nu_post = 2;
   double omega = 1.0;
   int64_t cycles = 0, coarse_its = 0;
+  std::map<hipStream_t, hipEvent_t> stream_marks;
+  ~gdsw_mg() {
+    for (auto& kv : stream_marks) {
+      (void)hipEventSynchronize(kv.second);
+      (void)hipEventDestroy(kv.second);
+    }
+  }
 };
 
 namespace gdsw {
@@ -1800,6 +1821,26 @@ double* scratch_on_current_device() {
 
 using gdsw::Error;
 
+namespace gdsw {
+namespace {
+// Records (creating on first use) the mark event of stream s in `marks` when the guard goes out
+// of scope, also when the call throws.
+struct StreamMark {
+  std::map<hipStream_t, hipEvent_t>* marks;
+  hipStream_t s;
+  ~StreamMark() {
+    if (!marks) return;
+    hipEvent_t& e = (*marks)[s];
+    if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      e = nullptr;
+      return;
+    }
+    (void)hipEventRecord(e, s);
+  }
+};
+}  // namespace
+}  // namespace gdsw
+
 extern "C" {
 
 void gdsw_default_options(gdsw_options* o) {
@@ -1840,7 +1881,7 @@ int gdsw_setup(const gdsw_problem* prob, const gdsw_options* opt, void* stream, 
         !(C->opt.tol >= 0.0) || (C->opt.combine != 0 && C->opt.combine != 1) ||
         (C->opt.precision != 0 && C->opt.precision != 1) ||
         (C->opt.ls_waves != 0 && C->opt.ls_waves != 2 && C->opt.ls_waves != 4 && C->opt.ls_waves != 8) ||
-        C->opt.tune < 0 || C->opt.tune > 3 || C->opt.lu_variant < 0 || C->opt.lu_variant > 3 ||
+        C->opt.tune < 0 || C->opt.tune > 3 || C->opt.lu_variant < 0 || C->opt.lu_variant > 7 ||
         (C->opt.pressure_gamma != 0 && C->opt.pressure_gamma != 1))
       throw Error(GDSW_EINVAL, "invalid options");
     C->mixed = C->opt.precision == GDSW_MIXED;
@@ -1882,6 +1923,7 @@ int gdsw_apply(gdsw_ctx* C, const double* r, double* z, void* stream) {
     gdsw::g_last_error = "gdsw_apply: NULL or aliased argument";
     return GDSW_EINVAL;
   }
+  gdsw::StreamMark mark_{&C->stream_marks, static_cast<hipStream_t>(stream)};
   try {
     gdsw::apply_any(C, r, z, static_cast<hipStream_t>(stream));
   } catch (const Error& e) {
@@ -1895,6 +1937,7 @@ int gdsw_solve(gdsw_ctx* C, const double* b, double* x, void* stream, gdsw_solve
     gdsw::g_last_error = "gdsw_solve: NULL or aliased argument";
     return GDSW_EINVAL;
   }
+  gdsw::StreamMark mark_{&C->stream_marks, static_cast<hipStream_t>(stream)};
   try {
     const gdsw::KrylovWs ws = gdsw::context_workspace(C);
     return gdsw::solve_impl(C, b, x, static_cast<hipStream_t>(stream), info, ws, C->opt.graph != 0);
@@ -1908,6 +1951,7 @@ int gdsw_solve_noalloc(gdsw_ctx* C, const double* b, double* x, void* stream, gd
     gdsw::g_last_error = "gdsw_solve_noalloc: NULL or aliased argument";
     return GDSW_EINVAL;
   }
+  gdsw::StreamMark mark_{&C->stream_marks, static_cast<hipStream_t>(stream)};
   try {
     const int64_t n = C->levels[0].n;
     const int m = C->opt.restart;
@@ -1935,6 +1979,7 @@ int gdsw_apply_multi(gdsw_ctx* C, int32_t k, const double* R, int64_t ldr, doubl
     gdsw::g_last_error = "gdsw_apply_multi: NULL, aliased or out-of-range argument";
     return GDSW_EINVAL;
   }
+  gdsw::StreamMark mark_{&C->stream_marks, static_cast<hipStream_t>(stream)};
   try {
     gdsw::apply_multi_any(C, R, ldr, Z, ldz, k, static_cast<hipStream_t>(stream));
   } catch (const Error& e) {
@@ -1949,6 +1994,7 @@ int gdsw_solve_multi(gdsw_ctx* C, int32_t k, const double* B, int64_t ldb, doubl
     gdsw::g_last_error = "gdsw_solve_multi: NULL, aliased or out-of-range argument";
     return GDSW_EINVAL;
   }
+  gdsw::StreamMark mark_{&C->stream_marks, static_cast<hipStream_t>(stream)};
   try {
     return gdsw::solve_multi_impl(C, k, B, ldb, X, ldx, static_cast<hipStream_t>(stream), info);
   } catch (const Error& e) {
@@ -1991,7 +2037,7 @@ int gdsw_mg_create(gdsw_ctx* fine, gdsw_ctx* coarse, int64_t n_fine, int64_t n_c
     M->omega = omega;
     GDSW_HIP(hipStreamSynchronize(s));
   } catch (const Error& e) {
-    (void)hipDeviceSynchronize();
+    (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
     delete M;
     return gdsw::fail(e);
   }
@@ -2004,6 +2050,9 @@ int gdsw_mg_apply(gdsw_mg* M, const double* r, double* z, void* stream) {
     gdsw::g_last_error = "gdsw_mg_apply: NULL or aliased argument";
     return GDSW_EINVAL;
   }
+  gdsw::StreamMark mark_{&M->stream_marks, static_cast<hipStream_t>(stream)};
+  gdsw::StreamMark mark_f{&M->fine->stream_marks, static_cast<hipStream_t>(stream)};
+  gdsw::StreamMark mark_c{&M->coarse->stream_marks, static_cast<hipStream_t>(stream)};
   try {
     gdsw::mg_cycle(M, r, z, static_cast<hipStream_t>(stream));
   } catch (const Error& e) {
@@ -2017,6 +2066,9 @@ int gdsw_mg_solve(gdsw_mg* M, const double* b, double* x, void* stream, gdsw_sol
     gdsw::g_last_error = "gdsw_mg_solve: NULL or aliased argument";
     return GDSW_EINVAL;
   }
+  gdsw::StreamMark mark_{&M->stream_marks, static_cast<hipStream_t>(stream)};
+  gdsw::StreamMark mark_f{&M->fine->stream_marks, static_cast<hipStream_t>(stream)};
+  gdsw::StreamMark mark_c{&M->coarse->stream_marks, static_cast<hipStream_t>(stream)};
   try {
     const gdsw::KrylovWs ws = gdsw::context_workspace(M->fine);
     const gdsw::Precond pc = [M](const double* v, double* z, hipStream_t s) { gdsw::mg_cycle(M, v, z, s); };
@@ -2038,8 +2090,7 @@ int gdsw_mg_counts(gdsw_mg* M, int64_t* cycles, int64_t* coarse_iterations) {
 
 void gdsw_mg_destroy(gdsw_mg* M) {
   if (!M) return;
-  (void)hipDeviceSynchronize();
-  delete M;
+  delete M;                      // waits for the marks of its calls first (~gdsw_mg)
 }
 
 int gdsw_spmv(gdsw_ctx* C, const double* x, double* y, void* stream) {
@@ -2047,6 +2098,7 @@ int gdsw_spmv(gdsw_ctx* C, const double* x, double* y, void* stream) {
     gdsw::g_last_error = "gdsw_spmv: NULL argument";
     return GDSW_EINVAL;
   }
+  gdsw::StreamMark mark_{&C->stream_marks, static_cast<hipStream_t>(stream)};
   try {
     gdsw::spmv(C->levels[0].K, x, y, static_cast<hipStream_t>(stream));
   } catch (const Error& e) {
@@ -2060,6 +2112,7 @@ int gdsw_scatter_local(gdsw_ctx* C, int32_t level, const double* w, double* z, v
     gdsw::g_last_error = "gdsw_scatter_local: bad argument";
     return GDSW_EINVAL;
   }
+  gdsw::StreamMark mark_{&C->stream_marks, static_cast<hipStream_t>(stream)};
   try {
     gdsw::Level& L = C->levels[level - 1];
     gdsw::scatter_sum(L.n, L.sc_ptr, L.sc_pos, w, z, static_cast<hipStream_t>(stream));
@@ -2202,9 +2255,9 @@ size_t gdsw_footprint_bytes(const gdsw_problem* prob, const gdsw_options* opt) {
 
 void gdsw_destroy(gdsw_ctx* C) {
   if (!C) return;
-  // the device blocks go back to the process cache: drain the device first
-  // (the same wait hipFree implies), so no queued work still uses them
-  (void)hipDeviceSynchronize();
+  // the device blocks go back to the process cache: the context's destructor first waits for the
+  // work of its calls (the mark recorded on every caller stream after each call, and its own
+  // streams), so no queued work still uses them; other contexts' work is not waited for
   delete C;
 }
 

@@ -44,6 +44,11 @@ struct LuBatch {
   // FP64 panels of 769..2048 rows: 0 = two half-width (16-column) register panels, 1 = one
   // full-width panel whenever it fits the registers (an autotuner choice; same pivots and results).
   int full_panels = 0;
+  // Size classes for the register panels (an autotuner choice): order = matrix ids by
+  // decreasing order (device), order_dims = their orders in that order (host).
+  int panel_classes = 0;
+  const int* order = nullptr;
+  const int* order_dims = nullptr;
 };
 size_t lu_tall_scratch_bytes(int n, int value_bytes);
 // X = A^{-1} (column-major) of a single LU-factored FP64 matrix (b.count == 1, b.off

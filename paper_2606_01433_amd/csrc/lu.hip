@@ -491,11 +491,13 @@ template <typename T, int NB, int NT, int R>
 __global__ __launch_bounds__(NT, (sizeof(T) == 8 && NT == 256 && R == 3) ? 2 : 1) void k_lu_panel_rot(T* __restrict__ Ab, const int64_t* __restrict__ off,
                                                      const int* __restrict__ dim, int* __restrict__ pivb,
                                                      const int64_t* __restrict__ poff, int* __restrict__ info,
-                                                     int k, int pad) {
+                                                     int k, int pad, const int* __restrict__ list = nullptr,
+                                                     int first = 0) {
   static_assert(NB % 8 == 0, "panel width must be a multiple of 8");
   constexpr int NW = NT / 64;
   constexpr int CH = 8;
-  const int i = blockIdx.x;
+  // list: the matrices of one size class (a range of the batch sorted by decreasing order)
+  const int i = list ? list[first + blockIdx.x] : blockIdx.x;
   const int n = dim[i];
   const int m = n - k;
   if (m <= 0 || m > NT * R) return;         // taller panels go to k_lu_panel
@@ -1222,9 +1224,51 @@ void launch_panel_split(const LuBatch& b, T* A, int k, hipStream_t s) {
 
 // split: every matrix of the batch is held by the register panels at this step
 // (none is left to k_lu_panel), so the half-width path may run on all of them.
+// Size classes: every matrix's panel goes to the smallest full-width register
+// panel that holds it (one launch per class, over a range of the batch sorted by
+// decreasing order) instead of all to the variant of the tallest one, so the
+// short panels run with fewer registers per lane and more workgroups per CU.
+// Only while no panel of the step needs the half-width or memory paths.
+template <typename T>
+bool launch_panel_classes(const LuBatch& b, T* A, int k, int rows, hipStream_t s) {
+  constexpr int NB = LU_NB;
+  if (!b.order || !b.order_dims || rows > (sizeof(T) == 8 ? 768 : 2048)) return false;
+  // order_dims: orders in decreasing order; matrices with n - k in (lo, hi] form one class
+  auto first_above = [&](int64_t n_lim) {     // first position whose order is <= n_lim
+    int lo = 0, hi = b.count;
+    while (lo < hi) {
+      const int mid = (lo + hi) / 2;
+      if (b.order_dims[mid] > n_lim) lo = mid + 1;
+      else hi = mid;
+    }
+    return lo;
+  };
+  int lo_cap = 0;
+  auto cls = [&](auto kern, int nt, int cap) {
+    const int p0 = first_above((int64_t)k + cap);
+    const int p1 = first_above((int64_t)k + lo_cap);
+    lo_cap = cap;
+    if (p1 > p0) {
+      hipLaunchKernelGGL(kern, dim3(p1 - p0), dim3(nt), 0, s, A, b.off, b.dim, b.piv, b.poff, b.info, k, b.pad,
+                         b.order, p0);
+      GDSW_LAUNCH_CHECK();
+    }
+  };
+  cls(k_lu_panel_rot<T, NB, 256, 1>, 256, 256);
+  cls(k_lu_panel_rot<T, NB, 256, 2>, 256, 512);
+  cls(k_lu_panel_rot<T, NB, 256, 3>, 256, 768);
+  if constexpr (sizeof(T) == 4) {
+    cls(k_lu_panel_rot<T, NB, 512, 2>, 512, 1024);
+    cls(k_lu_panel_rot<T, NB, 512, 3>, 512, 1536);
+    cls(k_lu_panel_rot<T, NB, 512, 4>, 512, 2048);
+  }
+  return true;
+}
+
 template <typename T>
 void launch_panel_rot(const LuBatch& b, T* A, int k, int rows, bool split, hipStream_t s) {
   constexpr int NB = LU_NB;
+  if (b.panel_classes && launch_panel_classes<T>(b, A, k, rows, s)) return;
 #define GDSW_PANEL(NT, R)                                                                                       \
   if (rows <= NT * R) {                                                                                         \
     hipLaunchKernelGGL((k_lu_panel_rot<T, NB, NT, R>), dim3(b.count), dim3(NT), 0, s, A, b.off, b.dim, b.piv, \

@@ -33,6 +33,7 @@ class Request:
         self.info = None
         self.error = None
         self.footprint = None
+        self.oom_retries = 0
         self._done = threading.Event()
 
     def wait(self, timeout=None):
@@ -127,13 +128,26 @@ class Server:
                 del K, b
         except Exception as e:          # reported on the request, the server keeps serving
             req.error = e
-        req.t_done = time.perf_counter()
+        retry = False
         with self.lock:
             self.used -= req.footprint
             self.active -= 1
-            self.finished.append(req)
+            # out of device memory while others run (their memory, or cached blocks, was not yet
+            # free): back to the head of the queue, admitted again when a running request ends;
+            # alone on the device it fails for good
+            if (isinstance(req.error, gdsw.GdswError) and req.error.code == gdsw.ENOMEM and self.active > 0
+                    and req.oom_retries < 8):
+                req.oom_retries += 1
+                req.error = None
+                req.x = req.info = None
+                self.queue.appendleft(req)
+                retry = True
+            else:
+                req.t_done = time.perf_counter()
+                self.finished.append(req)
             self.lock.notify_all()
-        req._done.set()
+        if not retry:
+            req._done.set()
 
     def close(self):
         with self.lock:
@@ -166,6 +180,7 @@ def run_stream(server, problems, n_requests, rate_hz, seed=0, **options):
 def summarize(reqs, t0, t1):
     lat = [r.latency * 1e3 for r in reqs if r.error is None]
     return {"requests": len(reqs), "failed": sum(r.error is not None for r in reqs),
+            "out_of_memory_requeues": sum(r.oom_retries for r in reqs),
             "errors": sorted({str(r.error)[:160] for r in reqs if r.error is not None}),
             "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
             "solves_per_s": len(lat) / (t1 - t0),

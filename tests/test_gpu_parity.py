@@ -421,8 +421,9 @@ def test_apply_parity_two_node_layers(gd):
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-3)])
 def test_lu_autotuner_variants_match_oracle(gd, precision, tol):
     """tune = all also times the batched LU variants per level (rank-128 paired steps or rank-64 single
-    steps; FP64 half- or full-width panels); whatever is chosen, the apply matches the oracle, and a
-    second context of the same shape reuses the choice (bit-identical apply)."""
+    steps; size-classed or batch-wide register panels; FP64 half- or full-width panels); whatever is
+    chosen, the apply matches the oracle, a second context of the same shape reuses the choice
+    (bit-identical apply), and every variant forced through lu_variant matches the oracle."""
     name = "die16_L4_uneven"
     P = _problem(name)
     r = random_vector(P.n, 17)
@@ -435,12 +436,12 @@ def test_lu_autotuner_variants_match_oracle(gd, precision, tol):
         z2 = ctx.apply(_dev(r)).cpu().numpy()
         st2 = ctx.stats()
     _say("  variants", st["lu_variant"][:3], "waves", st["ls_waves"][:3])
-    assert all(0 <= v <= 3 for v in st["lu_variant"][:3])
+    assert all(0 <= v <= 7 for v in st["lu_variant"][:3])
     assert list(st["lu_variant"][:3]) == list(st2["lu_variant"][:3])
     assert np.array_equal(z1, z2)
     err, emax = _errs(z1, zo)
     assert err <= tol and emax <= tol
-    for v in range(4 if precision == "fp64" else 2):
+    for v in (range(8) if precision == "fp64" else (0, 1, 4, 5)):
         with gd.Context(P, precision=precision, lu_variant=v) as ctx:
             zv = ctx.apply(_dev(r)).cpu().numpy()
             assert list(ctx.stats()["lu_variant"][:3]) == [v] * 3
