@@ -144,6 +144,22 @@ def local_solve_roofline(stats, traffic_key, precision, seed):
             "launches": launches, "avg_launch_us": ms_ls / launches * 1e3 if launches else None}
 
 
+def local_solve_levels(stats):
+    """Event-timed local solves of every Schwarz level (levels >= 2 run on a side stream beside the
+    level-1 solves, so their rate is that of a shared GPU)."""
+    out = []
+    L = stats[0]["levels"]
+    for l in range(8):
+        launches = sum(s["local_solve_launches_level"][l] for s in stats)
+        if not launches:
+            continue
+        ms = sum(s["ms_local_solve_level"][l] for s in stats) / launches
+        b = stats[0]["local_solve_bytes_level"][l]
+        out.append({"level": l + 1, "avg_launch_us": ms * 1e3, "bytes_per_launch": b,
+                    "achieved_gbs": b / (ms * 1e-3) / 1e9, "frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS})
+    return out
+
+
 def lu_rate(stats, precision):
     """Level-1 LU flops sum (2/3) n_i^3 over the event-timed level-1 LU kernels (median over steps)."""
     import numpy as np
@@ -578,6 +594,7 @@ def main():
                    "lu_variant_per_level": st0["lu_variant"][:st0["levels"] - 1]},
         "roofline": local_solve_roofline(stats, name, precision, args.seed),
         "factor": lu_rate(stats, precision),
+        "local_solves_per_level": local_solve_levels(stats),
     }
     say(f"headline {1.0 / T:.3f} solves/s, {infos[-1]['iterations']} its, residual {res:.2e}")
     if not args.no_legs:

@@ -106,9 +106,9 @@ typedef struct gdsw_problem {
  * tol       : relative residual target (default 1e-8).
  * no_coarse : 1 = omit the coarsest correction (one-level Schwarz for L = 2).
  * panel     : LU panel width, 0 = built-in default.
- * profile   : 1 = time every launch of the level-1 local-solve kernel with
- *             HIP events recorded by the dispatch itself on the caller's stream
- *             (reported by gdsw_get_stats); eager applies only.
+ * profile   : 1 = time every launch of the local-solve kernels (all levels)
+ *             with HIP events recorded by the dispatch itself on the stream it
+ *             runs on (reported by gdsw_get_stats); eager applies only.
  * graph     : 1 = inside gdsw_solve, each apply runs as a captured hipGraph
  *             (one per Krylov column, captured on first use and replayed by
  *             later solves on the same context); the solve then runs on a
@@ -196,6 +196,10 @@ typedef struct gdsw_stats {
    * s = 8 (FP64) or 4 (FP32 factors) */
   double apply_bytes;
   int32_t lu_variant[8];          /* batched LU variant of level l (see tune) */
+  /* profile = 1: event-timed local-solve launches of every level (level 1 also above) */
+  int64_t local_solve_launches_level[8];
+  double ms_local_solve_level[8];
+  double local_solve_bytes_level[8]; /* algorithmic bytes of one launch of level l */
 } gdsw_stats;
 
 /* Index maps of one level, host copies owned by the context (valid until

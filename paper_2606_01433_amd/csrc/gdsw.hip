@@ -294,6 +294,7 @@ struct gdsw_ctx {
   double* mhost = nullptr;
   // event pairs around level-1 local-solve launches (profile = 1)
   std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_level;           // level (0-based) of each event pair
   size_t ev_used = 0;
   // the coarse chain of the apply runs on `side`, forked from and joined to the caller's stream;
   // during setup `side` factors level 1 and `side2` the deeper levels
@@ -956,11 +957,11 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
   }
   const int schwarz = (int)C->levels.size();
   st.levels = schwarz + (coarsest ? 1 : 0);
-  {
-    const Level& L1 = C->levels[0];
+  for (int l = 0; l < schwarz && l < 8; ++l) {
     double bytes = 0;
-    for (int d : L1.dims) bytes += (double)d * d * sizeof(T) + 20.0 * d;
-    st.local_solve_bytes = bytes;
+    for (int d : C->levels[l].dims) bytes += (double)d * d * sizeof(T) + 20.0 * d;
+    st.local_solve_bytes_level[l] = bytes;
+    if (l == 0) st.local_solve_bytes = bytes;
   }
   int ec0 = -1, ec1 = -1;
   double* dense = nullptr;
@@ -1065,10 +1066,18 @@ void drain_events(gdsw_ctx* C) {
     GDSW_HIP(hipEventSynchronize(C->ev_pool[k + 1]));
     float ms = 0;
     GDSW_HIP(hipEventElapsedTime(&ms, C->ev_pool[k], C->ev_pool[k + 1]));
-    C->stats.ms_local_solve += ms;
-    C->stats.local_solve_launches++;
+    const int l = C->ev_level[k / 2];
+    if (l == 0) {
+      C->stats.ms_local_solve += ms;
+      C->stats.local_solve_launches++;
+    }
+    if (l < 8) {
+      C->stats.ms_local_solve_level[l] += ms;
+      C->stats.local_solve_launches_level[l]++;
+    }
   }
   C->ev_used = 0;
+  C->ev_level.clear();
 }
 
 // Autotuner: for every level, time the local solves with 2, 4 and 8 wavefronts
@@ -1149,12 +1158,13 @@ void apply_level(gdsw_ctx* C, int l, const double* r, double* z, hipStream_t s) 
     coarse_chain<T>(C, l, r, fs);
     GDSW_HIP(hipEventRecord(ev_join, fs));
   }
-  const bool prof = C->opt.profile && l == 0 && !C->capturing && !C->no_alloc_call;
+  const bool prof = C->opt.profile && !C->capturing && !C->no_alloc_call;
   hipEvent_t e_start = nullptr, e_stop = nullptr;
   if (prof) {
     if (C->ev_used + 2 > 4096) drain_events(C);
     e_start = next_event(C);
     e_stop = next_event(C);
+    C->ev_level.push_back(l);
   }
   local_solves<T>(L.nparts, L.max_n, L.order, L.dom_ptr, L.gidx, L.blk_off, static_cast<const T*>(L.blocks), L.pad,
                   r, L.w, l == 0, L.ls_waves, s, e_start, e_stop);

@@ -45,7 +45,8 @@ class Stats(ctypes.Structure):
                 ("ms_total", c_dbl), ("local_solve_launches", c_i64), ("ms_local_solve", c_dbl),
                 ("local_solve_bytes", c_dbl), ("ls_waves", c_i32 * 8), ("tl_factor", (c_dbl * 2) * 8),
                 ("tl_basis", (c_dbl * 2) * 8), ("tl_coarsest", c_dbl * 2), ("ms_lu", c_dbl * 8),
-                ("apply_bytes", c_dbl), ("lu_variant", c_i32 * 8)]
+                ("apply_bytes", c_dbl), ("lu_variant", c_i32 * 8), ("local_solve_launches_level", c_i64 * 8),
+                ("ms_local_solve_level", c_dbl * 8), ("local_solve_bytes_level", c_dbl * 8)]
 
 
 class MapsView(ctypes.Structure):
