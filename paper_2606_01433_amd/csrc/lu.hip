@@ -16,7 +16,10 @@
 //   outer  : the step's interchanges on all other columns, U12 = L11^{-1} A12
 //            (one thread per column), A22 -= L21 U12 with MFMA (16x16x4, FP64
 //            or FP32), 64x64 tiles, inner dimension 2*NB.
+#include <hip/hip_cooperative_groups.h>
+
 #include <algorithm>
+#include <mutex>
 
 #include "common.h"
 #include "kernels.h"
@@ -295,7 +298,11 @@ __device__ __forceinline__ void tall_candidates(const TallBufs<T>& B, int G, int
   double best = -1.0;
   int bi = 0x7fffffff;
   if (mine && r >= c) {
-    best = fabs((double)v[c - k]);
+    T vc = v[0];
+#pragma unroll
+    for (int q = 1; q < TALL_NB; ++q)
+      if (q == c - k) vc = v[q];
+    best = fabs((double)vc);
     bi = r;
   }
   int bt = tid;
@@ -326,14 +333,19 @@ __device__ __forceinline__ void tall_candidates(const TallBufs<T>& B, int G, int
     }
   const int g = blockIdx.x;
   if (tid == pt && p != 0x7fffffff) {
-    for (int q = 0; q < jb; ++q) B.cand[((size_t)slot * G + g) * TALL_NB + q] = v[q];
+#pragma unroll
+    for (int q = 0; q < TALL_NB; ++q)
+      if (q < jb) B.cand[((size_t)slot * G + g) * TALL_NB + q] = v[q];
   }
   if (tid == 0) {
     B.val[slot * G + g] = b;
     B.idx[slot * G + g] = p;
   }
-  if (mine && r == c)
-    for (int q = 0; q < jb; ++q) B.rowj[slot * TALL_NB + q] = v[q];
+  if (mine && r == c) {
+#pragma unroll
+    for (int q = 0; q < TALL_NB; ++q)
+      if (q < jb) B.rowj[slot * TALL_NB + q] = v[q];
+  }
 }
 
 // Candidates of the panel's first column k.
@@ -415,6 +427,82 @@ __global__ __launch_bounds__(TALL_T) void k_tall_step(T* __restrict__ A, int ld,
     }
   }
   if (j + 1 < k + jb) tall_candidates<T>(B, G, slot ^ 1, j + 1, k, jb, r, mine && r > j, v, s_v, s_i, s_t);
+}
+
+// The whole panel [k, k + jb) in one cooperative launch: the same column steps
+// as k_tall_first + k_tall_step (same candidates, pivot choice and arithmetic,
+// hence the same factors), with every thread's row kept in registers across
+// the panel's columns and a grid barrier where the per-column launches had a
+// kernel boundary.  The panel is read once and written once; one launch per
+// panel instead of jb + 1, which matters most when other streams keep every
+// CU busy and each launch waits for free slots.
+template <typename T>
+__global__ __launch_bounds__(TALL_T) void k_tall_panel_coop(T* __restrict__ A, int ld, int n, int k, int jb, int G,
+                                                            TallBufs<T> B, int* __restrict__ piv,
+                                                            int* __restrict__ info) {
+  namespace cg = cooperative_groups;
+  cg::grid_group grid = cg::this_grid();
+  __shared__ double s_v[TALL_T / 64];
+  __shared__ int s_i[TALL_T / 64], s_t[TALL_T / 64];
+  __shared__ T s_prow[TALL_NB];
+  const int tid = threadIdx.x;
+  const int r = k + blockIdx.x * TALL_T + tid;
+  const bool mine = r < n;
+  T v[TALL_NB];
+#pragma unroll
+  for (int q = 0; q < TALL_NB; ++q) v[q] = (mine && q < jb) ? A[r + (int64_t)(k + q) * ld] : T(0);
+  tall_candidates<T>(B, G, 0, k, k, jb, r, mine, v, s_v, s_i, s_t);
+  for (int j = k; j < k + jb; ++j) {
+    grid.sync();                       // every workgroup's candidates of column j are out
+    const int slot = (j - k) & 1;
+    double bv = B.val[slot * G];
+    int p = B.idx[slot * G], gw = 0;
+    for (int g = 1; g < G; ++g) {
+      const double cv = B.val[slot * G + g];
+      const int ci = B.idx[slot * G + g];
+      if (cv > bv || (cv == bv && ci < p)) {
+        bv = cv;
+        p = ci;
+        gw = g;
+      }
+    }
+    const bool singular = !(bv > 0.0) || p >= n;
+    if (singular) p = j;
+    if (blockIdx.x == 0 && tid == 0) {
+      piv[j] = p;
+      if (singular && info[0] == 0) info[0] = j + 1;
+    }
+    for (int q = tid; q < jb; q += TALL_T)
+      s_prow[q] = singular ? B.rowj[slot * TALL_NB + q] : B.cand[((size_t)slot * G + gw) * TALL_NB + q];
+    __syncthreads();
+    if (mine && r == j) {
+#pragma unroll
+      for (int q = 0; q < TALL_NB; ++q) v[q] = q < jb ? s_prow[q] : T(0);
+    } else if (mine && r == p) {       // p != j: receives row j
+#pragma unroll
+      for (int q = 0; q < TALL_NB; ++q) v[q] = q < jb ? B.rowj[slot * TALL_NB + q] : T(0);
+    }
+    const int cj = j - k;
+    if (mine && r > j) {
+      T vc = v[0];
+#pragma unroll
+      for (int q = 1; q < TALL_NB; ++q)
+        if (q == cj) vc = v[q];
+      const T pv = s_prow[cj];
+      const T l = (pv != T(0)) ? vc / pv : vc;
+#pragma unroll
+      for (int q = 0; q < TALL_NB; ++q) {
+        if (q == cj) v[q] = l;
+        if (q > cj && q < jb) v[q] -= l * s_prow[q];
+      }
+    }
+    if (j + 1 < k + jb) tall_candidates<T>(B, G, slot ^ 1, j + 1, k, jb, r, mine && r > j, v, s_v, s_i, s_t);
+  }
+  if (mine) {
+#pragma unroll
+    for (int q = 0; q < TALL_NB; ++q)
+      if (q < jb) A[r + (int64_t)(k + q) * ld] = v[q];
+  }
 }
 
 // (ov, ol) beats (val, lab): larger value, equal values to the smaller label.
@@ -1337,6 +1425,29 @@ void LuTiles::build(const int* dims, int count) {
   }
 }
 
+// Largest grid of k_tall_panel_coop that can be resident at once on the current
+// device (0 when cooperative launches are not supported); taller panels take
+// the per-column launches.
+template <typename T>
+int tall_coop_max_groups() {
+  static std::mutex mu;
+  static int cached[64];
+  static bool known[64];
+  int dev = 0;
+  GDSW_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return 0;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!known[dev]) {
+    int coop = 0, cus = 0, per_cu = 0;
+    GDSW_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    GDSW_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    GDSW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_tall_panel_coop<T>, TALL_T, 0));
+    cached[dev] = coop ? cus * per_cu : 0;
+    known[dev] = true;
+  }
+  return cached[dev];
+}
+
 template <typename T>
 void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
   constexpr int NB = LU_NB;
@@ -1356,7 +1467,16 @@ void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
       B.idx = reinterpret_cast<int*>(base + 2 * Gm * sizeof(double));
       B.cand = reinterpret_cast<T*>(base + 2 * Gm * (sizeof(double) + sizeof(int)) + 64);
       B.rowj = B.cand + (size_t)2 * Gm * TALL_NB;
-      const int ld = lead_dim(n, b.pad);
+      int ld = lead_dim(n, b.pad);
+      if (G <= tall_coop_max_groups<T>()) {
+        int kk = k, nn = n, jj = jb, gg = G;
+        T* AA = A;
+        int* pv = b.piv;
+        int* inf = b.info;
+        void* args[] = {&AA, &ld, &nn, &kk, &jj, &gg, &B, &pv, &inf};
+        GDSW_HIP(hipLaunchCooperativeKernel((const void*)k_tall_panel_coop<T>, dim3(G), dim3(TALL_T), args, 0, s));
+        return;
+      }
       hipLaunchKernelGGL((k_tall_first<T>), dim3(G), dim3(TALL_T), 0, s, A, ld, n, k, jb, G, B);
       GDSW_LAUNCH_CHECK();
       for (int j = k; j < k + jb; ++j) {
