@@ -203,7 +203,9 @@ def apply_roofline(run, precision, n_apply=10):
 
 def spmv_roofline(ctx, P, x, stream, calls=50):
     """y = K x through the library, timed with HIP events on the launching stream: algorithmic bytes
-    (CSR values and int32 columns, int64 row pointers, x once, y) over the mean duration."""
+    (CSR values, int32 columns read once per group of three rows that share them, int64 row pointers,
+    x once, y; the library's count) over the mean duration; the plain CSR bytes (every row's columns)
+    beside them."""
     import torch
     y = torch.empty_like(x)
     ctx.spmv(x, out=y, stream=stream)
@@ -214,9 +216,11 @@ def spmv_roofline(ctx, P, x, stream, calls=50):
     e1.record(stream)
     e1.synchronize()
     us = e0.elapsed_time(e1) / calls * 1e3
-    nbytes = 12.0 * len(P.col) + 8.0 * (P.n + 1) + 16.0 * P.n
+    csr_bytes = 12.0 * len(P.col) + 8.0 * (P.n + 1) + 16.0 * P.n
+    nbytes = float(ctx.stats()["spmv_bytes"]) or csr_bytes
     return {"bound": "hbm", "achieved": nbytes / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_call": nbytes, "us_per_call": us}
+            "frac": nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_call": nbytes, "us_per_call": us,
+            "plain_csr_bytes": csr_bytes, "plain_csr_gbs": csr_bytes / (us * 1e-6) / 1e9}
 
 
 def solve_only(run, precision, n_solves, tune=False):
@@ -588,6 +592,7 @@ def main():
         "config": {"workload": describe(name, precision) + (", autotuned local solves and LU variants" if tune else ""),
                    "n_dofs": int(P.n), "nnz": int(len(P.col)), "parts": st0["parts"][:st0["levels"]],
                    "level_dofs": st0["n"][:st0["levels"]], "iterations": infos[-1]["iterations"],
+                   "second_gram_schmidt_passes": infos[-1]["reorthogonalizations"],
                    "local_solve_waves_per_matrix": st0["ls_waves"][:st0["levels"] - 1],
                    "true_rel_residual": res, "precision": precision,
                    "ms_setup": float(sum(s["ms_total"] for s in stats) / len(stats)),

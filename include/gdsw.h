@@ -159,6 +159,7 @@ typedef struct gdsw_solve_info {
   int32_t converged;     /* 1 if the true relative residual reached tol      */
   double rel_residual;   /* true ||b - K x||_2 / ||b||_2 in FP64              */
   double ms_apply, ms_spmv, ms_orth, ms_total;   /* wall-clock per phase     */
+  int32_t reorthogonalizations;  /* iterations whose Gram-Schmidt took a second pass */
 } gdsw_solve_info;
 
 /* Sizes and algorithmic work of a built hierarchy (for reporting). */
@@ -200,6 +201,9 @@ typedef struct gdsw_stats {
   int64_t local_solve_launches_level[8];
   double ms_local_solve_level[8];
   double local_solve_bytes_level[8]; /* algorithmic bytes of one launch of level l */
+  /* algorithmic bytes of one gdsw_spmv: 8 per value, 4 per column index read (once for a
+   * group of three rows with one column list), 24 per row (row pointer, x, y) */
+  double spmv_bytes;
 } gdsw_stats;
 
 /* Index maps of one level, host copies owned by the context (valid until
@@ -240,7 +244,10 @@ int gdsw_setup(const gdsw_problem* prob, const gdsw_options* opt, void* stream, 
 int gdsw_apply(gdsw_ctx* ctx, const double* r, double* z, void* stream);
 
 /* Solve K x = b by FGMRES(restart) preconditioned by B (section 3), x0 = 0.
- * b, x: DEVICE FP64 vectors of length n.  Synchronizes the stream once per
+ * b, x: DEVICE FP64 vectors of length n.  Orthogonalization: classical
+ * Gram-Schmidt with a second pass in the iterations where the first removed
+ * more than half of |w|^2 (the test of Daniel, Gragg, Kaufman and Stewart).
+ * Synchronizes the stream once per
  * inner iteration (to read the Hessenberg column).  Returns GDSW_OK or
  * GDSW_NOTCONV (x then holds the last iterate); info may be NULL. */
 int gdsw_solve(gdsw_ctx* ctx, const double* b, double* x, void* stream, gdsw_solve_info* info);

@@ -870,6 +870,7 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
   // level-1 operator: a private copy of the caller's CSR
   CsrDev K;
   K.n = p->n;
+  unsigned long long* saved3 = nullptr;
   int64_t nnz = 0;
   GDSW_HIP(hipMemcpyAsync(&nnz, p->rowptr + p->n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   GDSW_HIP(hipStreamSynchronize(s));
@@ -885,6 +886,13 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
     K.rowptr = rp;
     K.col = cl;
     K.val = vl;
+    // groups of three rows with one column list (a node's velocity components) for the SpMV
+    unsigned char* same3 = C->arena.alloc_n<unsigned char>((size_t)(p->n + 2) / 3);
+    saved3 = C->arena.alloc_n<unsigned long long>(1);
+    C->setup_scratch.push_back(saved3);
+    GDSW_HIP(hipMemsetAsync(saved3, 0, sizeof(unsigned long long), s));
+    spmv_groups3(K, same3, saved3, s);
+    K.same3 = same3;
   }
   const int Lp = p->levels;
   C->levels.reserve(Lp);
@@ -981,6 +989,12 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
   GDSW_HIP(hipStreamSynchronize(s));
   GDSW_HIP(hipStreamSynchronize(C->up));
   C->release_pinned();
+  {
+    unsigned long long saved = 0;
+    GDSW_HIP(hipMemcpy(&saved, saved3, sizeof(saved), hipMemcpyDeviceToHost));
+    const int64_t nnz1 = C->levels.empty() ? 0 : C->levels[0].K.nnz;
+    st.spmv_bytes = 12.0 * (double)nnz1 - 4.0 * (double)saved + 24.0 * (double)p->n;
+  }
   for (void* p : C->setup_scratch) C->arena.free_one(p);
   C->setup_scratch.clear();
   for (const Level& L : C->levels) {
@@ -1379,6 +1393,7 @@ int solve_impl(gdsw_ctx* C, const double* b, double* x, hipStream_t caller, gdsw
   double* h1 = ws.hdev;               // [m+1]
   double* h2 = ws.hdev + (m + 1);     // [m+1]
   double* nr = ws.hdev + 2 * (m + 1); // [1]
+  double* gate = nr + 1;              // [1] second Gram-Schmidt pass taken
   double* hh = C->hhost;
   // the host polls an event after the copy (lower wake-up latency than a
   // blocking stream synchronization; the Krylov loop waits here every step)
@@ -1445,24 +1460,16 @@ int solve_impl(gdsw_ctx* C, const double* b, double* x, hipStream_t caller, gdsw
       tick(ms_apply, last);
       spmv(K, zj, w, s);
       tick(ms_spmv, last);
-      // classical Gram-Schmidt with one reorthogonalisation (two fused axpy + dot passes)
-      multi_dot(n, j + 1, V, n, w, dpart, h1, s);
-      if (j + 1 <= fused_gs_max_cols()) {
-        axpy_dot(n, j + 1, V, n, h1, w, dpart, h2, false, s);
-        axpy_dot(n, j + 1, V, n, h2, w, dpart, nr, true, s);
-      } else {
-        multi_axpy(n, j + 1, V, n, h1, w, s);
-        multi_dot(n, j + 1, V, n, w, dpart, h2, s);
-        multi_axpy(n, j + 1, V, n, h2, w, s);
-        multi_dot(n, 1, w, n, w, dpart, nr, s);
-      }
+      // classical Gram-Schmidt, reorthogonalised where needed
+      gram_schmidt(n, j + 1, V, n, w, dpart, h1, h2, nr, gate, s);
       scale_by_inv_norm(n, w, nr, V + (int64_t)(j + 1) * n, s);
-      fetch(2 * (m + 1) + 1);
+      fetch(2 * (m + 1) + 2);
       tick(ms_orth, last);
       (void)dummy;
       double* Hj = H.data() + (size_t)j * (m + 1);
       for (int i = 0; i <= j; ++i) Hj[i] = hh[i] + hh[(m + 1) + i];
       Hj[j + 1] = std::sqrt(hh[2 * (m + 1)]);
+      if (hh[2 * (m + 1) + 1] > 0.5) inf.reorthogonalizations++;
       const bool breakdown = Hj[j + 1] == 0.0;
       for (int i = 0; i < j; ++i) {
         const double t = cs[i] * Hj[i] + sn[i] * Hj[i + 1];
@@ -1514,7 +1521,7 @@ int solve_multi_impl(gdsw_ctx* C, int k, const double* B, int64_t ldb, double* X
   const int m = C->opt.restart;
   const int64_t n = C->levels[0].n;
   const CsrDev& K = C->levels[0].K;
-  const int hs = 2 * (m + 1) + 2;             // per-system Hessenberg slots (h1, h2, norm, pad)
+  const int hs = 2 * (m + 1) + 2;             // per-system slots (h1, h2, norm, second-pass flag)
   if (C->multi_cap < k || C->multi_m != m) {
     Arena& A = C->arena;
     C->mV = A.alloc_n<double>((size_t)k * n * (m + 1));
@@ -1543,7 +1550,7 @@ int solve_multi_impl(gdsw_ctx* C, int k, const double* B, int64_t ldb, double* X
   };
   struct Sys {
     double bnorm = 0, beta = 0;
-    int its = 0, k = 0, restarts = 0;
+    int its = 0, k = 0, restarts = 0, reorth = 0;
     bool done = false, conv = false, running = false;
     std::vector<double> H, cs, sn, g, y;
   };
@@ -1618,16 +1625,7 @@ int solve_multi_impl(gdsw_ctx* C, int k, const double* B, int64_t ldb, double* X
         double* h2 = Hs(q) + (m + 1);
         double* nr = Hs(q) + 2 * (m + 1);
         spmv(K, zj, w, s);
-        multi_dot(n, j + 1, V, n, w, C->mP, h1, s);
-        if (j + 1 <= fused_gs_max_cols()) {
-          axpy_dot(n, j + 1, V, n, h1, w, C->mP, h2, false, s);
-          axpy_dot(n, j + 1, V, n, h2, w, C->mP, nr, true, s);
-        } else {
-          multi_axpy(n, j + 1, V, n, h1, w, s);
-          multi_dot(n, j + 1, V, n, w, C->mP, h2, s);
-          multi_axpy(n, j + 1, V, n, h2, w, s);
-          multi_dot(n, 1, w, n, w, C->mP, nr, s);
-        }
+        gram_schmidt(n, j + 1, V, n, w, C->mP, h1, h2, nr, nr + 1, s);
         scale_by_inv_norm(n, w, nr, V + (int64_t)(j + 1) * n, s);
       }
       fetch_all();
@@ -1638,6 +1636,7 @@ int solve_multi_impl(gdsw_ctx* C, int k, const double* B, int64_t ldb, double* X
         double* Hj = S.H.data() + (size_t)j * (m + 1);
         for (int i = 0; i <= j; ++i) Hj[i] = hq[i] + hq[(m + 1) + i];
         Hj[j + 1] = std::sqrt(hq[2 * (m + 1)]);
+        if (hq[2 * (m + 1) + 1] > 0.5) S.reorth++;
         const bool breakdown = Hj[j + 1] == 0.0;
         for (int i = 0; i < j; ++i) {
           const double t = S.cs[i] * Hj[i] + S.sn[i] * Hj[i + 1];
@@ -1683,6 +1682,7 @@ int solve_multi_impl(gdsw_ctx* C, int k, const double* B, int64_t ldb, double* X
     std::memset(&inf, 0, sizeof(inf));
     inf.iterations = sy[q].its;
     inf.restarts = sy[q].restarts;
+    inf.reorthogonalizations = sy[q].reorth;
     inf.converged = sy[q].conv ? 1 : 0;
     inf.rel_residual = rel[q];
     inf.ms_total = total;
@@ -2257,6 +2257,7 @@ size_t gdsw_footprint_bytes(const gdsw_problem* prob, const gdsw_options* opt) {
     if (P.coarsest) total += 2 * n_last * n_last * 8 + 128 * n_last * 8;
     const size_t n = (size_t)prob->n;
     total += (size_t)(o.restart * 2 + 4) * n * 8;
+    total += n / 3 + 512;                              // SpMV row-group flags
     return total;
   } catch (...) {
     return 0;

@@ -81,6 +81,9 @@ struct CsrDev {
   const int64_t* rowptr = nullptr;
   const int* col = nullptr;
   const double* val = nullptr;
+  // optional: same3[g] = 1 when rows 3g, 3g+1, 3g+2 have identical column lists (the three velocity
+  // components of a node); the SpMV then reads those columns and gathers x once for the three rows
+  const unsigned char* same3 = nullptr;
 };
 
 // Dense local blocks A_i = K[D_i, D_i] (blocks pre-zeroed); one workgroup per
@@ -160,15 +163,19 @@ void dense_gemv_rows(int n, const double* AT, const double* x, double* y, hipStr
 
 // ---- Krylov ---------------------------------------------------------------
 void spmv(const CsrDev& K, const double* x, double* y, hipStream_t s);
+// K.same3 flags for every group of three rows; *saved += column entries the shared reads save
+void spmv_groups3(const CsrDev& K, unsigned char* same3, unsigned long long* saved, hipStream_t s);
 // h[c] = V[:, c] . w for c < ncols (V column-major, ld n); partial has blocks*ncols doubles.
 void multi_dot(int64_t n, int ncols, const double* V, int64_t ldv, const double* w, double* partial, double* h,
                hipStream_t s);
 int multi_dot_blocks(int64_t n);
-// Fused Gram-Schmidt pass: w -= V[:, 0..ncols) h, then out = V[:, 0..ncols)^T w (norm = false)
-// or out[0] = w . w (norm = true); ncols <= fused_gs_max_cols().
-void axpy_dot(int64_t n, int ncols, const double* V, int64_t ldv, const double* h, double* w, double* partial,
-              double* out, bool norm, hipStream_t s);
-int fused_gs_max_cols();
+// Classical Gram-Schmidt of w against V[:, 0..ncols) (ncols <= 250) with a second pass only where
+// the test of Daniel, Gragg, Kaufman and Stewart asks for it: h1 = first coefficients (h1[ncols]
+// = |w|^2 before), h2 = second coefficients (zero without a second pass), nr[0] = |w|^2 after,
+// gate[0] = 1 if the second pass ran.  h1, h2 hold ncols + 1 doubles; partial
+// multi_dot_blocks(n) * (ncols + 1).
+void gram_schmidt(int64_t n, int ncols, const double* V, int64_t ldv, double* w, double* partial, double* h1,
+                  double* h2, double* nr, double* gate, hipStream_t s);
 // w -= V[:, 0..ncols) h
 void multi_axpy(int64_t n, int ncols, const double* V, int64_t ldv, const double* h, double* w, hipStream_t s);
 // y = alpha * x   (alpha read from device: 1 / sqrt(*nrm2))

@@ -36,10 +36,8 @@ __device__ __forceinline__ double spmv_lane(const CsrDev& K, const double* __res
   return s;
 }
 
-__global__ __launch_bounds__(256) void k_spmv(CsrDev K, const double* __restrict__ x, double* __restrict__ y) {
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= K.n) return;
-  const int lane = threadIdx.x & 63;
+// (K x)[row] by one wavefront (every lane returns the sum).
+__device__ __forceinline__ double spmv_row(const CsrDev& K, const double* __restrict__ x, int64_t row, int lane) {
   const int64_t e0 = K.rowptr[row] + lane, e1 = K.rowptr[row + 1];
   const int64_t len = e1 - K.rowptr[row];
   double s = 0.0;
@@ -50,8 +48,112 @@ __global__ __launch_bounds__(256) void k_spmv(CsrDev K, const double* __restrict
   } else {
     for (int64_t e = e0; e < e1; e += 64) s += K.val[e] * x[K.col[e]];
   }
-  s = wave_sum(s);
+  return wave_sum(s);
+}
+
+__global__ __launch_bounds__(256) void k_spmv(CsrDev K, const double* __restrict__ x, double* __restrict__ y) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= K.n) return;
+  const int lane = threadIdx.x & 63;
+  const double s = spmv_row(K, x, row, lane);
   if (lane == 0) y[row] = s;
+}
+
+// Three rows with one column list (offsets ea, eb, ec; len entries each): the columns are read
+// and x gathered once; each row's sum takes its entries in the order spmv_lane does.
+template <int S>
+__device__ __forceinline__ void spmv_lane3(const CsrDev& K, const double* __restrict__ x, int64_t ea, int64_t eb,
+                                           int64_t ec, int len, int lane, double& sa, double& sb, double& sc) {
+  int c[S];
+  double va[S], vb[S], vc[S];
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    const int e = lane + 64 * j;
+    const bool in = e < len;
+    c[j] = in ? K.col[ea + e] : 0;
+    va[j] = in ? K.val[ea + e] : 0.0;
+    vb[j] = in ? K.val[eb + e] : 0.0;
+    vc[j] = in ? K.val[ec + e] : 0.0;
+  }
+  double xv[S];
+#pragma unroll
+  for (int j = 0; j < S; ++j) xv[j] = (lane + 64 * j < len) ? x[c[j]] : 0.0;
+  sa = sb = sc = 0.0;
+#pragma unroll
+  for (int j = 0; j < S; ++j)
+    if (lane + 64 * j < len) {
+      sa += va[j] * xv[j];
+      sb += vb[j] * xv[j];
+      sc += vc[j] * xv[j];
+    }
+}
+
+// One wavefront per group of three rows; groups flagged in K.same3 share the column reads and
+// the gathers of x, the others are three single rows.  Every y[row] equals k_spmv's bit for bit.
+__global__ __launch_bounds__(256) void k_spmv3(CsrDev K, const double* __restrict__ x, double* __restrict__ y) {
+  const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t r0 = 3 * g;
+  if (r0 >= K.n) return;
+  const int lane = threadIdx.x & 63;
+  if (K.same3[g]) {
+    const int64_t ea = K.rowptr[r0], eb = K.rowptr[r0 + 1], ec = K.rowptr[r0 + 2];
+    const int len = (int)(eb - ea);
+    double sa, sb, sc;
+    if (len <= 4 * 64) {
+      spmv_lane3<4>(K, x, ea, eb, ec, len, lane, sa, sb, sc);
+    } else if (len <= 8 * 64) {
+      spmv_lane3<8>(K, x, ea, eb, ec, len, lane, sa, sb, sc);
+    } else {
+      sa = sb = sc = 0.0;
+      for (int e = lane; e < len; e += 64) {
+        const double xv = x[K.col[ea + e]];
+        sa += K.val[ea + e] * xv;
+        sb += K.val[eb + e] * xv;
+        sc += K.val[ec + e] * xv;
+      }
+    }
+    sa = wave_sum(sa);
+    sb = wave_sum(sb);
+    sc = wave_sum(sc);
+    if (lane == 0) {
+      y[r0] = sa;
+      y[r0 + 1] = sb;
+      y[r0 + 2] = sc;
+    }
+    return;
+  }
+  for (int q = 0; q < 3 && r0 + q < K.n; ++q) {
+    const double s = spmv_row(K, x, r0 + q, lane);
+    if (lane == 0) y[r0 + q] = s;
+  }
+}
+
+// same3[g] for every group of three rows (0 for a last, incomplete group); shared[0] += the
+// column entries the shared reads save (2 len per flagged group).
+__global__ __launch_bounds__(256) void k_same_pattern3(CsrDev K, unsigned char* __restrict__ same3,
+                                                       unsigned long long* __restrict__ saved) {
+  const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t r0 = 3 * g;
+  if (r0 >= K.n) return;
+  const int lane = threadIdx.x & 63;
+  int ok = 0;
+  int64_t len = 0;
+  if (r0 + 2 < K.n) {
+    const int64_t ea = K.rowptr[r0], eb = K.rowptr[r0 + 1], ec = K.rowptr[r0 + 2], ed = K.rowptr[r0 + 3];
+    len = eb - ea;
+    if (ec - eb == len && ed - ec == len) {
+      ok = 1;
+      for (int64_t e = lane; e < len; e += 64) {
+        const int c = K.col[ea + e];
+        if (K.col[eb + e] != c || K.col[ec + e] != c) ok = 0;
+      }
+      ok = __all(ok);
+    }
+  }
+  if (lane == 0) {
+    same3[g] = (unsigned char)ok;
+    if (ok) atomicAdd(saved, (unsigned long long)(2 * len));
+  }
 }
 
 // partial[b * ncols + c] = sum over this block's rows of V[r, c0 + c] w[r].  Thread t takes rows
@@ -60,14 +162,17 @@ __global__ __launch_bounds__(256) void k_spmv(CsrDev K, const double* __restrict
 static_assert(DOT_BLOCK_ROWS == 512, "two rows per thread of a 256-thread block");
 __global__ __launch_bounds__(256) void k_multi_dot_partial(int64_t n, int ncols, const double* __restrict__ V,
                                                            int64_t ldv, const double* __restrict__ w,
-                                                           double* __restrict__ partial) {
+                                                           double* __restrict__ partial, int self,
+                                                           const double* __restrict__ gate) {
+  if (gate && !(gate[0] > 0.5)) return;
   __shared__ double red[4][DOT_MAXC];
   const int64_t ra = (int64_t)blockIdx.x * DOT_BLOCK_ROWS + threadIdx.x, rb = ra + 256;
   const bool ha = ra < n, hb = rb < n;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nout = ncols + self;
+  const double wa = ha ? w[ra] : 0.0, wb = hb ? w[rb] : 0.0;
   for (int c0 = 0; c0 < ncols; c0 += DOT_MAXC) {
     const int nc = min(DOT_MAXC, ncols - c0);
-    const double wa = ha ? w[ra] : 0.0, wb = hb ? w[rb] : 0.0;
     double va[DOT_MAXC], vb[DOT_MAXC];
 #pragma unroll
     for (int c = 0; c < DOT_MAXC; ++c) {
@@ -91,15 +196,26 @@ __global__ __launch_bounds__(256) void k_multi_dot_partial(int64_t n, int ncols,
     __syncthreads();
     if (threadIdx.x < nc) {
       const int c = threadIdx.x;
-      partial[(int64_t)blockIdx.x * ncols + c0 + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+      partial[(int64_t)blockIdx.x * nout + c0 + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
     }
     __syncthreads();
+  }
+  if (self) {                        // output column ncols: |w|^2
+    double acc = 0.0;
+    if (ha) acc += wa * wa;
+    if (hb) acc += wb * wb;
+    const double t = wave_sum(acc);
+    if (lane == 0) red[wid][0] = t;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      partial[(int64_t)blockIdx.x * nout + ncols] = ((red[0][0] + red[1][0]) + red[2][0]) + red[3][0];
   }
 }
 
 // One wave per column: lanes stride over the block partials, then a fixed butterfly.
 __global__ __launch_bounds__(256) void k_multi_dot_reduce(int nblocks, int ncols, const double* __restrict__ partial,
-                                                          double* __restrict__ h) {
+                                                          double* __restrict__ h, const double* __restrict__ gate) {
+  if (gate && !(gate[0] > 0.5)) return;
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= ncols) return;
   const int lane = threadIdx.x & 63;
@@ -110,21 +226,25 @@ __global__ __launch_bounds__(256) void k_multi_dot_reduce(int nblocks, int ncols
 }
 
 // Fused pass of classical Gram-Schmidt: w -= V[:, :ncols] h, then per-block
-// partial dots of the updated w with V's columns (norm = 0) or with itself
-// (norm = 1).  Same rows per thread, load order and reduction tree as
-// k_multi_dot_partial.
+// partial dots of the updated w with V's columns (mode 0), with itself (mode 1)
+// or both (mode 2: ncols dots, then the norm as output ncols).  Same rows per
+// thread, load order and reduction tree as k_multi_dot_partial.  Skipped when
+// gate is given and not set.
 __global__ __launch_bounds__(256) void k_axpy_dot_partial(int64_t n, int ncols, const double* __restrict__ V,
                                                           int64_t ldv, const double* __restrict__ h,
                                                           double* __restrict__ w, double* __restrict__ partial,
-                                                          int norm) {
+                                                          int mode, const double* __restrict__ gate) {
+  if (gate && !(gate[0] > 0.5)) return;
   __shared__ double hs[DOT_MAXC];
-  __shared__ double red[4][DOT_MAXC];
+  __shared__ double red[4][DOT_MAXC + 1];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (threadIdx.x < ncols) hs[threadIdx.x] = h[threadIdx.x];
   __syncthreads();
   const int64_t ra = (int64_t)blockIdx.x * DOT_BLOCK_ROWS + threadIdx.x, rb = ra + 256;
   const bool ha = ra < n, hb = rb < n;
-  const int nout = norm ? 1 : ncols;
+  const bool dots = mode != 1, norm = mode != 0;
+  const int ndot = dots ? ncols : 0;
+  const int nout = ndot + (norm ? 1 : 0);
   double va[DOT_MAXC], vb[DOT_MAXC];
 #pragma unroll
   for (int c = 0; c < DOT_MAXC; ++c) {
@@ -135,15 +255,15 @@ __global__ __launch_bounds__(256) void k_axpy_dot_partial(int64_t n, int ncols, 
   double acc[DOT_MAXC];
 #pragma unroll
   for (int c = 0; c < DOT_MAXC; ++c) acc[c] = 0.0;
+  double nacc = 0.0;
   auto row = [&](const double* v, double w0, int64_t r) {
     double t = 0.0;
 #pragma unroll
     for (int c = 0; c < DOT_MAXC; ++c) t += v[c] * hs[min(c, ncols - 1)] * (c < ncols ? 1.0 : 0.0);
     const double wr = w0 - t;
     w[r] = wr;
-    if (norm) {
-      acc[0] += wr * wr;
-    } else {
+    if (norm) nacc += wr * wr;
+    if (dots) {
 #pragma unroll
       for (int c = 0; c < DOT_MAXC; ++c)
         if (c < ncols) acc[c] += v[c] * wr;
@@ -153,15 +273,73 @@ __global__ __launch_bounds__(256) void k_axpy_dot_partial(int64_t n, int ncols, 
   if (hb) row(vb, wb0, rb);
 #pragma unroll
   for (int c = 0; c < DOT_MAXC; ++c) {
-    if (c < nout) {
+    if (c < ndot) {
       const double t = wave_sum(acc[c]);
       if (lane == 0) red[wid][c] = t;
     }
+  }
+  if (norm) {
+    const double t = wave_sum(nacc);
+    if (lane == 0) red[wid][ndot] = t;
   }
   __syncthreads();
   if (threadIdx.x < nout) {
     const int c = threadIdx.x;
     partial[(int64_t)blockIdx.x * nout + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+  }
+}
+
+// w -= V[:, :ncols] h over the rows of k_multi_dot_partial's blocks, with the
+// block partial of |w|^2 after the update.  Skipped when gate is given and not set.
+__global__ __launch_bounds__(256) void k_multi_axpy_norm(int64_t n, int ncols, const double* __restrict__ V,
+                                                         int64_t ldv, const double* __restrict__ h,
+                                                         double* __restrict__ w, double* __restrict__ partial,
+                                                         const double* __restrict__ gate) {
+  if (gate && !(gate[0] > 0.5)) return;
+  __shared__ double hs[256];
+  __shared__ double red[4];
+  for (int c = threadIdx.x; c < ncols; c += blockDim.x) hs[c] = h[c];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t ra = (int64_t)blockIdx.x * DOT_BLOCK_ROWS + threadIdx.x, rb = ra + 256;
+  const bool ha = ra < n, hb = rb < n;
+  double ta = 0.0, tb = 0.0;
+  for (int c = 0; c < ncols; ++c) {
+    const double hc = hs[c];
+    if (ha) ta += V[ra + (int64_t)c * ldv] * hc;
+    if (hb) tb += V[rb + (int64_t)c * ldv] * hc;
+  }
+  double nacc = 0.0;
+  if (ha) {
+    const double wr = w[ra] - ta;
+    w[ra] = wr;
+    nacc += wr * wr;
+  }
+  if (hb) {
+    const double wr = w[rb] - tb;
+    w[rb] = wr;
+    nacc += wr * wr;
+  }
+  const double t = wave_sum(nacc);
+  if (lane == 0) red[wid] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// Reorthogonalisation test of Daniel, Gragg, Kaufman and Stewart (1976): a
+// second Gram-Schmidt pass is needed when the first one removed more than half
+// of |w|^2 (|w'|^2 < |w|^2 / 2).  Sets gate; without a second pass the second
+// coefficients are zero and |w'|^2 is the final norm.
+__global__ void k_gs_decide(int ncols, const double* __restrict__ wn_before, const double* __restrict__ wn_after,
+                            double* __restrict__ gate, double* __restrict__ h2, double* __restrict__ nr) {
+  const double before = wn_before[0], after = wn_after[0];
+  const bool again = after < 0.5 * before;
+  for (int c = threadIdx.x; c < ncols; c += blockDim.x)
+    if (!again) h2[c] = 0.0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    gate[0] = again ? 1.0 : 0.0;
+    if (!again) nr[0] = after;
   }
 }
 
@@ -204,7 +382,16 @@ void axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_
 }
 
 void spmv(const CsrDev& K, const double* x, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_spmv, dim3(blocks_for(K.n, 4)), dim3(256), 0, s, K, x, y);
+  if (K.same3) {
+    hipLaunchKernelGGL(k_spmv3, dim3(blocks_for((K.n + 2) / 3, 4)), dim3(256), 0, s, K, x, y);
+  } else {
+    hipLaunchKernelGGL(k_spmv, dim3(blocks_for(K.n, 4)), dim3(256), 0, s, K, x, y);
+  }
+  GDSW_LAUNCH_CHECK();
+}
+
+void spmv_groups3(const CsrDev& K, unsigned char* same3, unsigned long long* saved, hipStream_t s) {
+  hipLaunchKernelGGL(k_same_pattern3, dim3(blocks_for((K.n + 2) / 3, 4)), dim3(256), 0, s, K, same3, saved);
   GDSW_LAUNCH_CHECK();
 }
 
@@ -213,22 +400,11 @@ int multi_dot_blocks(int64_t n) { return (int)blocks_for(n, DOT_BLOCK_ROWS); }
 void multi_dot(int64_t n, int ncols, const double* V, int64_t ldv, const double* w, double* partial, double* h,
                hipStream_t s) {
   const int nb = multi_dot_blocks(n);
-  hipLaunchKernelGGL(k_multi_dot_partial, dim3(nb), dim3(256), 0, s, n, ncols, V, ldv, w, partial);
+  hipLaunchKernelGGL(k_multi_dot_partial, dim3(nb), dim3(256), 0, s, n, ncols, V, ldv, w, partial, 0,
+                     (const double*)nullptr);
   GDSW_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_multi_dot_reduce, dim3(blocks_for(ncols, 4)), dim3(256), 0, s, nb, ncols, partial, h);
-  GDSW_LAUNCH_CHECK();
-}
-
-int fused_gs_max_cols() { return DOT_MAXC; }
-
-void axpy_dot(int64_t n, int ncols, const double* V, int64_t ldv, const double* h, double* w, double* partial,
-              double* out, bool norm, hipStream_t s) {
-  if (ncols > DOT_MAXC) throw Error(-1, "axpy_dot: too many columns");
-  const int nb = multi_dot_blocks(n);
-  hipLaunchKernelGGL(k_axpy_dot_partial, dim3(nb), dim3(256), 0, s, n, ncols, V, ldv, h, w, partial, norm ? 1 : 0);
-  GDSW_LAUNCH_CHECK();
-  const int nout = norm ? 1 : ncols;
-  hipLaunchKernelGGL(k_multi_dot_reduce, dim3(blocks_for(nout, 4)), dim3(256), 0, s, nb, nout, partial, out);
+  hipLaunchKernelGGL(k_multi_dot_reduce, dim3(blocks_for(ncols, 4)), dim3(256), 0, s, nb, ncols, partial, h,
+                     (const double*)nullptr);
   GDSW_LAUNCH_CHECK();
 }
 
@@ -236,6 +412,44 @@ void multi_axpy(int64_t n, int ncols, const double* V, int64_t ldv, const double
   if (ncols > 256) throw Error(-1, "multi_axpy: more than 256 columns");
   hipLaunchKernelGGL(k_multi_axpy, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, ncols, V, ldv, h, w);
   GDSW_LAUNCH_CHECK();
+}
+
+void gram_schmidt(int64_t n, int ncols, const double* V, int64_t ldv, double* w, double* partial, double* h1,
+                  double* h2, double* nr, double* gate, hipStream_t s) {
+  if (ncols > 250) throw Error(-1, "gram_schmidt: more than 250 columns");
+  const int nb = multi_dot_blocks(n);
+  const double* none = nullptr;
+  auto reduce = [&](int count, double* out, const double* g) {
+    hipLaunchKernelGGL(k_multi_dot_reduce, dim3(blocks_for(count, 4)), dim3(256), 0, s, nb, count, partial, out, g);
+    GDSW_LAUNCH_CHECK();
+  };
+  // first pass: h1 = V^T w, and |w|^2 in h1[ncols]
+  hipLaunchKernelGGL(k_multi_dot_partial, dim3(nb), dim3(256), 0, s, n, ncols, V, ldv, w, partial, 1, none);
+  GDSW_LAUNCH_CHECK();
+  reduce(ncols + 1, h1, none);
+  if (ncols <= DOT_MAXC) {
+    // w -= V h1 with V^T w (the second coefficients, kept if needed) and |w|^2 (h2[ncols]) in one pass
+    hipLaunchKernelGGL(k_axpy_dot_partial, dim3(nb), dim3(256), 0, s, n, ncols, V, ldv, h1, w, partial, 2, none);
+    GDSW_LAUNCH_CHECK();
+    reduce(ncols + 1, h2, none);
+    hipLaunchKernelGGL(k_gs_decide, dim3(1), dim3(256), 0, s, ncols, h1 + ncols, h2 + ncols, gate, h2, nr);
+    GDSW_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_axpy_dot_partial, dim3(nb), dim3(256), 0, s, n, ncols, V, ldv, h2, w, partial, 1, gate);
+    GDSW_LAUNCH_CHECK();
+    reduce(1, nr, gate);
+  } else {
+    hipLaunchKernelGGL(k_multi_axpy_norm, dim3(nb), dim3(256), 0, s, n, ncols, V, ldv, h1, w, partial, none);
+    GDSW_LAUNCH_CHECK();
+    reduce(1, h2 + ncols, none);
+    hipLaunchKernelGGL(k_gs_decide, dim3(1), dim3(256), 0, s, ncols, h1 + ncols, h2 + ncols, gate, h2, nr);
+    GDSW_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_multi_dot_partial, dim3(nb), dim3(256), 0, s, n, ncols, V, ldv, w, partial, 0, gate);
+    GDSW_LAUNCH_CHECK();
+    reduce(ncols, h2, gate);
+    hipLaunchKernelGGL(k_multi_axpy_norm, dim3(nb), dim3(256), 0, s, n, ncols, V, ldv, h2, w, partial, gate);
+    GDSW_LAUNCH_CHECK();
+    reduce(1, nr, gate);
+  }
 }
 
 void scale_by_inv_norm(int64_t n, const double* x, const double* nrm2, double* y, hipStream_t s) {

@@ -34,7 +34,8 @@ class Options(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", c_i32), ("restarts", c_i32), ("converged", c_i32), ("rel_residual", c_dbl),
-                ("ms_apply", c_dbl), ("ms_spmv", c_dbl), ("ms_orth", c_dbl), ("ms_total", c_dbl)]
+                ("ms_apply", c_dbl), ("ms_spmv", c_dbl), ("ms_orth", c_dbl), ("ms_total", c_dbl),
+                ("reorthogonalizations", c_i32)]
 
 
 class Stats(ctypes.Structure):
@@ -46,7 +47,8 @@ class Stats(ctypes.Structure):
                 ("local_solve_bytes", c_dbl), ("ls_waves", c_i32 * 8), ("tl_factor", (c_dbl * 2) * 8),
                 ("tl_basis", (c_dbl * 2) * 8), ("tl_coarsest", c_dbl * 2), ("ms_lu", c_dbl * 8),
                 ("apply_bytes", c_dbl), ("lu_variant", c_i32 * 8), ("local_solve_launches_level", c_i64 * 8),
-                ("ms_local_solve_level", c_dbl * 8), ("local_solve_bytes_level", c_dbl * 8)]
+                ("ms_local_solve_level", c_dbl * 8), ("local_solve_bytes_level", c_dbl * 8),
+                ("spmv_bytes", c_dbl)]
 
 
 class MapsView(ctypes.Structure):

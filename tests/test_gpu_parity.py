@@ -121,6 +121,33 @@ def test_spmv_matches_cpu_product(gd):
     assert np.all(np.abs(y - ref) <= 2.0 * L * np.finfo(np.float64).eps * scale)
 
 
+def test_spmv_row_groups_counted_exactly(gd):
+    """The SpMV reads the column list once for three consecutive rows with identical lists (a node's
+    velocity components); the library's byte count of one SpMV reflects the groups it found, which a
+    host count over the CSR arrays must reproduce exactly: 12 nnz - 4 (2 len per group) + 24 n."""
+    for name in ("cube4_L2", "die16_L3"):
+        P = _problem(name)
+        K = P.K().tocsr()
+        saved, groups = 0, 0
+        for g in range(K.shape[0] // 3):
+            a, b, c, d = K.indptr[3 * g:3 * g + 4]
+            if b - a == c - b == d - c and np.array_equal(K.indices[a:b], K.indices[b:c]) \
+                    and np.array_equal(K.indices[a:b], K.indices[c:d]):
+                saved += 2 * (b - a)
+                groups += 1
+        _say(name, "groups of three rows with one column list:", groups, "of", K.shape[0] // 3)
+        if name.startswith("die"):          # symmetric-gradient form: full 3x3 node couplings
+            assert groups >= (K.shape[0] // 3) // 2
+        with gd.Context(P, no_coarse=True) as ctx:
+            st = ctx.stats()
+            x = random_vector(P.n, 3)
+            y = ctx.spmv(_dev(x)).cpu().numpy()
+        assert st["spmv_bytes"] == 12.0 * K.nnz - 4.0 * saved + 24.0 * P.n
+        ref = K @ x
+        L = np.diff(K.indptr)
+        assert np.all(np.abs(y - ref) <= 2.0 * L * np.finfo(np.float64).eps * (abs(K) @ np.abs(x)))
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-3)])
 def test_apply_parity_blocks_of_order_2295(gd, precision, tol):
     """3^3-voxel parts: the interior part's block (order 2295) is taller than any register panel in FP64
