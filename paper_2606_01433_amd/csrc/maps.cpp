@@ -10,6 +10,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <functional>
+#include <memory>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -116,20 +117,24 @@ void parallel_for(int n, int nthreads, F f) {
   for (auto& th : pool) th.join();
 }
 
-// Sort and deduplicate each segment of a CSR list in place, then compact.
+// Sort and deduplicate each segment of a CSR list (segments in parallel), then
+// compact in place.
 void sort_unique_segments(std::vector<int64_t>& ptr, std::vector<int>& val) {
-  const int64_t nseg = (int64_t)ptr.size() - 1;
-  int64_t w = 0;
-  int64_t start = 0;
-  for (int64_t s = 0; s < nseg; ++s) {
-    const int64_t a = start, b = ptr[s + 1];
-    std::sort(val.begin() + a, val.begin() + b);
-    const int64_t seg_begin = w;
-    for (int64_t k = a; k < b; ++k) {
-      if (k == a || val[k] != val[k - 1]) val[w++] = val[k];
+  const int nseg = (int)ptr.size() - 1;
+  if (nseg <= 0) return;
+  std::vector<int> cnt(nseg);
+  parallel_for(nseg, host_threads(), [&](int, int s0, int s1) {
+    for (int s = s0; s < s1; ++s) {
+      auto a = val.begin() + ptr[s], b = val.begin() + ptr[s + 1];
+      std::sort(a, b);
+      cnt[s] = (int)(std::unique(a, b) - a);
     }
-    start = b;
-    ptr[s] = seg_begin;
+  });
+  int64_t w = 0;
+  for (int s = 0; s < nseg; ++s) {          // forward: the write position never passes the read one
+    const int64_t a = ptr[s];
+    ptr[s] = w;
+    for (int k = 0; k < cnt[s]; ++k) val[w++] = val[a + k];
   }
   ptr[nseg] = w;
   val.resize(w);
@@ -137,6 +142,11 @@ void sort_unique_segments(std::vector<int64_t>& ptr, std::vector<int>& val) {
 
 // elements containing each node (CSR)
 void node_elements(const LevelMesh& mesh, std::vector<int64_t>& ptr, std::vector<int>& el) {
+  if (!mesh.ne_ptr.empty()) {
+    ptr = mesh.ne_ptr;
+    el = mesh.ne;
+    return;
+  }
   ptr.assign(mesh.n_nodes + 1, 0);
   for (int e = 0; e < mesh.n_elem; ++e)
     for (int64_t k = mesh.en_ptr[e]; k < mesh.en_ptr[e + 1]; ++k) ptr[mesh.en[k] + 1]++;
@@ -228,7 +238,24 @@ std::string build_level1_mesh(int64_t n, int n_nodes, const int* node_dof, int n
       }
   }
   constexpr int MAXNB = 26;
-  std::vector<int> nbuf((size_t)n_nodes * MAXNB);
+  // the positions of a 27-node element within one lattice step of each position, ascending
+  struct Near {
+    int count;
+    int pos[26];
+  };
+  static const std::vector<Near> near = [] {
+    std::vector<Near> t(27);
+    for (int a = 0; a < 27; ++a) {
+      t[a].count = 0;
+      for (int b = 0; b < 27; ++b) {
+        if (b == a) continue;
+        const int dx = a % 3 - b % 3, dy = (a / 3) % 3 - (b / 3) % 3, dz = a / 9 - b / 9;
+        if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) t[a].pos[t[a].count++] = b;
+      }
+    }
+    return t;
+  }();
+  std::unique_ptr<int[]> nbuf(new int[(size_t)n_nodes * MAXNB]);   // every row written before it is read
   std::vector<int> ncount(n_nodes, 0);
   std::atomic<bool> overflow(false);
   parallel_for(n_nodes, host_threads(), [&](int, int v0, int v1) {
@@ -240,13 +267,9 @@ std::string build_level1_mesh(int64_t n, int n_nodes, const int* node_dof, int n
         continue;
       }
       for (int64_t q = ne_ptr[v]; q < ne_ptr[v + 1]; ++q) {
-        const int e = ne_el[q], a = ne_loc[q];
-        const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
-        for (int b = 0; b < 27; ++b) {
-          if (b == a) continue;
-          const int dx = ax - b % 3, dy = ay - (b / 3) % 3, dz = az - b / 9;
-          if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) cand[nc++] = out.en[(size_t)e * 27 + b];
-        }
+        const int* el = out.en.data() + (size_t)ne_el[q] * 27;
+        const Near& t = near[ne_loc[q]];
+        for (int k = 0; k < t.count; ++k) cand[nc++] = el[t.pos[k]];
       }
       std::sort(cand, cand + nc);
       int w = 0;
@@ -267,10 +290,12 @@ std::string build_level1_mesh(int64_t n, int n_nodes, const int* node_dof, int n
   std::vector<int> nb(cntp[n_nodes]);
   parallel_for(n_nodes, host_threads(), [&](int, int v0, int v1) {
     for (int v = v0; v < v1; ++v)
-      std::copy(nbuf.begin() + (size_t)v * MAXNB, nbuf.begin() + (size_t)v * MAXNB + ncount[v], nb.begin() + cntp[v]);
+      std::copy(nbuf.get() + (size_t)v * MAXNB, nbuf.get() + (size_t)v * MAXNB + ncount[v], nb.begin() + cntp[v]);
   });
   out.adj_ptr = std::move(cntp);
   out.adj = std::move(nb);
+  out.ne_ptr = std::move(ne_ptr);
+  out.ne = std::move(ne_el);
   return "";
 }
 
@@ -287,19 +312,23 @@ void build_domains(const LevelMesh& mesh, int delta, LevelMaps& m) {
   sort_unique_segments(m.s_ptr, m.s);
   // owning part of every dof (restricted combination): first part of S(v), the element's part for pressure
   m.owner.assign(mesh.n_dof, -1);
-  for (int v = 0; v < nn; ++v) {
-    if (m.s_ptr[v + 1] == m.s_ptr[v]) continue;
-    const int own = m.s[m.s_ptr[v]];
-    for (int d = 0; d < 3; ++d) {
-      const int g = mesh.node_dof[3 * v + d];
-      if (g >= 0) m.owner[g] = own;
+  parallel_for(nn, host_threads(), [&](int, int v0, int v1) {     // every dof has one node or element
+    for (int v = v0; v < v1; ++v) {
+      if (m.s_ptr[v + 1] == m.s_ptr[v]) continue;
+      const int own = m.s[m.s_ptr[v]];
+      for (int d = 0; d < 3; ++d) {
+        const int g = mesh.node_dof[3 * v + d];
+        if (g >= 0) m.owner[g] = own;
+      }
     }
-  }
-  for (int e = 0; e < mesh.n_elem; ++e)
-    for (int q = 0; q < 4; ++q) {
-      const int g = mesh.elem_pdof[4 * e + q];
-      if (g >= 0) m.owner[g] = mesh.elem_part[e];
-    }
+  });
+  parallel_for(mesh.n_elem, host_threads(), [&](int, int e0, int e1) {
+    for (int e = e0; e < e1; ++e)
+      for (int q = 0; q < 4; ++q) {
+        const int g = mesh.elem_pdof[4 * e + q];
+        if (g >= 0) m.owner[g] = mesh.elem_part[e];
+      }
+  });
   // D_i: nodes of the part's elements grown by delta node-graph layers, plus its pressure dofs
   std::vector<std::vector<int>> part_elems(N);
   for (int e = 0; e < mesh.n_elem; ++e) part_elems[mesh.elem_part[e]].push_back(e);

@@ -27,6 +27,8 @@ struct LevelMesh {
   int n_parts = 0;
   std::vector<int64_t> adj_ptr;       // node graph (sorted, no self loops)
   std::vector<int> adj;
+  std::vector<int64_t> ne_ptr;        // node -> elements (ascending), when the builder made it
+  std::vector<int> ne;
 };
 
 struct LevelMaps {
