@@ -48,7 +48,7 @@ __device__ __forceinline__ void ls_row_update(const T* __restrict__ A, int ld, T
     T v[H];
 #pragma unroll
     for (int j = 0; j < H; ++j) {
-      v[j] = (FULL || h * H + j < pw) ? A[o] : T(0);
+      v[j] = (FULL || h * H + j < pw) ? ld_stream(A + o) : T(0);
       o += ld;
       asm volatile("" : "+v"(o));
     }
@@ -77,7 +77,7 @@ __device__ __forceinline__ void ls_tri_lower(const T* __restrict__ A, int ld, T*
     for (int j = 0; j < H; ++j) {
       int l = lj;
       asm volatile("" : "+v"(l));
-      d[j] = (h * H + j < l) ? A[o] : T(0);
+      d[j] = (h * H + j < l) ? ld_stream(A + o) : T(0);
       o += ld;
       asm volatile("" : "+v"(o));
     }
@@ -110,7 +110,7 @@ __device__ __forceinline__ void ls_tri_upper(const T* __restrict__ A, int ld, T*
     for (int j = 0; j < H; ++j) {
       int l = lj;
       asm volatile("" : "+v"(l));
-      d[j] = (h * H + j > l && (FULL || h * H + j < pw)) ? A[o] : T(0);
+      d[j] = (h * H + j > l && (FULL || h * H + j < pw)) ? ld_stream(A + o) : T(0);
       o += ld;
       asm volatile("" : "+v"(o));
     }
@@ -189,7 +189,7 @@ __device__ __forceinline__ void lsm_row_update(const T* __restrict__ A, int ld, 
     T v[H];
 #pragma unroll
     for (int j = 0; j < H; ++j) {
-      v[j] = (FULL || h * H + j < pw) ? A[o] : T(0);
+      v[j] = (FULL || h * H + j < pw) ? ld_stream(A + o) : T(0);
       o += ld;
       asm volatile("" : "+v"(o));
     }
@@ -223,7 +223,7 @@ __device__ __forceinline__ void lsm_tri_lower(const T* __restrict__ A, int ld, T
     for (int j = 0; j < H; ++j) {
       int l = lj;
       asm volatile("" : "+v"(l));
-      d[j] = (h * H + j < l) ? A[o] : T(0);
+      d[j] = (h * H + j < l) ? ld_stream(A + o) : T(0);
       o += ld;
       asm volatile("" : "+v"(o));
     }
@@ -262,7 +262,7 @@ __device__ __forceinline__ void lsm_tri_upper(const T* __restrict__ A, int ld, T
     for (int j = 0; j < H; ++j) {
       int l = lj;
       asm volatile("" : "+v"(l));
-      d[j] = (h * H + j > l && (FULL || h * H + j < pw)) ? A[o] : T(0);
+      d[j] = (h * H + j > l && (FULL || h * H + j < pw)) ? ld_stream(A + o) : T(0);
       o += ld;
       asm volatile("" : "+v"(o));
     }
@@ -380,7 +380,7 @@ __global__ __launch_bounds__(256) void k_restrict(int n_coarse, const int64_t* _
       const int nIt = lane_value(nI, t);
       const T* ph = phi + pot;
       const int* I = inter + ibt;
-      for (int a = lane; a < nIt; a += 64) s += (double)ph[a] * r[I[a]];
+      for (int a = lane; a < nIt; a += 64) s += (double)ld_stream(ph + a) * r[I[a]];
     }
   }
   s = wave_sum(s);
@@ -417,7 +417,7 @@ __global__ __launch_bounds__(128) void k_prolong_interior(const int64_t* __restr
   const T* ph = phi + phi_off[i];
   for (int a = threadIdx.x; a < nI; a += blockDim.x) {
     double p = 0.0;
-    for (int c = 0; c < m; ++c) p += (double)ph[a + (int64_t)c * nI] * ys[c];
+    for (int c = 0; c < m; ++c) p += (double)ld_stream(ph + a + (int64_t)c * nI) * ys[c];
     z[inter[ib + a]] += p;
   }
 }
@@ -434,14 +434,15 @@ __global__ __launch_bounds__(256) void k_gemv_rows(int n, const double* __restri
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int c = lane;
   for (; c + 192 < n; c += 256) {
-    const double a0 = row[c], a1 = row[c + 64], a2 = row[c + 128], a3 = row[c + 192];
+    const double a0 = ld_stream(row + c), a1 = ld_stream(row + c + 64), a2 = ld_stream(row + c + 128),
+                 a3 = ld_stream(row + c + 192);
     const double x0 = x[c], x1 = x[c + 64], x2 = x[c + 128], x3 = x[c + 192];
     s0 += a0 * x0;
     s1 += a1 * x1;
     s2 += a2 * x2;
     s3 += a3 * x3;
   }
-  for (; c < n; c += 64) s0 += row[c] * x[c];
+  for (; c < n; c += 64) s0 += ld_stream(row + c) * x[c];
   double s = (s0 + s1) + (s2 + s3);
   s = wave_sum(s);
   if (lane == 0) y[r] = s;

@@ -33,6 +33,14 @@ inline unsigned blocks_for(int64_t n, int per_block) {
 }
 
 // Fixed-shape butterfly sum over the 64 lanes of a wavefront (deterministic).
+// Load of data read once per pass (factor, operator and basis streams): a
+// nontemporal hint, so the stream does not displace what the caches hold for
+// reuse.  Same value as a plain load.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);

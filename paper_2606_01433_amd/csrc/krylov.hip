@@ -23,8 +23,8 @@ __device__ __forceinline__ double spmv_lane(const CsrDev& K, const double* __res
 #pragma unroll
   for (int j = 0; j < S; ++j) {
     const int64_t e = e0 + 64 * j;
-    c[j] = (e < e1) ? K.col[e] : 0;
-    v[j] = (e < e1) ? K.val[e] : 0.0;
+    c[j] = (e < e1) ? ld_stream(K.col + e) : 0;
+    v[j] = (e < e1) ? ld_stream(K.val + e) : 0.0;
   }
   double xv[S];
 #pragma unroll
@@ -46,7 +46,7 @@ __device__ __forceinline__ double spmv_row(const CsrDev& K, const double* __rest
   } else if (len <= 8 * 64) {               // vertex rows of Q2 meshes (up to about 410 entries)
     s = spmv_lane<8>(K, x, e0, e1);
   } else {
-    for (int64_t e = e0; e < e1; e += 64) s += K.val[e] * x[K.col[e]];
+    for (int64_t e = e0; e < e1; e += 64) s += ld_stream(K.val + e) * x[ld_stream(K.col + e)];
   }
   return wave_sum(s);
 }
@@ -70,10 +70,10 @@ __device__ __forceinline__ void spmv_lane3(const CsrDev& K, const double* __rest
   for (int j = 0; j < S; ++j) {
     const int e = lane + 64 * j;
     const bool in = e < len;
-    c[j] = in ? K.col[ea + e] : 0;
-    va[j] = in ? K.val[ea + e] : 0.0;
-    vb[j] = in ? K.val[eb + e] : 0.0;
-    vc[j] = in ? K.val[ec + e] : 0.0;
+    c[j] = in ? ld_stream(K.col + ea + e) : 0;
+    va[j] = in ? ld_stream(K.val + ea + e) : 0.0;
+    vb[j] = in ? ld_stream(K.val + eb + e) : 0.0;
+    vc[j] = in ? ld_stream(K.val + ec + e) : 0.0;
   }
   double xv[S];
 #pragma unroll
@@ -106,10 +106,10 @@ __global__ __launch_bounds__(256) void k_spmv3(CsrDev K, const double* __restric
     } else {
       sa = sb = sc = 0.0;
       for (int e = lane; e < len; e += 64) {
-        const double xv = x[K.col[ea + e]];
-        sa += K.val[ea + e] * xv;
-        sb += K.val[eb + e] * xv;
-        sc += K.val[ec + e] * xv;
+        const double xv = x[ld_stream(K.col + ea + e)];
+        sa += ld_stream(K.val + ea + e) * xv;
+        sb += ld_stream(K.val + eb + e) * xv;
+        sc += ld_stream(K.val + ec + e) * xv;
       }
     }
     sa = wave_sum(sa);
@@ -176,8 +176,8 @@ __global__ __launch_bounds__(256) void k_multi_dot_partial(int64_t n, int ncols,
     double va[DOT_MAXC], vb[DOT_MAXC];
 #pragma unroll
     for (int c = 0; c < DOT_MAXC; ++c) {
-      va[c] = (c < nc && ha) ? V[ra + (int64_t)(c0 + c) * ldv] : 0.0;
-      vb[c] = (c < nc && hb) ? V[rb + (int64_t)(c0 + c) * ldv] : 0.0;
+      va[c] = (c < nc && ha) ? ld_stream(V + ra + (int64_t)(c0 + c) * ldv) : 0.0;
+      vb[c] = (c < nc && hb) ? ld_stream(V + rb + (int64_t)(c0 + c) * ldv) : 0.0;
     }
     double acc[DOT_MAXC];
 #pragma unroll
@@ -248,8 +248,8 @@ __global__ __launch_bounds__(256) void k_axpy_dot_partial(int64_t n, int ncols, 
   double va[DOT_MAXC], vb[DOT_MAXC];
 #pragma unroll
   for (int c = 0; c < DOT_MAXC; ++c) {
-    va[c] = (c < ncols && ha) ? V[ra + (int64_t)c * ldv] : 0.0;
-    vb[c] = (c < ncols && hb) ? V[rb + (int64_t)c * ldv] : 0.0;
+    va[c] = (c < ncols && ha) ? ld_stream(V + ra + (int64_t)c * ldv) : 0.0;
+    vb[c] = (c < ncols && hb) ? ld_stream(V + rb + (int64_t)c * ldv) : 0.0;
   }
   const double wa0 = ha ? w[ra] : 0.0, wb0 = hb ? w[rb] : 0.0;
   double acc[DOT_MAXC];
@@ -306,8 +306,8 @@ __global__ __launch_bounds__(256) void k_multi_axpy_norm(int64_t n, int ncols, c
   double ta = 0.0, tb = 0.0;
   for (int c = 0; c < ncols; ++c) {
     const double hc = hs[c];
-    if (ha) ta += V[ra + (int64_t)c * ldv] * hc;
-    if (hb) tb += V[rb + (int64_t)c * ldv] * hc;
+    if (ha) ta += ld_stream(V + ra + (int64_t)c * ldv) * hc;
+    if (hb) tb += ld_stream(V + rb + (int64_t)c * ldv) * hc;
   }
   double nacc = 0.0;
   if (ha) {
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(256) void k_multi_axpy(int64_t n, int ncols, const 
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   double acc = 0.0;
-  for (int c = 0; c < ncols; ++c) acc += V[r + (int64_t)c * ldv] * hs[c];
+  for (int c = 0; c < ncols; ++c) acc += ld_stream(V + r + (int64_t)c * ldv) * hs[c];
   w[r] -= acc;
 }
 
