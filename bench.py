@@ -39,6 +39,7 @@ RESTART = 150
 # runs scaled by a plain 1 GiB device copy (profiles/), valid only for the local-solve kernel source it
 # was measured on (hash of that part of apply.hip) and for the precision and seed it was taken with.
 LOCAL_SOLVE_TRAFFIC = {
+    ("die32x16x16", "fp64"): {"bytes": 3.985e9, "source_hash": "2f2b22309d915614"},
     ("die96x48x48", "mixed"): {"bytes": 86.121e9, "source_hash": "2f2b22309d915614"},
 }
 
