@@ -88,6 +88,26 @@ def test_solve_multi_equals_single_solves(gd, tol):
     _say("  iterations", [i["iterations"] for i in infos])
 
 
+def test_solve_multi_long_restart_equals_single_solves(gd):
+    """Lockstep solves past 32 Krylov columns (FGMRES(60) to 1e-10): the unfused Gram-Schmidt passes and
+    the per-system second-pass decisions give each system gdsw_solve's iterate bit for bit."""
+    P = cached(("gpu", "die16_L3"), lambda: die_problem(16, 8, 8, seed=0, levels=3))
+    k = 3
+    B = _block(P.n, k, 80)
+    _say("solve_multi restart 60, k =", k)
+    with gd.Context(P, tol=1e-10, restart=60) as ctx:
+        X, infos = ctx.solve_multi(B)
+        X = X.cpu().numpy()
+        for q in range(k):
+            x1, i1 = ctx.solve(B[q].contiguous())
+            assert infos[q]["converged"] and i1["converged"]
+            assert infos[q]["iterations"] == i1["iterations"] > 32, q
+            assert infos[q]["reorthogonalizations"] == i1["reorthogonalizations"], q
+            assert np.array_equal(X[q], x1.cpu().numpy()), q
+    _say("  iterations", [i["iterations"] for i in infos], "second passes",
+         [i["reorthogonalizations"] for i in infos])
+
+
 def test_solve_multi_reports_notconv_per_system(gd):
     P = cached(("gpu", "die16_L3"), lambda: die_problem(16, 8, 8, seed=0, levels=3))
     B = _block(P.n, 3, 70)

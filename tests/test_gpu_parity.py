@@ -257,6 +257,29 @@ def test_solve_parity(gd, name, tol):
         assert np.abs(x - P.x_exact).max() <= 1e-6
 
 
+def test_solve_parity_long_restart(gd):
+    """FGMRES(60) to 1e-10: more than 32 Krylov columns, so Gram-Schmidt takes its unfused passes
+    (separate update-and-norm and dot passes) and decides its second pass by the DGKS test; against the
+    oracle's FGMRES(60) with modified Gram-Schmidt and the direct solve."""
+    name = "die16_L3"
+    P = _problem(name)
+    K = P.K()
+    tol = 1e-10
+    xo, info_o = oracle.fgmres(lambda v: K @ v, lambda v: oracle.apply(_orc(name), v), P.b, tol=tol, restart=60)
+    _say("solve restart 60, oracle iterations", info_o["iterations"])
+    with gd.Context(P, tol=tol, restart=60) as ctx:
+        x, info = ctx.solve(_dev(P.b))
+    x = x.cpu().numpy()
+    _say("  gpu iterations", info["iterations"], "second passes", info["reorthogonalizations"])
+    assert info["converged"] and info_o["converged"]
+    assert info["iterations"] > 32           # the first cycle holds more than 32 columns
+    assert 0 <= info["reorthogonalizations"] <= info["iterations"]
+    assert abs(info["iterations"] - info_o["iterations"]) <= 2
+    assert np.linalg.norm(K @ x - P.b) <= tol * np.linalg.norm(P.b) * 1.0001
+    err, emax = _errs(x, xo)
+    assert err <= 1e3 * tol and emax <= 1e3 * tol
+
+
 def test_mixed_precision_solve(gd):
     P = _problem("die16_L3")
     _say("solve mixed die16_L3")
