@@ -51,7 +51,9 @@ void wait_event_polling(hipEvent_t e) {
 // context are handed to the next setup instead of being freed (hipMalloc and
 // hipFree are slow and hipFree synchronizes the device).  A request takes the
 // smallest cached block that fits with at most 25% slack; at most
-// DEVICE_CACHE_LIMIT bytes stay cached, the rest is freed.
+// DEVICE_CACHE_LIMIT bytes stay cached, and none while less than a quarter of
+// the device's memory is free (contexts alive beside each other, as in the
+// serving loop, then get the memory instead of the cache).
 constexpr size_t DEVICE_CACHE_LIMIT = size_t(64) << 30;
 std::mutex g_dev_mu;
 std::map<int, std::multimap<size_t, void*>> g_dev_free;
@@ -99,9 +101,22 @@ void* device_take(size_t bytes, size_t& cap, int& dev) {
   return p;
 }
 
+// Whether device dev has at least a quarter of its memory free (only known for
+// the current device; other devices count as having room).
+bool device_has_room(int dev) {
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != dev) return true;
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;
+  }
+  return free_b >= total_b / 4;
+}
+
 // The caller guarantees that no queued work still uses p.
 void device_give(void* p, size_t cap, int dev) {
-  {
+  if (device_has_room(dev)) {
     std::lock_guard<std::mutex> g(g_dev_mu);
     if (g_dev_cached + cap <= DEVICE_CACHE_LIMIT) {
       g_dev_free[dev].emplace(cap, p);
