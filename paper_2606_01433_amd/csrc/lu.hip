@@ -109,24 +109,45 @@ __device__ __forceinline__ void gemm_sub_tile(T* __restrict__ C, int64_t ldc, co
 }
 
 // C[M x N] -= A[M x K] * B[K x N] on the 64x64 tile (ty, tx), K <= KMAX, without
-// LDS: each wave (32x32 quarter, 2x2 MFMA blocks) prefetches its C values, then
-// takes K in two halves, loading a half's operand fragments straight into
-// registers before its MFMA chain (the halves reuse the registers, which leaves
-// room for three waves per SIMD; a half beyond K is skipped).  Same transposed
-// product and C layout as gemm_sub_tile.
+// LDS: each wave (32x32 quarter, 2x2 MFMA blocks) takes K in phases of S
+// MFMA steps (8 for FP32, 4 for FP64) and loads the operand fragments of
+// phase p + 1 straight into registers while the MFMA chain of phase p runs
+// (two register buffers).  The C values are loaded after the first phase's
+// operands, so that waiting for those does not wait for C; C is needed only
+// at the end.  The MFMA sequence is the same for every phase length (bit-
+// identical results).  Same transposed product and C layout as gemm_sub_tile.
 // B_ROWS: B is stored by rows (B[k][c] at B[c + k * ldb]), so the 16 lanes of
 // a lane group read 16 consecutive values of one row.
 template <typename T, int KMAX, bool B_ROWS = false>
 __device__ __forceinline__ void gemm_sub_tile_direct(T* __restrict__ C, int64_t ldc, const T* __restrict__ A,
                                                      int64_t lda, const T* __restrict__ B, int64_t ldb, int M, int N,
                                                      int K, int ty, int tx) {
-  constexpr int NPH = KMAX > 64 ? KMAX / 32 : 2;
-  constexpr int S = KMAX / 4 / NPH;
+  constexpr int SP = sizeof(T) == 8 ? 4 : 8;
+  constexpr int S = KMAX / 4 < SP ? KMAX / 4 : SP;
+  constexpr int NPH = KMAX / 4 / S;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wy = w >> 1, wx = w & 1;
   const int li = lane & 15, lk = lane >> 4;
   const int rbase = ty * TILE + wy * 32, cbase = tx * TILE + wx * 32;
   typedef typename Mfma<T>::v4 v4;
+  T av[2][S][2], bv[2][S][2];
+  auto load_phase = [&](int ph, T (&a)[S][2], T (&b)[S][2]) {
+#pragma unroll
+    for (int st = 0; st < S; ++st) {
+      const int k = 4 * (ph * S + st) + lk;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        const int r = rbase + rb * 16 + li;
+        a[st][rb] = (r < M && k < K) ? A[r + (int64_t)k * lda] : T(0);
+      }
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        const int c = cbase + cb * 16 + li;
+        b[st][cb] = (c < N && k < K) ? (B_ROWS ? B[c + (int64_t)k * ldb] : B[k + (int64_t)c * ldb]) : T(0);
+      }
+    }
+  };
+  load_phase(0, av[0], bv[0]);
   T cv[2][2][4];
 #pragma unroll
   for (int cb = 0; cb < 2; ++cb)
@@ -146,27 +167,14 @@ __device__ __forceinline__ void gemm_sub_tile_direct(T* __restrict__ C, int64_t 
 #pragma unroll
   for (int ph = 0; ph < NPH; ++ph) {
     if (ph > 0 && 4 * S * ph >= K) break;
-    T av[S][2], bv[S][2];
-#pragma unroll
-    for (int st = 0; st < S; ++st) {
-      const int k = 4 * (ph * S + st) + lk;
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb) {
-        const int r = rbase + rb * 16 + li;
-        av[st][rb] = (r < M && k < K) ? A[r + (int64_t)k * lda] : T(0);
-      }
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        const int c = cbase + cb * 16 + li;
-        bv[st][cb] = (c < N && k < K) ? (B_ROWS ? B[c + (int64_t)k * ldb] : B[k + (int64_t)c * ldb]) : T(0);
-      }
-    }
+    if (ph + 1 < NPH && 4 * S * (ph + 1) < K) load_phase(ph + 1, av[(ph + 1) & 1], bv[(ph + 1) & 1]);
 #pragma unroll
     for (int st = 0; st < S; ++st)
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb) acc[cb][rb] = Mfma<T>::mac(bv[st][cb], av[st][rb], acc[cb][rb]);
+        for (int rb = 0; rb < 2; ++rb)
+          acc[cb][rb] = Mfma<T>::mac(bv[ph & 1][st][cb], av[ph & 1][st][rb], acc[cb][rb]);
   }
 #pragma unroll
   for (int cb = 0; cb < 2; ++cb)
