@@ -4,6 +4,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "common.h"
 #include "kernels.h"
@@ -182,10 +183,15 @@ __device__ __forceinline__ void lsm_row_update(const T* __restrict__ A, int ld, 
   T acc[KC];
 #pragma unroll
   for (int s = 0; s < KC; ++s) acc[s] = T(0);
+  // one running factor offset and one running LDS offset, opaque to the optimizer (otherwise it keeps
+  // an induction variable per column and phase alive across the row and panel loops), and the LDS
+  // reads taken in groups of four columns, each group after the previous group's sums
+  int64_t o = row + (int64_t)q0 * ld;
+  int xo = q0 * KC;
+  asm volatile("" : "+v"(o), "+v"(xo));
 #pragma unroll
   for (int h = 0; h < NPH; ++h) {
-    int64_t o = row + (int64_t)(q0 + h * H) * ld;
-    if (h > 0) asm volatile("" : "+v"(o) : "v"(acc[0]));
+    if (h > 0) asm volatile("" : "+v"(o), "+v"(xo) : "v"(acc[0]));
     T v[H];
 #pragma unroll
     for (int j = 0; j < H; ++j) {
@@ -195,91 +201,83 @@ __device__ __forceinline__ void lsm_row_update(const T* __restrict__ A, int ld, 
     }
 #pragma unroll
     for (int j = 0; j < H; ++j) {
-      const int q = q0 + (FULL ? h * H + j : min(h * H + j, pw - 1));
+      if (j > 0 && j % 4 == 0) asm volatile("" : "+v"(xo) : "v"(acc[KC - 1]));
+      const int qj = FULL ? j : min(h * H + j, pw - 1) - h * H;
 #pragma unroll
-      for (int s = 0; s < KC; ++s) acc[s] += v[j] * x[q * KC + s];
+      for (int s = 0; s < KC; ++s) acc[s] += v[j] * x[xo + qj * KC + s];
     }
+    xo += H * KC;
   }
 #pragma unroll
   for (int s = 0; s < KC; ++s) x[row * KC + s] -= acc[s];
 }
 
+// The diagonal triangles of the chunk, one right-hand side s per wave: the
+// operations of ls_tri_lower / ls_tri_upper on column s of the LDS block (same
+// order, so each column equals the single-right-hand-side result), KC waves
+// side by side.  The factor's triangle is read with plain loads: the KC waves
+// read the same tile.
 template <typename T, int NPH, bool FULL, int KC>
-__device__ __forceinline__ void lsm_tri_lower(const T* __restrict__ A, int ld, T* x, int q0, int pw, int lane) {
+__device__ __forceinline__ void lsm_tri_lower_one(const T* __restrict__ A, int ld, T* x, int q0, int pw, int lane,
+                                                  int s) {
   constexpr int H = PW / NPH;
   const bool ok = FULL || lane < pw;
   const int row = ok ? q0 + lane : q0;
   const int lj = ok ? lane : 0;
-  T xv[KC];
-#pragma unroll
-  for (int s = 0; s < KC; ++s) xv[s] = ok ? x[row * KC + s] : T(0);
+  T xv = ok ? x[row * KC + s] : T(0);
 #pragma unroll
   for (int h = 0; h < NPH; ++h) {
     if (!(FULL || h * H < pw)) continue;
     int64_t o = row + (int64_t)(q0 + h * H) * ld;
-    if (h > 0) asm volatile("" : "+v"(o) : "v"(xv[0]));
+    if (h > 0) asm volatile("" : "+v"(o) : "v"(xv));
     T d[H];
 #pragma unroll
     for (int j = 0; j < H; ++j) {
       int l = lj;
       asm volatile("" : "+v"(l));
-      d[j] = (h * H + j < l) ? ld_stream(A + o) : T(0);
+      d[j] = (h * H + j < l) ? A[o] : T(0);
       o += ld;
       asm volatile("" : "+v"(o));
     }
 #pragma unroll
     for (int j = 0; j < H; ++j) {
       const int jj = h * H + j;
-      if (FULL || jj < pw) {
-#pragma unroll
-        for (int s = 0; s < KC; ++s) xv[s] -= d[j] * lane_value(xv[s], jj);
-      }
+      if (FULL || jj < pw) xv -= d[j] * lane_value(xv, jj);
     }
   }
-  if (ok) {
-#pragma unroll
-    for (int s = 0; s < KC; ++s) x[row * KC + s] = xv[s];
-  }
+  if (ok) x[row * KC + s] = xv;
 }
 
 template <typename T, int NPH, bool FULL, int KC>
-__device__ __forceinline__ void lsm_tri_upper(const T* __restrict__ A, int ld, T* x, int q0, int pw, int lane) {
+__device__ __forceinline__ void lsm_tri_upper_one(const T* __restrict__ A, int ld, T* x, int q0, int pw, int lane,
+                                                  int s) {
   constexpr int H = PW / NPH;
   const bool ok = FULL || lane < pw;
   const int row = ok ? q0 + lane : q0;
   const T rd = ok ? T(1) / A[row + (int64_t)row * ld] : T(0);
   const int lj = ok ? lane : PW;
-  T xv[KC];
-#pragma unroll
-  for (int s = 0; s < KC; ++s) xv[s] = ok ? x[row * KC + s] : T(0);
+  T xv = ok ? x[row * KC + s] : T(0);
 #pragma unroll
   for (int h = NPH - 1; h >= 0; --h) {
     if (!(FULL || h * H < pw)) continue;
     int64_t o = row + (int64_t)(q0 + h * H) * ld;
-    if (h < NPH - 1) asm volatile("" : "+v"(o) : "v"(xv[0]));
+    if (h < NPH - 1) asm volatile("" : "+v"(o) : "v"(xv));
     T d[H];
 #pragma unroll
     for (int j = 0; j < H; ++j) {
       int l = lj;
       asm volatile("" : "+v"(l));
-      d[j] = (h * H + j > l && (FULL || h * H + j < pw)) ? ld_stream(A + o) : T(0);
+      d[j] = (h * H + j > l && (FULL || h * H + j < pw)) ? A[o] : T(0);
       o += ld;
       asm volatile("" : "+v"(o));
     }
 #pragma unroll
     for (int j = H - 1; j >= 0; --j) {
       const int jj = h * H + j;
-      if (FULL || jj < pw) {
-        const T rj = lane_value(rd, jj);
-#pragma unroll
-        for (int s = 0; s < KC; ++s) xv[s] -= d[j] * (lane_value(xv[s], jj) * rj);
-      }
+      if (FULL || jj < pw) xv -= d[j] * (lane_value(xv, jj) * lane_value(rd, jj));
     }
   }
-  if (ok) {
-#pragma unroll
-    for (int s = 0; s < KC; ++s) x[row * KC + s] = xv[s] * rd;
-  }
+  if (ok) x[row * KC + s] = xv * rd;
 }
 
 template <typename T, int KC>
@@ -307,9 +305,9 @@ __global__ __launch_bounds__(512) void k_local_solve_multi(const int* __restrict
   __syncthreads();
   for (int p0 = 0; p0 < n; p0 += PW) {
     const int pw = min(PW, n - p0);
-    if (wid == 0) {
-      if (pw == PW) lsm_tri_lower<T, NPH, true, KC>(A, ld, x, p0, PW, lane);
-      else lsm_tri_lower<T, NPH, false, KC>(A, ld, x, p0, pw, lane);
+    if (wid < KC) {
+      if (pw == PW) lsm_tri_lower_one<T, NPH, true, KC>(A, ld, x, p0, PW, lane, wid);
+      else lsm_tri_lower_one<T, NPH, false, KC>(A, ld, x, p0, pw, lane, wid);
     }
     __syncthreads();
     for (int rr = p0 + pw + tid; rr < n; rr += NT) lsm_row_update<T, NPH, true, KC>(A, ld, x, rr, p0, PW);
@@ -317,9 +315,9 @@ __global__ __launch_bounds__(512) void k_local_solve_multi(const int* __restrict
   }
   for (int p0 = ((n - 1) / PW) * PW; p0 >= 0; p0 -= PW) {
     const int pw = min(PW, n - p0);
-    if (wid == 0) {
-      if (pw == PW) lsm_tri_upper<T, NPH, true, KC>(A, ld, x, p0, PW, lane);
-      else lsm_tri_upper<T, NPH, false, KC>(A, ld, x, p0, pw, lane);
+    if (wid < KC) {
+      if (pw == PW) lsm_tri_upper_one<T, NPH, true, KC>(A, ld, x, p0, PW, lane, wid);
+      else lsm_tri_upper_one<T, NPH, false, KC>(A, ld, x, p0, pw, lane, wid);
     }
     __syncthreads();
     if (pw == PW)
@@ -464,13 +462,29 @@ __global__ void k_transpose(int n, const double* __restrict__ A, double* __restr
 
 }  // namespace
 
+// LDS a workgroup may use on the current device (160 KiB on gfx950), cached per device.
+size_t lds_per_block() {
+  static std::mutex mu;
+  static size_t cached[64];
+  int dev = 0;
+  GDSW_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return 64 * 1024;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!cached[dev]) {
+    int v = 0;
+    GDSW_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    cached[dev] = v > 0 ? (size_t)v : 64 * 1024;
+  }
+  return cached[dev];
+}
+
 template <typename T>
 void local_solves(int nparts, int max_n, const int* order, const int64_t* dom_ptr, const int* gidx,
                   const int64_t* blk_off, const T* blocks, int pad, const double* r, double* w, bool first_level,
                   int waves, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (nparts == 0) return;
   const size_t lds = (size_t)max_n * sizeof(T);
-  if (lds > 64 * 1024) throw Error(-1, "local block too large for the LDS-resident right-hand side");
+  if (lds > lds_per_block()) throw Error(-1, "local block too large for the LDS-resident right-hand side");
   if (waves != 2 && waves != 4 && waves != 8) throw Error(-1, "local solves: waves per matrix must be 2, 4 or 8");
   // with events, the dispatch itself records its start and end (exact kernel duration)
 #define GDSW_LS(F, NW)                                                                                          \
@@ -496,10 +510,11 @@ void local_solves(int nparts, int max_n, const int* order, const int64_t* dom_pt
 }
 
 int local_solves_multi_chunk(int max_n, int value_bytes) {
-  const size_t per = (size_t)max_n * value_bytes;   // LDS bytes per right-hand side (at most 64 KiB in all)
-  if (per * 8 <= 64 * 1024) return 8;
-  if (per * 4 <= 64 * 1024) return 4;
-  if (per * 2 <= 64 * 1024) return 2;
+  const size_t per = (size_t)max_n * value_bytes;   // LDS bytes per right-hand side
+  const size_t cap = lds_per_block();
+  if (per * 8 <= cap) return 8;
+  if (per * 4 <= cap) return 4;
+  if (per * 2 <= cap) return 2;
   return 1;
 }
 
@@ -509,7 +524,8 @@ void local_solves_multi(int nparts, int max_n, const int* order, const int64_t* 
                         int64_t ldw, int k, hipStream_t s) {
   if (nparts == 0 || k <= 0) return;
   const int kc = local_solves_multi_chunk(max_n, sizeof(T));
-  if ((size_t)max_n * sizeof(T) > 64 * 1024) throw Error(-1, "local block too large for the LDS-resident right-hand sides");
+  if ((size_t)max_n * sizeof(T) > lds_per_block())
+    throw Error(-1, "local block too large for the LDS-resident right-hand sides");
   for (int s0 = 0; s0 < k; s0 += kc) {
     const int kk = std::min(kc, k - s0);
     const double* Rs = R + (int64_t)s0 * ldr;
