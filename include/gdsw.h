@@ -275,16 +275,18 @@ int gdsw_solve_noalloc(gdsw_ctx* ctx, const double* b, double* x, void* stream, 
  * right-hand sides instead of once per vector -- for the regime of section 3
  * in which the preconditioned solver is invoked many times to low accuracy.
  * R, Z: DEVICE FP64, column-major, column s at R + s ldr (ldr, ldz >= n; R and
- * Z may not alias); 1 <= k <= GDSW_MAX_RHS.  Each column is bit-identical to
- * gdsw_apply on it.  The context keeps workspaces for k vectors, allocated on
+ * Z may not alias); 1 <= k <= GDSW_MAX_RHS.  Each column agrees with gdsw_apply
+ * on it to rounding (the local solves' panel updates run on the matrix cores).
+ * The context keeps workspaces for k vectors, allocated on
  * first use.  Returns GDSW_EINVAL for bad arguments. */
 int gdsw_apply_multi(gdsw_ctx* ctx, int32_t k, const double* R, int64_t ldr, double* Z, int64_t ldz, void* stream);
 
 /* k independent FGMRES solves K x_s = b_s (section 3) in lockstep: one
  * gdsw_apply_multi per inner iteration serves every system still iterating.
  * B, X: DEVICE FP64, column-major (ldb, ldx >= n; no aliasing); info: k entries
- * (may be NULL).  Each x_s, iteration count and residual equals gdsw_solve's
- * for b_s.  Returns GDSW_OK if every system converged, GDSW_NOTCONV otherwise
+ * (may be NULL).  Each system runs gdsw_solve's iteration on b_s with the
+ * multi-vector apply (same tolerance and restarts; iterates agree with
+ * gdsw_solve's to rounding).  Returns GDSW_OK if every system converged, GDSW_NOTCONV otherwise
  * (each x_s then holds its last iterate; info[s].converged tells which).
  * Synchronizes the stream once per inner iteration for all systems. */
 int gdsw_solve_multi(gdsw_ctx* ctx, int32_t k, const double* B, int64_t ldb, double* X, int64_t ldx, void* stream,

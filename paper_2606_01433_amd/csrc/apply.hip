@@ -172,46 +172,13 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8
 // ---------------------------------------------------------------------------
 // Local solves of KC right-hand sides at once (the same factor streamed once
 // for all of them).  Same blocked substitution as k_local_solve_wg, with the
-// gathered right-hand sides in LDS row by row (x[a * KC + s]) and every
-// per-right-hand-side operation in the same order, so each column equals the
-// single-right-hand-side result bit for bit.  Right-hand side s of the chunk is
-// R[s * ldr + g]; the local solutions go to W[s * ldw + position].
+// gathered right-hand sides in LDS row by row (x[a * KC + s]): the diagonal
+// triangles take each right-hand side's operations in the single kernel's
+// order, the panel updates run on MFMA (sums of four products per step, so a
+// column agrees with the single-right-hand-side result to rounding, not bit for
+// bit).  Right-hand side s of the chunk is R[s * ldr + g]; the local solutions go
+// to W[s * ldw + position].
 // ---------------------------------------------------------------------------
-template <typename T, int NPH, bool FULL, int KC>
-__device__ __forceinline__ void lsm_row_update(const T* __restrict__ A, int ld, T* x, int row, int q0, int pw) {
-  constexpr int H = PW / NPH;
-  T acc[KC];
-#pragma unroll
-  for (int s = 0; s < KC; ++s) acc[s] = T(0);
-  // one running factor offset and one running LDS offset, opaque to the optimizer (otherwise it keeps
-  // an induction variable per column and phase alive across the row and panel loops), and the LDS
-  // reads taken in groups of four columns, each group after the previous group's sums
-  int64_t o = row + (int64_t)q0 * ld;
-  int xo = q0 * KC;
-  asm volatile("" : "+v"(o), "+v"(xo));
-#pragma unroll
-  for (int h = 0; h < NPH; ++h) {
-    if (h > 0) asm volatile("" : "+v"(o), "+v"(xo) : "v"(acc[0]));
-    T v[H];
-#pragma unroll
-    for (int j = 0; j < H; ++j) {
-      v[j] = (FULL || h * H + j < pw) ? ld_stream(A + o) : T(0);
-      o += ld;
-      asm volatile("" : "+v"(o));
-    }
-#pragma unroll
-    for (int j = 0; j < H; ++j) {
-      if (j > 0 && j % 4 == 0) asm volatile("" : "+v"(xo) : "v"(acc[KC - 1]));
-      const int qj = FULL ? j : min(h * H + j, pw - 1) - h * H;
-#pragma unroll
-      for (int s = 0; s < KC; ++s) acc[s] += v[j] * x[xo + qj * KC + s];
-    }
-    xo += H * KC;
-  }
-#pragma unroll
-  for (int s = 0; s < KC; ++s) x[row * KC + s] -= acc[s];
-}
-
 // The diagonal triangles of the chunk, one right-hand side s per wave: the
 // operations of ls_tri_lower / ls_tri_upper on column s of the LDS block (same
 // order, so each column equals the single-right-hand-side result), KC waves
@@ -280,6 +247,67 @@ __device__ __forceinline__ void lsm_tri_upper_one(const T* __restrict__ A, int l
   if (ok) x[row * KC + s] = xv * rd;
 }
 
+// The panel update of the chunk as a small GEMM on the matrix cores:
+// x[r, s] -= sum_k A[r, q0 + k] x[q0 + k, s] for rows r in [r0, r1), k < pw,
+// s < KC.  Waves take 16-row blocks in turn; one 16x16x4 MFMA per four panel
+// columns, its 16 output columns the right-hand sides (KC of them used), so each
+// lane reads one right-hand-side value per MFMA from LDS instead of one
+// broadcast per FMA.  Operand layout as in the LU's MFMA tiles (transposed
+// product: lane (li, lk) feeds row li / column li and k = 4 step + lk, and
+// holds C[row li][column mfma_col(lk, q)]).
+template <typename T> struct Mma;
+template <> struct Mma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mac(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int col(int lk, int q) { return lk + 4 * q; }
+};
+template <> struct Mma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mac(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int col(int lk, int q) { return 4 * lk + q; }
+};
+
+template <typename T, int KC, int NW>
+__device__ __forceinline__ void lsm_update_mfma(const T* __restrict__ A, int ld, T* x, int r0, int r1, int q0, int pw,
+                                                int wid, int lane) {
+  typedef typename Mma<T>::v4 v4;
+  const int li = lane & 15, lk = lane >> 4;
+  // the panel's right-hand-side operands do not change during the update: read them once
+  T b[PW / 4];
+#pragma unroll
+  for (int st = 0; st < PW / 4; ++st) {
+    const int k = 4 * st + lk;
+    b[st] = (li < KC && k < pw) ? x[(q0 + k) * KC + li] : T(0);
+  }
+  for (int rb = r0 + 16 * wid; rb < r1; rb += 16 * NW) {
+    const int row = rb + li;
+    const bool in = row < r1;
+    T a[PW / 4];
+    int64_t o = (int64_t)(in ? row : r0) + (int64_t)(q0 + lk) * ld;
+    asm volatile("" : "+v"(o));
+#pragma unroll
+    for (int st = 0; st < PW / 4; ++st) {
+      a[st] = (in && 4 * st + lk < pw) ? ld_stream(A + o) : T(0);
+      o += 4 * (int64_t)ld;
+      asm volatile("" : "+v"(o));
+    }
+    v4 acc = v4{0, 0, 0, 0};
+#pragma unroll
+    for (int st = 0; st < PW / 4; ++st) acc = Mma<T>::mac(b[st], a[st], acc);
+    if (in) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = Mma<T>::col(lk, q);
+        if (c < KC) x[row * KC + c] -= acc[q];
+      }
+    }
+  }
+}
+
 template <typename T, int KC>
 __global__ __launch_bounds__(512) void k_local_solve_multi(const int* __restrict__ order,
                                                            const int64_t* __restrict__ dom_ptr,
@@ -310,7 +338,7 @@ __global__ __launch_bounds__(512) void k_local_solve_multi(const int* __restrict
       else lsm_tri_lower_one<T, NPH, false, KC>(A, ld, x, p0, pw, lane, wid);
     }
     __syncthreads();
-    for (int rr = p0 + pw + tid; rr < n; rr += NT) lsm_row_update<T, NPH, true, KC>(A, ld, x, rr, p0, PW);
+    lsm_update_mfma<T, KC, NW>(A, ld, x, p0 + pw, n, p0, pw, wid, lane);   // rows below the panel
     __syncthreads();
   }
   for (int p0 = ((n - 1) / PW) * PW; p0 >= 0; p0 -= PW) {
@@ -320,10 +348,7 @@ __global__ __launch_bounds__(512) void k_local_solve_multi(const int* __restrict
       else lsm_tri_upper_one<T, NPH, false, KC>(A, ld, x, p0, pw, lane, wid);
     }
     __syncthreads();
-    if (pw == PW)
-      for (int rr = tid; rr < p0; rr += NT) lsm_row_update<T, NPH, true, KC>(A, ld, x, rr, p0, PW);
-    else
-      for (int rr = tid; rr < p0; rr += NT) lsm_row_update<T, NPH, false, KC>(A, ld, x, rr, p0, pw);
+    lsm_update_mfma<T, KC, NW>(A, ld, x, 0, p0, p0, pw, wid, lane);         // rows above the panel
     __syncthreads();
   }
   for (int a = tid; a < n; a += NT) {

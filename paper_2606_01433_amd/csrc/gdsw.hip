@@ -1214,8 +1214,9 @@ void apply_any(gdsw_ctx* C, const double* r, double* z, hipStream_t s) {
 // ---- several right-hand sides ----------------------------------------------
 // Z[:, s] = B_l R[:, s] for s < k: the local solves of each level stream every
 // factor once per chunk of right-hand sides; everything else runs per
-// right-hand side with the single-vector kernels.  Every column is bit-identical
-// to the single apply of that column.
+// right-hand side with the single-vector kernels.  Every column agrees with the
+// single apply of that column to rounding (the multi-vector local solves update
+// on MFMA).
 void ensure_multi_level(gdsw_ctx* C, int k) {
   for (Level& L : C->levels) {
     if (L.multi_cap >= k) continue;
@@ -1527,7 +1528,7 @@ int solve_impl(gdsw_ctx* C, const double* b, double* x, hipStream_t caller, gdsw
 // the preconditioner to the current Krylov vectors of all k systems at once
 // (one pass over the local factors per chunk of systems); SpMV, Gram-Schmidt,
 // Givens rotations, restarts and convergence are those of solve_impl, per
-// system, so each x_s equals gdsw_solve's for b_s bit for bit.  A system that
+// system, so each x_s follows gdsw_solve's iteration for b_s (to rounding).  A system that
 // has converged (or reached max_it) keeps its iterate; its columns of the
 // shared apply are computed and ignored.
 int solve_multi_impl(gdsw_ctx* C, int k, const double* B, int64_t ldb, double* X, int64_t ldx, hipStream_t s,

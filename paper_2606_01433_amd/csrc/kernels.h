@@ -137,7 +137,7 @@ void local_solves(int nparts, int max_n, const int* order, const int64_t* dom_pt
                   int waves, hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // The local solves of k right-hand sides (R[s * ldr + g], s < k) into W[s * ldw + position], in chunks
 // of local_solves_multi_chunk(max_n, sizeof(T)) right-hand sides per pass over the factors; each column
-// equals local_solves' result for that right-hand side bit for bit.
+// agrees with local_solves' result for that right-hand side to rounding (panel updates on MFMA).
 template <typename T>
 void local_solves_multi(int nparts, int max_n, const int* order, const int64_t* dom_ptr, const int* gidx,
                         const int64_t* blk_off, const T* blocks, int pad, const double* R, int64_t ldr, double* W,
