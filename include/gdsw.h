@@ -180,7 +180,10 @@ typedef struct gdsw_stats {
   /* profile = 1 only: event-timed level-1 local-solve launches since setup */
   int64_t local_solve_launches;
   double ms_local_solve;          /* summed kernel time                         */
-  double local_solve_bytes;       /* algorithmic bytes of one launch: sum_i n_i^2 s + 20 n_i */
+  /* algorithmic bytes of one launch: sum_i (e_i s + 20 n_i), e_i = elements of the factor tiles
+   * the substitution reads (diagonal 64 x 64 tiles and off-diagonal tiles with a nonzero; n_i^2
+   * for blocks of more than 64 tiles per side) */
+  double local_solve_bytes;
   int32_t ls_waves[8];            /* wavefronts per matrix used by the local solves of level l */
   /* setup timeline from GPU events, in ms after the setup's first event on the caller's stream:
    * [l][0] begin and [l][1] end of level l+1's local factorization (side stream) and of its
@@ -192,7 +195,7 @@ typedef struct gdsw_stats {
    * factorization stream; other setup work runs concurrently on other streams) */
   double ms_lu[8];
   /* algorithmic bytes of one apply: sum over Schwarz levels and parts of
-   * n_i^2 s + 24 n_i (factor, pivoted index, gathered r, local solution, scattered z),
+   * e_i s + 24 n_i (factor tiles read, pivoted index, gathered r, local solution, scattered z),
    * plus 2 |Phi_I| s (restriction and prolongation), plus 8 n_c^2 (coarsest inverse);
    * s = 8 (FP64) or 4 (FP32 factors) */
   double apply_bytes;

@@ -129,7 +129,7 @@ template <typename T, bool FIRST, int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 4 : 1))) void k_local_solve_wg(
     const int* __restrict__ order, const int64_t* __restrict__ dom_ptr, const int* __restrict__ gidx,
     const int64_t* __restrict__ blk_off, const T* __restrict__ blocks, const double* __restrict__ r,
-    double* __restrict__ w, int pad) {
+    double* __restrict__ w, int pad, const int64_t* __restrict__ moff, const unsigned long long* __restrict__ tmask) {
   constexpr int NT = 64 * NW;
   constexpr int NPH = NW == 8 ? 2 : 1;
   extern __shared__ unsigned char smem_raw[];
@@ -140,30 +140,57 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8
   const T* A = blocks + blk_off[i];
   const int ld = lead_dim(n, pad);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  // tile masks of this block: nw words per 64-column panel, bit q of word (p, q / 64) set when
+  // the 64-row tile q of panel p holds a nonzero
+  const unsigned long long* M = tmask + moff[i];
+  const int nt = (n + PW - 1) / PW, nw = (nt + 63) >> 6;
   for (int a = tid; a < n; a += NT) x[a] = (T)r[gidx[base + a]];
   __syncthreads();
   for (int p0 = 0; p0 < n; p0 += PW) {
     const int pw = min(PW, n - p0);
+    const int p = p0 / PW;
     if (wid == 0) {
       if (pw == PW) ls_tri_lower<T, NPH, true>(A, ld, x, p0, PW, lane);
       else ls_tri_lower<T, NPH, false>(A, ld, x, p0, pw, lane);
     }
     __syncthreads();
-    // rows below a ragged (last) panel: none
-    for (int rr = p0 + pw + tid; rr < n; rr += NT) ls_row_update<T, NPH, true>(A, ld, x, rr, p0, PW);
+    // the nonzero row tiles below the panel (none below a ragged last panel), dealt to the
+    // wavefronts in turn
+    int k = 0;
+    for (int wi = (p + 1) >> 6; wi < nw; ++wi) {
+      unsigned long long bits = M[(int64_t)p * nw + wi];
+      if (wi == (p + 1) >> 6) bits &= ~0ull << ((p + 1) & 63);
+      for (; bits; ++k) {
+        const int q = wi * 64 + __builtin_ctzll(bits);
+        bits &= bits - 1;
+        const int rr = q * PW + lane;
+        if ((k & (NW - 1)) == wid && rr < n) ls_row_update<T, NPH, true>(A, ld, x, rr, p0, PW);
+      }
+    }
     __syncthreads();
   }
   for (int p0 = ((n - 1) / PW) * PW; p0 >= 0; p0 -= PW) {
     const int pw = min(PW, n - p0);
+    const int p = p0 / PW;
     if (wid == 0) {
       if (pw == PW) ls_tri_upper<T, NPH, true>(A, ld, x, p0, PW, lane);
       else ls_tri_upper<T, NPH, false>(A, ld, x, p0, pw, lane);
     }
     __syncthreads();
-    if (pw == PW)
-      for (int rr = tid; rr < p0; rr += NT) ls_row_update<T, NPH, true>(A, ld, x, rr, p0, PW);
-    else
-      for (int rr = tid; rr < p0; rr += NT) ls_row_update<T, NPH, false>(A, ld, x, rr, p0, pw);
+    // the nonzero row tiles above the panel (all their rows lie above it)
+    int k = 0;
+    for (int wi = 0; wi <= (p >> 6); ++wi) {
+      unsigned long long bits = M[(int64_t)p * nw + wi];
+      if (wi == (p >> 6)) bits &= (1ull << (p & 63)) - 1ull;
+      for (; bits; ++k) {
+        const int q = wi * 64 + __builtin_ctzll(bits);
+        bits &= bits - 1;
+        if ((k & (NW - 1)) != wid) continue;
+        const int rr = q * PW + lane;
+        if (pw == PW) ls_row_update<T, NPH, true>(A, ld, x, rr, p0, PW);
+        else ls_row_update<T, NPH, false>(A, ld, x, rr, p0, pw);
+      }
+    }
     __syncthreads();
   }
   for (int a = tid; a < n; a += NT) w[base + a] = (double)x[a];
@@ -503,10 +530,73 @@ size_t lds_per_block() {
   return cached[dev];
 }
 
+// Which 64 x 64 tiles of the stored LU factors hold a nonzero: with nt = ceil(n_i / 64) tiles per
+// side and nw = ceil(nt / 64) words per panel, bit q % 64 of tmask[moff[i] + p nw + q / 64] is set
+// when rows [64 q, 64 q + 64) x columns [64 p, 64 p + 64) of block i (q != p) have a nonzero entry
+// (q > p: the unit-lower factor, q < p: the upper one).  The substitution skips the other tiles:
+// their products are exact zeros, so its result is unchanged.  tmask must be zeroed beforehand.
+// kept[0] += the elements the substitution then reads (diagonal tiles and nonzero off-diagonal
+// tiles).  One workgroup per block; every element is read once.
+template <typename T>
+__global__ __launch_bounds__(512) void k_tile_mask(const int64_t* __restrict__ dom_ptr,
+                                                   const int64_t* __restrict__ blk_off, const T* __restrict__ blocks,
+                                                   int pad, const int64_t* __restrict__ moff,
+                                                   unsigned long long* __restrict__ tmask,
+                                                   unsigned long long* __restrict__ kept) {
+  __shared__ unsigned long long cnt;
+  const int i = blockIdx.x;
+  const int n = (int)(dom_ptr[i + 1] - dom_ptr[i]);
+  unsigned long long* M = tmask + moff[i];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int nt = (n + PW - 1) / PW, nw = (nt + 63) >> 6;
+  if (tid == 0) cnt = 0ull;
+  __syncthreads();
+  const T* A = blocks + blk_off[i];
+  const int ld = lead_dim(n, pad);
+  for (int64_t t = wid; t < (int64_t)nt * nt; t += 8) {
+    const int q = (int)(t / nt), p = (int)(t - (int64_t)q * nt);
+    if (q == p) continue;
+    const int row = q * PW + lane;
+    const int c0 = p * PW, c1 = min(n, c0 + PW);
+    bool nz = false;
+    if (row < n) {
+      int64_t o = row + (int64_t)c0 * ld;
+#pragma unroll 16
+      for (int c = c0; c < c1; ++c) {
+        nz |= ld_stream(A + o) != T(0);
+        o += ld;
+      }
+    }
+    if (__any(nz) && lane == 0) {
+      atomicOr(M + (int64_t)p * nw + (q >> 6), 1ull << (q & 63));
+      atomicAdd(&cnt, (unsigned long long)(min(n, q * PW + PW) - q * PW) * (unsigned long long)(c1 - c0));
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long diag = 0;
+    for (int p = 0; p < nt; ++p) {
+      const unsigned long long wp = (unsigned long long)min(PW, n - p * PW);
+      diag += wp * wp;
+    }
+    atomicAdd(kept, cnt + diag);
+  }
+}
+
+template <typename T>
+void tile_masks(int nparts, const int64_t* dom_ptr, const int64_t* blk_off, const T* blocks, int pad,
+                const int64_t* moff, unsigned long long* tmask, unsigned long long* kept, hipStream_t s) {
+  if (nparts == 0) return;
+  hipLaunchKernelGGL((k_tile_mask<T>), dim3(nparts), dim3(512), 0, s, dom_ptr, blk_off, blocks, pad, moff, tmask,
+                     kept);
+  GDSW_LAUNCH_CHECK();
+}
+
 template <typename T>
 void local_solves(int nparts, int max_n, const int* order, const int64_t* dom_ptr, const int* gidx,
-                  const int64_t* blk_off, const T* blocks, int pad, const double* r, double* w, bool first_level,
-                  int waves, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+                  const int64_t* blk_off, const T* blocks, int pad, const int64_t* moff,
+                  const unsigned long long* tmask, const double* r, double* w, bool first_level, int waves,
+                  hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (nparts == 0) return;
   const size_t lds = (size_t)max_n * sizeof(T);
   if (lds > lds_per_block()) throw Error(-1, "local block too large for the LDS-resident right-hand side");
@@ -516,10 +606,10 @@ void local_solves(int nparts, int max_n, const int* order, const int64_t* dom_pt
   do {                                                                                                          \
     if (ev_start)                                                                                               \
       hipExtLaunchKernelGGL((k_local_solve_wg<T, F, NW>), dim3(nparts), dim3(64 * NW), lds, s, ev_start, ev_stop, \
-                            0, order, dom_ptr, gidx, blk_off, blocks, r, w, pad);                               \
+                            0, order, dom_ptr, gidx, blk_off, blocks, r, w, pad, moff, tmask);                  \
     else                                                                                                        \
       hipLaunchKernelGGL((k_local_solve_wg<T, F, NW>), dim3(nparts), dim3(64 * NW), lds, s, order, dom_ptr,     \
-                         gidx, blk_off, blocks, r, w, pad);                                                     \
+                         gidx, blk_off, blocks, r, w, pad, moff, tmask);                                        \
   } while (0)
   if (first_level) {
     if (waves == 2) GDSW_LS(true, 2);
@@ -609,15 +699,20 @@ void dense_gemv_rows(int n, const double* AT, const double* x, double* y, hipStr
 }
 
 template void local_solves<double>(int, int, const int*, const int64_t*, const int*, const int64_t*,
-                                   const double*, int, const double*, double*, bool, int, hipStream_t, hipEvent_t,
-                                   hipEvent_t);
+                                   const double*, int, const int64_t*, const unsigned long long*, const double*,
+                                   double*, bool, int, hipStream_t, hipEvent_t, hipEvent_t);
 template void local_solves_multi<double>(int, int, const int*, const int64_t*, const int*, const int64_t*,
                                          const double*, int, const double*, int64_t, double*, int64_t, int,
                                          hipStream_t);
 template void local_solves_multi<float>(int, int, const int*, const int64_t*, const int*, const int64_t*,
                                         const float*, int, const double*, int64_t, double*, int64_t, int, hipStream_t);
 template void local_solves<float>(int, int, const int*, const int64_t*, const int*, const int64_t*, const float*, int,
-                                  const double*, double*, bool, int, hipStream_t, hipEvent_t, hipEvent_t);
+                                  const int64_t*, const unsigned long long*, const double*, double*, bool, int,
+                                  hipStream_t, hipEvent_t, hipEvent_t);
+template void tile_masks<double>(int, const int64_t*, const int64_t*, const double*, int, const int64_t*,
+                                 unsigned long long*, unsigned long long*, hipStream_t);
+template void tile_masks<float>(int, const int64_t*, const int64_t*, const float*, int, const int64_t*,
+                                unsigned long long*, unsigned long long*, hipStream_t);
 template void restrict_phi<double>(int, const int64_t*, const int*, const int64_t*, const int*, const int*,
                                    const int64_t*, const int*, const int64_t*, const double*, const double*, double*,
                                    hipStream_t);

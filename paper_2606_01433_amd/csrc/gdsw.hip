@@ -238,6 +238,9 @@ struct Level {
   int* gidx = nullptr;
   int* info = nullptr;
   int* order = nullptr;          // parts by decreasing block size (apply visiting order)
+  int64_t* tmask_off = nullptr;  // per part: offset of its nonzero-tile masks (see tile_masks)
+  unsigned long long* tmask = nullptr;
+  unsigned long long* tkept = nullptr;  // factor elements the masked substitution reads
   int ls_waves = 8;              // wavefronts per matrix of the local solves (2, 4 or 8); autotuned
                                  // with tune = 1
   int64_t* sc_ptr = nullptr;
@@ -509,6 +512,14 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
   std::vector<int> sc_pos;
   const std::string err = scatter_lists(m, L.n, C->opt.combine == GDSW_COMBINE_ADDITIVE, sc_ptr, sc_pos);
   if (!err.empty()) throw Error(GDSW_EINVAL, err);
+  // tile masks: ceil(nt / 64) 64-bit words per 64-column panel (nt panels per block)
+  std::vector<int64_t> tmask_off(N);
+  int64_t tmask_words = 0;
+  for (int i = 0; i < N; ++i) {
+    const int64_t nt = (L.dims[i] + 63) / 64;
+    tmask_off[i] = tmask_words;
+    tmask_words += nt * ((nt + 63) / 64);
+  }
   LuTiles tiles;
   tiles.build(L.dims.data(), N);
   int64_t *d_tiles_outer, *d_tiles_inner;
@@ -520,6 +531,7 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
   B.add(&L.blk_off, L.blk_off_h);
   B.add(&L.order, L.order_h);
   B.add(&L.dim, L.dims);
+  B.add(&L.tmask_off, tmask_off);
   if (!sc_ptr.empty()) B.add(&L.sc_ptr, sc_ptr);
   B.add(&L.sc_pos, sc_pos);
   B.flush(C, s);
@@ -602,6 +614,11 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
   GDSW_HIP(hipEventRecord(L.lu_ev[0], s));
   lu_batched<T>(b, blocks, s);
   GDSW_HIP(hipEventRecord(L.lu_ev[1], s));
+  L.tmask = A.alloc_n<unsigned long long>((size_t)std::max<int64_t>(1, tmask_words));
+  L.tkept = A.alloc_n<unsigned long long>(1);
+  GDSW_HIP(hipMemsetAsync(L.tmask, 0, (size_t)std::max<int64_t>(1, tmask_words) * sizeof(unsigned long long), s));
+  GDSW_HIP(hipMemsetAsync(L.tkept, 0, sizeof(unsigned long long), s));
+  tile_masks<T>(N, L.dom_ptr, L.blk_off, blocks, L.pad, L.tmask_off, L.tmask, L.tkept, s);
   L.perm = A.alloc_n<int>((size_t)L.sum_n);
   lu_build_perm(b, L.perm, s);
   L.gidx = A.alloc_n<int>((size_t)L.sum_n);
@@ -980,12 +997,6 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
   }
   const int schwarz = (int)C->levels.size();
   st.levels = schwarz + (coarsest ? 1 : 0);
-  for (int l = 0; l < schwarz && l < 8; ++l) {
-    double bytes = 0;
-    for (int d : C->levels[l].dims) bytes += (double)d * d * sizeof(T) + 20.0 * d;
-    st.local_solve_bytes_level[l] = bytes;
-    if (l == 0) st.local_solve_bytes = bytes;
-  }
   int ec0 = -1, ec1 = -1;
   double* dense = nullptr;
   int* cinfo = nullptr;
@@ -1065,12 +1076,21 @@ void setup_impl(gdsw_ctx* C, const gdsw_problem* p, hipStream_t s) {
         e = nullptr;
       }
   }
-  // algorithmic bytes of one apply: local factors and their gathers/stores on every Schwarz
-  // level, Phi_I read twice (restriction, prolongation), the coarsest dense inverse
+  // algorithmic bytes of one local-solve launch (the factor tiles the substitution reads, from the
+  // tile masks, and 20 bytes per row) and of one apply: local factor tiles and their gathers/stores
+  // on every Schwarz level, Phi_I read twice (restriction, prolongation), the coarsest dense inverse
   {
     double ab = 0;
-    for (const Level& L : C->levels) {
-      for (int d : L.dims) ab += (double)d * d * sizeof(T) + 24.0 * d;
+    for (size_t l = 0; l < C->levels.size(); ++l) {
+      const Level& L = C->levels[l];
+      unsigned long long kept = 0;
+      GDSW_HIP(hipMemcpy(&kept, L.tkept, sizeof(kept), hipMemcpyDeviceToHost));
+      double rows = 0;
+      for (int d : L.dims) rows += d;
+      const double bytes = (double)kept * sizeof(T) + 20.0 * rows;
+      if (l < 8) st.local_solve_bytes_level[l] = bytes;
+      if (l == 0) st.local_solve_bytes = bytes;
+      ab += (double)kept * sizeof(T) + 24.0 * rows;
       if (L.has_coarse) ab += 2.0 * (double)L.phi_elems * sizeof(T);
     }
     if (coarsest) ab += 8.0 * (double)C->nc * C->nc;
@@ -1135,7 +1155,7 @@ void tune_local_solves(gdsw_ctx* C, hipStream_t s) {
       for (int rep = 0; rep < 2; ++rep) {
         GDSW_HIP(hipEventRecord(e0, s));
         local_solves<T>(L.nparts, L.max_n, L.order, L.dom_ptr, L.gidx, L.blk_off, static_cast<const T*>(L.blocks),
-                        L.pad, r0, L.w, l == 0, wv, s);
+                        L.pad, L.tmask_off, L.tmask, r0, L.w, l == 0, wv, s);
         GDSW_HIP(hipEventRecord(e1, s));
         GDSW_HIP(hipEventSynchronize(e1));
         float ms = 0;
@@ -1196,7 +1216,7 @@ void apply_level(gdsw_ctx* C, int l, const double* r, double* z, hipStream_t s) 
     C->ev_level.push_back(l);
   }
   local_solves<T>(L.nparts, L.max_n, L.order, L.dom_ptr, L.gidx, L.blk_off, static_cast<const T*>(L.blocks), L.pad,
-                  r, L.w, l == 0, L.ls_waves, s, e_start, e_stop);
+                  L.tmask_off, L.tmask, r, L.w, l == 0, L.ls_waves, s, e_start, e_stop);
   scatter_sum(L.n, L.sc_ptr, L.sc_pos, L.w, z, s);
   if (!L.has_coarse) return;
   if (fork) GDSW_HIP(hipStreamWaitEvent(s, ev_join, 0));

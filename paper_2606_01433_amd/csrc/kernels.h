@@ -130,11 +130,19 @@ template <typename S, typename D> void convert(const S* in, D* out, int64_t n, h
 // ---- apply ----------------------------------------------------------------
 // w[k] = local solutions: per part, gather r at gidx, forward/backward TRSV with the LU in place.
 // order: part ids, largest block first (the visiting order of the workgroups);
-// waves: wavefronts per matrix (2, 4 or 8).
+// waves: wavefronts per matrix (2, 4 or 8).  moff/tmask: the nonzero-tile masks from tile_masks;
+// the substitution reads only those tiles (and the diagonal ones).
 template <typename T>
 void local_solves(int nparts, int max_n, const int* order, const int64_t* dom_ptr, const int* gidx,
-                  const int64_t* blk_off, const T* blocks, int pad, const double* r, double* w, bool first_level,
-                  int waves, hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+                  const int64_t* blk_off, const T* blocks, int pad, const int64_t* moff,
+                  const unsigned long long* tmask, const double* r, double* w, bool first_level, int waves,
+                  hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// Nonzero 64 x 64 tiles of the factored blocks: with nt tiles per side and nw = ceil(nt / 64),
+// bit q % 64 of tmask[moff[i] + p nw + q / 64] marks row tile q of column tile p (q != p);
+// tmask zeroed beforehand.  kept[0] += the factor elements the masked substitution reads.
+template <typename T>
+void tile_masks(int nparts, const int64_t* dom_ptr, const int64_t* blk_off, const T* blocks, int pad,
+                const int64_t* moff, unsigned long long* tmask, unsigned long long* kept, hipStream_t s);
 // The local solves of k right-hand sides (R[s * ldr + g], s < k) into W[s * ldw + position], in chunks
 // of local_solves_multi_chunk(max_n, sizeof(T)) right-hand sides per pass over the factors; each column
 // agrees with local_solves' result for that right-hand side to rounding (panel updates on MFMA).
