@@ -299,8 +299,8 @@ template <> struct Mma<float> {
 };
 
 template <typename T, int KC, int NW>
-__device__ __forceinline__ void lsm_update_mfma(const T* __restrict__ A, int ld, T* x, int r0, int r1, int q0, int pw,
-                                                int wid, int lane) {
+__device__ __forceinline__ void lsm_update_mfma(const T* __restrict__ A, int ld, T* x, const unsigned long long* M,
+                                                int t0, int t1, int r1, int q0, int pw, int wid, int lane) {
   typedef typename Mma<T>::v4 v4;
   const int li = lane & 15, lk = lane >> 4;
   // the panel's right-hand-side operands do not change during the update: read them once
@@ -310,26 +310,39 @@ __device__ __forceinline__ void lsm_update_mfma(const T* __restrict__ A, int ld,
     const int k = 4 * st + lk;
     b[st] = (li < KC && k < pw) ? x[(q0 + k) * KC + li] : T(0);
   }
-  for (int rb = r0 + 16 * wid; rb < r1; rb += 16 * NW) {
-    const int row = rb + li;
-    const bool in = row < r1;
-    T a[PW / 4];
-    int64_t o = (int64_t)(in ? row : r0) + (int64_t)(q0 + lk) * ld;
-    asm volatile("" : "+v"(o));
+  // the 16-row blocks of the nonzero 64-row tiles t0 <= q < t1, dealt to the wavefronts in turn
+  int k = 0;
+  for (int wi = t0 >> 6; t0 < t1 && wi <= (t1 - 1) >> 6; ++wi) {
+    unsigned long long bits = M[wi];
+    if (wi == t0 >> 6) bits &= ~0ull << (t0 & 63);
+    if (wi == (t1 - 1) >> 6 && ((t1 - 1) & 63) < 63) bits &= (1ull << (((t1 - 1) & 63) + 1)) - 1ull;
+    while (bits) {
+      const int q = wi * 64 + __builtin_ctzll(bits);
+      bits &= bits - 1;
+      for (int sb = 0; sb < PW / 16; ++sb, ++k) {
+        const int rb = q * PW + 16 * sb;
+        if ((k & (NW - 1)) != wid || rb >= r1) continue;
+        const int row = rb + li;
+        const bool in = row < r1;
+        T a[PW / 4];
+        int64_t o = (int64_t)(in ? row : rb) + (int64_t)(q0 + lk) * ld;
+        asm volatile("" : "+v"(o));
 #pragma unroll
-    for (int st = 0; st < PW / 4; ++st) {
-      a[st] = (in && 4 * st + lk < pw) ? ld_stream(A + o) : T(0);
-      o += 4 * (int64_t)ld;
-      asm volatile("" : "+v"(o));
-    }
-    v4 acc = v4{0, 0, 0, 0};
+        for (int st = 0; st < PW / 4; ++st) {
+          a[st] = (in && 4 * st + lk < pw) ? ld_stream(A + o) : T(0);
+          o += 4 * (int64_t)ld;
+          asm volatile("" : "+v"(o));
+        }
+        v4 acc = v4{0, 0, 0, 0};
 #pragma unroll
-    for (int st = 0; st < PW / 4; ++st) acc = Mma<T>::mac(b[st], a[st], acc);
-    if (in) {
+        for (int st = 0; st < PW / 4; ++st) acc = Mma<T>::mac(b[st], a[st], acc);
+        if (in) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int c = Mma<T>::col(lk, q);
-        if (c < KC) x[row * KC + c] -= acc[q];
+          for (int q2 = 0; q2 < 4; ++q2) {
+            const int c = Mma<T>::col(lk, q2);
+            if (c < KC) x[row * KC + c] -= acc[q2];
+          }
+        }
       }
     }
   }
@@ -342,7 +355,8 @@ __global__ __launch_bounds__(512) void k_local_solve_multi(const int* __restrict
                                                            const int64_t* __restrict__ blk_off,
                                                            const T* __restrict__ blocks, const double* __restrict__ R,
                                                            int64_t ldr, double* __restrict__ W, int64_t ldw, int kk,
-                                                           int pad) {
+                                                           int pad, const int64_t* __restrict__ moff,
+                                                           const unsigned long long* __restrict__ tmask) {
   constexpr int NW = 8, NT = 64 * NW, NPH = 2;
   extern __shared__ unsigned char smem_raw[];
   T* x = reinterpret_cast<T*>(smem_raw);
@@ -352,6 +366,8 @@ __global__ __launch_bounds__(512) void k_local_solve_multi(const int* __restrict
   const T* A = blocks + blk_off[i];
   const int ld = lead_dim(n, pad);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const unsigned long long* M = tmask + moff[i];   // nonzero-tile masks (see k_tile_mask)
+  const int nt = (n + PW - 1) / PW, nw = (nt + 63) >> 6;
   for (int a = tid; a < n; a += NT) {
     const int g = gidx[base + a];
 #pragma unroll
@@ -365,7 +381,8 @@ __global__ __launch_bounds__(512) void k_local_solve_multi(const int* __restrict
       else lsm_tri_lower_one<T, NPH, false, KC>(A, ld, x, p0, pw, lane, wid);
     }
     __syncthreads();
-    lsm_update_mfma<T, KC, NW>(A, ld, x, p0 + pw, n, p0, pw, wid, lane);   // rows below the panel
+    lsm_update_mfma<T, KC, NW>(A, ld, x, M + (int64_t)(p0 / PW) * nw, p0 / PW + 1, nt, n, p0, pw, wid,
+                               lane);   // rows below the panel
     __syncthreads();
   }
   for (int p0 = ((n - 1) / PW) * PW; p0 >= 0; p0 -= PW) {
@@ -375,7 +392,8 @@ __global__ __launch_bounds__(512) void k_local_solve_multi(const int* __restrict
       else lsm_tri_upper_one<T, NPH, false, KC>(A, ld, x, p0, pw, lane, wid);
     }
     __syncthreads();
-    lsm_update_mfma<T, KC, NW>(A, ld, x, 0, p0, p0, pw, wid, lane);         // rows above the panel
+    lsm_update_mfma<T, KC, NW>(A, ld, x, M + (int64_t)(p0 / PW) * nw, 0, p0 / PW, p0, p0, pw, wid,
+                               lane);   // rows above the panel
     __syncthreads();
   }
   for (int a = tid; a < n; a += NT) {
@@ -635,8 +653,9 @@ int local_solves_multi_chunk(int max_n, int value_bytes) {
 
 template <typename T>
 void local_solves_multi(int nparts, int max_n, const int* order, const int64_t* dom_ptr, const int* gidx,
-                        const int64_t* blk_off, const T* blocks, int pad, const double* R, int64_t ldr, double* W,
-                        int64_t ldw, int k, hipStream_t s) {
+                        const int64_t* blk_off, const T* blocks, int pad, const int64_t* moff,
+                        const unsigned long long* tmask, const double* R, int64_t ldr, double* W, int64_t ldw, int k,
+                        hipStream_t s) {
   if (nparts == 0 || k <= 0) return;
   const int kc = local_solves_multi_chunk(max_n, sizeof(T));
   if ((size_t)max_n * sizeof(T) > lds_per_block())
@@ -648,7 +667,7 @@ void local_solves_multi(int nparts, int max_n, const int* order, const int64_t* 
     const size_t lds = (size_t)max_n * sizeof(T) * kc;
 #define GDSW_LSM(KC)                                                                                              \
   hipLaunchKernelGGL((k_local_solve_multi<T, KC>), dim3(nparts), dim3(512), lds, s, order, dom_ptr, gidx, blk_off, \
-                     blocks, Rs, ldr, Ws, ldw, kk, pad)
+                     blocks, Rs, ldr, Ws, ldw, kk, pad, moff, tmask)
     if (kc == 8) GDSW_LSM(8);
     else if (kc == 4) GDSW_LSM(4);
     else if (kc == 2) GDSW_LSM(2);
@@ -702,10 +721,11 @@ template void local_solves<double>(int, int, const int*, const int64_t*, const i
                                    const double*, int, const int64_t*, const unsigned long long*, const double*,
                                    double*, bool, int, hipStream_t, hipEvent_t, hipEvent_t);
 template void local_solves_multi<double>(int, int, const int*, const int64_t*, const int*, const int64_t*,
-                                         const double*, int, const double*, int64_t, double*, int64_t, int,
-                                         hipStream_t);
+                                         const double*, int, const int64_t*, const unsigned long long*,
+                                         const double*, int64_t, double*, int64_t, int, hipStream_t);
 template void local_solves_multi<float>(int, int, const int*, const int64_t*, const int*, const int64_t*,
-                                        const float*, int, const double*, int64_t, double*, int64_t, int, hipStream_t);
+                                        const float*, int, const int64_t*, const unsigned long long*, const double*,
+                                        int64_t, double*, int64_t, int, hipStream_t);
 template void local_solves<float>(int, int, const int*, const int64_t*, const int*, const int64_t*, const float*, int,
                                   const int64_t*, const unsigned long long*, const double*, double*, bool, int,
                                   hipStream_t, hipEvent_t, hipEvent_t);

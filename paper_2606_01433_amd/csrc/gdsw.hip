@@ -1280,7 +1280,7 @@ void apply_level_multi(gdsw_ctx* C, int l, const double* R, int64_t ldr, double*
     GDSW_HIP(hipEventRecord(C->ev_join, C->side));
   }
   local_solves_multi<T>(L.nparts, L.max_n, L.order, L.dom_ptr, L.gidx, L.blk_off, static_cast<const T*>(L.blocks),
-                        L.pad, R, ldr, L.wm, L.sum_n, k, s);
+                        L.pad, L.tmask_off, L.tmask, R, ldr, L.wm, L.sum_n, k, s);
   for (int q = 0; q < k; ++q) scatter_sum(L.n, L.sc_ptr, L.sc_pos, L.wm + q * L.sum_n, Z + q * ldz, s);
   if (!L.has_coarse) return;
   if (fork) GDSW_HIP(hipStreamWaitEvent(s, C->ev_join, 0));

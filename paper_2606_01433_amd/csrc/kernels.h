@@ -148,8 +148,9 @@ void tile_masks(int nparts, const int64_t* dom_ptr, const int64_t* blk_off, cons
 // agrees with local_solves' result for that right-hand side to rounding (panel updates on MFMA).
 template <typename T>
 void local_solves_multi(int nparts, int max_n, const int* order, const int64_t* dom_ptr, const int* gidx,
-                        const int64_t* blk_off, const T* blocks, int pad, const double* R, int64_t ldr, double* W,
-                        int64_t ldw, int k, hipStream_t s);
+                        const int64_t* blk_off, const T* blocks, int pad, const int64_t* moff,
+                        const unsigned long long* tmask, const double* R, int64_t ldr, double* W, int64_t ldw, int k,
+                        hipStream_t s);
 int local_solves_multi_chunk(int max_n, int value_bytes);
 // z[g] = 0.0 + sum_k w[pos[k]] over sc_ptr[g]..sc_ptr[g+1]; with sc_ptr == nullptr, z[g] = 0.0 + w[pos[g]]
 void scatter_sum(int64_t n, const int64_t* sc_ptr, const int* sc_pos, const double* w, double* z, hipStream_t s);
