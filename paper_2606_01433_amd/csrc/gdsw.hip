@@ -559,6 +559,8 @@ void factor_level(gdsw_ctx* C, Level& L, hipStream_t s) {
   b.wide = true;
   b.ut = A.alloc_n<T>((size_t)128 * L.sum_n);
   C->setup_scratch.push_back(b.ut);
+  b.step_masks = A.alloc_n<unsigned long long>((size_t)2 * N);
+  C->setup_scratch.push_back(b.step_masks);
   std::vector<int> sorted_dims(N);
   for (int q = 0; q < N; ++q) sorted_dims[q] = L.dims[L.order_h[q]];
   b.order = L.order;
@@ -727,6 +729,8 @@ CsrDev coarse_level(gdsw_ctx* C, Level& L, hipStream_t s, std::vector<int64_t>& 
   b.wide = true;
   b.ut = A.alloc_n<T>((size_t)128 * m.inter.size());
   C->setup_scratch.push_back(b.ut);
+  b.step_masks = A.alloc_n<unsigned long long>((size_t)2 * N);
+  C->setup_scratch.push_back(b.step_masks);
   lu_batched<T>(b, aii, s);
   T* phi;
   if (sizeof(T) == sizeof(double)) {

@@ -49,6 +49,10 @@ struct LuBatch {
   int panel_classes = 0;
   const int* order = nullptr;
   const int* order_dims = nullptr;
+  // Optional device scratch of 2 * count words (wide steps only): before each rank-128 trailing
+  // update, which 64-row tiles of L21 and 64-column tiles of U12 hold a nonzero; the update skips
+  // the C tiles whose product is an exact zero (same result).
+  unsigned long long* step_masks = nullptr;
 };
 size_t lu_tall_scratch_bytes(int n, int value_bytes);
 // X = A^{-1} (column-major) of a single LU-factored FP64 matrix (b.count == 1, b.off

@@ -932,19 +932,76 @@ __global__ __launch_bounds__(256) void k_lu_update(T* __restrict__ Ab, const int
                                     A + k + (int64_t)c0 * ld, ld, M, N, kw, ty, tx);
 }
 
+// Zero tiles of the operands of the rank-4NB trailing update of the pair at k0 (wide steps):
+// bit t of masks[2 i] is set when rows [r0 + 64 t, r0 + 64 t + 64) of columns [k0, k0 + 4NB) of
+// matrix i (L21, r0 = k0 + 4NB) hold a nonzero, bit t of masks[2 i + 1] when columns
+// [c0 + 64 t, ...) of the 4NB rows of U12 (row-major scratch, c0 = k0 + 4NB) do.  Tiles from the
+// 65th on are not tracked (k_lu_update_ut treats them as nonzero).  One workgroup per matrix.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_step_masks(const T* __restrict__ Ab, const int64_t* __restrict__ off,
+                                                       const int* __restrict__ dim, int k0, int pad,
+                                                       const T* __restrict__ ut, const int64_t* __restrict__ poff,
+                                                       int ut_rows, unsigned long long* __restrict__ masks) {
+  __shared__ unsigned long long lm, um;
+  constexpr int KW = 4 * LU_NB;
+  const int i = blockIdx.x;
+  const int n = dim[i];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (tid == 0) lm = um = 0ull;
+  __syncthreads();
+  const int r0 = k0 + KW;
+  if (r0 < n) {
+    const int ld = lead_dim(n, pad);
+    const T* A = Ab + off[i];
+    const int tl = min(64, (n - r0 + TILE - 1) / TILE);
+    for (int t = wid; t < tl; t += 4) {          // L21: lane = row, over the 4NB columns
+      const int row = r0 + t * TILE + lane;
+      bool nz = false;
+      if (row < n) {
+        int64_t o = row + (int64_t)k0 * ld;
+#pragma unroll 16
+        for (int c = 0; c < KW; ++c) {
+          nz |= A[o] != T(0);
+          o += ld;
+        }
+      }
+      if (__any(nz) && lane == 0) atomicOr(&lm, 1ull << t);
+    }
+    const int urow = n - k0 - 2 * LU_NB;        // U12 rows: columns k0 + 2NB ... n - 1
+    const T* U = ut + (int64_t)ut_rows * poff[i] + (r0 - k0 - 2 * LU_NB);
+    for (int t = wid; t < tl; t += 4) {          // U12: lane = column, over the 4NB rows
+      const int c = t * TILE + lane;
+      bool nz = false;
+      if (r0 + c < n) {
+        const T* u = U + c;
+#pragma unroll 16
+        for (int k = 0; k < KW; ++k) nz |= u[(int64_t)k * urow] != T(0);
+      }
+      if (__any(nz) && lane == 0) atomicOr(&um, 1ull << t);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    masks[2 * i] = lm;
+    masks[2 * i + 1] = um;
+  }
+}
+
 // Updates of the paired-step factorization (lu_batched, wide): with k0 the
 // first column of the pair,
 //   A[r0 : r0 + M, c0 : c1) -= A[r0 : r0 + M, k0 : k0 + kw) * U[0 : kw, c0 : c1)
 // r0 = k0 + r0_rel, M = min(n - r0, m_cap), c0 = k0 + c0_rel, c1 = k0 + c1_rel (n if c1_rel < 0).
 // U's rows come from the row-major scratch (rows of length n - k0 - 64 starting
 // at column k0 + 64, matrix i at ut_rows * poff[i]).
+// masks (may be null): words 2i and 2i + 1 from k_lu_step_masks; a C tile whose 64 rows of the A
+// operand or 64 columns of U are all zero is left as it is (its product is an exact zero).
 template <typename T, int KMAX>
 __global__ __launch_bounds__(256) void k_lu_update_ut(T* __restrict__ Ab, const int64_t* __restrict__ off,
                                                       const int* __restrict__ dim, int k0, int r0_rel, int m_cap,
                                                       int c0_rel, int c1_rel, int kw, int tiles_m, int tiles_n,
                                                       const int64_t* __restrict__ tab, int count, int pad,
                                                       const T* __restrict__ ut, const int64_t* __restrict__ poff,
-                                                      int ut_rows) {
+                                                      int ut_rows, const unsigned long long* __restrict__ masks) {
   const int w = (int)xcd_remap(blockIdx.x, gridDim.x);
   int i, tl;
   if (tab) {
@@ -966,6 +1023,10 @@ __global__ __launch_bounds__(256) void k_lu_update_ut(T* __restrict__ Ab, const 
   const int tm = tab ? (M + TILE - 1) / TILE : tiles_m;
   const int ty = tl % tm, tx = tl / tm;
   if (ty * TILE >= M || tx * TILE >= N) return;
+  if (masks) {
+    const unsigned long long lm = masks[2 * i], um = masks[2 * i + 1];
+    if ((ty < 64 && !((lm >> ty) & 1ull)) || (tx < 64 && !((um >> tx) & 1ull))) return;
+  }
   const int ld = lead_dim(n, pad);
   T* A = Ab + off[i];
   const int urow = n - k0 - 2 * LU_NB;
@@ -1545,7 +1606,7 @@ void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
         const int tm = (int)blocks_for(rest_a, TILE);
         hipLaunchKernelGGL((k_lu_update_ut<T, 2 * NB>), dim3((unsigned)((int64_t)b.count * tm)), dim3(256), 0, s, A,
                            b.off, b.dim, k0, 2 * NB, (int)huge, 2 * NB, 4 * NB, 2 * NB, tm, 1, nullptr, b.count, b.pad,
-                           static_cast<const T*>(ut), b.poff, 4 * NB);
+                           static_cast<const T*>(ut), b.poff, 4 * NB, nullptr);
         GDSW_LAUNCH_CHECK();
       }
       block(k0 + 2 * NB);
@@ -1558,7 +1619,7 @@ void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
         const int tn = (int)blocks_for(rest_b, TILE);
         hipLaunchKernelGGL((k_lu_update_ut<T, 2 * NB>), dim3((unsigned)((int64_t)b.count * tn)), dim3(256), 0, s, A,
                            b.off, b.dim, k0, 2 * NB, 2 * NB, 4 * NB, -1, 2 * NB, 1, tn, nullptr, b.count, b.pad,
-                           static_cast<const T*>(ut), b.poff, 4 * NB);
+                           static_cast<const T*>(ut), b.poff, 4 * NB, nullptr);
         GDSW_LAUNCH_CHECK();
       }
       trsm(k0 + 2 * NB, rest_b, 0, 4 * NB, 2 * NB, k0);
@@ -1567,10 +1628,16 @@ void lu_batched(const LuBatch& b, T* A, hipStream_t s) {
         const int st = k0 / (2 * NB) + 1;
         const int64_t grid = b.tiles_outer ? b.total_outer[st] : (int64_t)b.count * t * t;
         if (grid > 0) {
+          if (b.step_masks) {
+            hipLaunchKernelGGL((k_lu_step_masks<T>), dim3(b.count), dim3(256), 0, s, A, b.off, b.dim, k0, b.pad,
+                               static_cast<const T*>(ut), b.poff, 4 * NB, b.step_masks);
+            GDSW_LAUNCH_CHECK();
+          }
           hipLaunchKernelGGL((k_lu_update_ut<T, 4 * NB>), dim3((unsigned)grid), dim3(256), 0, s, A, b.off, b.dim, k0,
                              4 * NB, (int)huge, 4 * NB, -1, 4 * NB, t, t,
                              b.tiles_outer ? b.tiles_outer + (size_t)st * (b.count + 1) : nullptr, b.count, b.pad,
-                             static_cast<const T*>(ut), b.poff, 4 * NB);
+                             static_cast<const T*>(ut), b.poff, 4 * NB,
+                             static_cast<const unsigned long long*>(b.step_masks));
           GDSW_LAUNCH_CHECK();
         }
       }
