@@ -28,3 +28,17 @@ def test_table1_efficiencies():
 def test_percentile_nearest_rank():
     xs = list(range(1, 101))
     assert percentile(xs, 50) == 50 and percentile(xs, 99) == 99 and percentile([5.0], 99) == 5.0
+
+
+def test_bench_traffic_entries_match_the_local_solve_source():
+    """The HBM traffic bench.py attaches to its roofline was measured on the current local-solve source
+    (otherwise it reports null): every recorded entry carries the hash of the kernel it was taken on."""
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import bench
+    h = bench.local_solve_source_hash()
+    assert bench.LOCAL_SOLVE_TRAFFIC
+    for key, rec in bench.LOCAL_SOLVE_TRAFFIC.items():
+        assert rec["source_hash"] == h, key
+        assert rec["bytes"] > 0
