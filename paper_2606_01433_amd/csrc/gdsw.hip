@@ -391,8 +391,8 @@ void wait_uploads(gdsw_ctx* C, hipStream_t s) {
 // one device allocation; each destination pointer is set to its slice.
 class UploadBatch {
  public:
-  template <typename T>
-  void add(T** dst, const std::vector<T>& v) {
+  template <typename T, typename A>
+  void add(T** dst, const std::vector<T, A>& v) {
     entries_.push_back({reinterpret_cast<void**>(dst), v.data(), v.size() * sizeof(T), total_});
     total_ += (v.size() * sizeof(T) + 255) & ~size_t(255);
   }

@@ -119,7 +119,8 @@ void parallel_for(int n, int nthreads, F f) {
 
 // Sort and deduplicate each segment of a CSR list (segments in parallel), then
 // compact in place.
-void sort_unique_segments(std::vector<int64_t>& ptr, std::vector<int>& val) {
+template <typename V>
+void sort_unique_segments(std::vector<int64_t>& ptr, V& val) {
   const int nseg = (int)ptr.size() - 1;
   if (nseg <= 0) return;
   std::vector<int> cnt(nseg);
@@ -140,13 +141,16 @@ void sort_unique_segments(std::vector<int64_t>& ptr, std::vector<int>& val) {
   val.resize(w);
 }
 
-// elements containing each node (CSR)
-void node_elements(const LevelMesh& mesh, std::vector<int64_t>& ptr, std::vector<int>& el) {
-  if (!mesh.ne_ptr.empty()) {
-    ptr = mesh.ne_ptr;
-    el = mesh.ne;
-    return;
-  }
+// v = n copies of x, written in parallel
+void fill_n_parallel(RawVec<int>& v, int64_t n, int x) {
+  v.resize(n);
+  parallel_for((int)((n + 4095) / 4096), host_threads(), [&](int, int b0, int b1) {
+    std::fill(v.begin() + (int64_t)b0 * 4096, v.begin() + std::min<int64_t>(n, (int64_t)b1 * 4096), x);
+  });
+}
+
+// elements containing each node (CSR, ascending), for meshes whose builder did not make them
+void node_elements(const LevelMesh& mesh, std::vector<int64_t>& ptr, RawVec<int>& el) {
   ptr.assign(mesh.n_nodes + 1, 0);
   for (int e = 0; e < mesh.n_elem; ++e)
     for (int64_t k = mesh.en_ptr[e]; k < mesh.en_ptr[e + 1]; ++k) ptr[mesh.en[k] + 1]++;
@@ -191,30 +195,49 @@ std::string build_level1_mesh(int64_t n, int n_nodes, const int* node_dof, int n
   out.n_nodes = n_nodes;
   out.node_dof.assign(node_dof, node_dof + (size_t)n_nodes * 3);
   out.n_elem = n_elem;
-  out.en.assign(elem_node, elem_node + (size_t)n_elem * 27);
+  const int nt = host_threads();
+  out.en.resize((size_t)n_elem * 27);
+  parallel_for(n_elem, nt, [&](int, int e0, int e1) {
+    std::copy(elem_node + (size_t)e0 * 27, elem_node + (size_t)e1 * 27, out.en.begin() + (size_t)e0 * 27);
+  });
   out.en_ptr.resize(n_elem + 1);
   for (int e = 0; e <= n_elem; ++e) out.en_ptr[e] = (int64_t)e * 27;
   out.elem_pdof.assign(elem_pdof, elem_pdof + (size_t)n_elem * 4);
   out.elem_part.assign(elem_part, elem_part + n_elem);
   out.n_parts = n_parts;
-  // every free dof exactly once
-  std::vector<char> seen(n, 0);
-  auto mark = [&](int g) -> bool {
-    if (g < -1 || g >= n) return false;
-    if (g >= 0) {
-      if (seen[g]) return false;
-      seen[g] = 1;
-    }
-    return true;
+  // every free dof exactly once: node_dof marked first, then elem_pdof (in parallel; the second mark
+  // of an id, whichever thread makes it, is a repeat)
+  std::unique_ptr<std::atomic<unsigned char>[]> seen(new std::atomic<unsigned char>[n]);
+  parallel_for((int)n, nt, [&](int, int g0, int g1) {
+    for (int g = g0; g < g1; ++g) seen[g].store(0, std::memory_order_relaxed);
+  });
+  std::atomic<bool> bad(false);
+  auto mark_all = [&](const std::vector<int>& ids) {
+    parallel_for((int)ids.size(), nt, [&](int, int k0, int k1) {
+      for (int k = k0; k < k1; ++k) {
+        const int g = ids[k];
+        if (g < -1 || g >= n || (g >= 0 && seen[g].exchange(1, std::memory_order_relaxed))) bad = true;
+      }
+    });
+    return !bad.load();
   };
-  for (size_t k = 0; k < out.node_dof.size(); ++k)
-    if (!mark(out.node_dof[k])) return "node_dof: id out of range or repeated";
-  for (size_t k = 0; k < out.elem_pdof.size(); ++k)
-    if (!mark(out.elem_pdof[k])) return "elem_pdof: id out of range or repeated";
-  for (int64_t g = 0; g < n; ++g)
-    if (!seen[g]) return "dof " + std::to_string(g) + " is not referenced by node_dof/elem_pdof";
-  for (int v : out.en)
-    if (v < 0 || v >= n_nodes) return "elem_node: node id out of range";
+  if (!mark_all(out.node_dof)) return "node_dof: id out of range or repeated";
+  if (!mark_all(out.elem_pdof)) return "elem_pdof: id out of range or repeated";
+  std::atomic<int64_t> missing(n);
+  parallel_for((int)n, nt, [&](int, int g0, int g1) {
+    for (int g = g0; g < g1; ++g)
+      if (!seen[g].load(std::memory_order_relaxed)) {
+        int64_t cur = missing.load();
+        while (g < cur && !missing.compare_exchange_weak(cur, g)) {
+        }
+      }
+  });
+  if (missing.load() < n) return "dof " + std::to_string(missing.load()) + " is not referenced by node_dof/elem_pdof";
+  parallel_for(n_elem, nt, [&](int, int e0, int e1) {
+    for (size_t k = (size_t)e0 * 27; k < (size_t)e1 * 27; ++k)
+      if (out.en[k] < 0 || out.en[k] >= n_nodes) bad = true;
+  });
+  if (bad.load()) return "elem_node: node id out of range";
   std::vector<int> cnt(n_parts, 0);
   for (int p : out.elem_part) {
     if (p < 0 || p >= n_parts) return "elem_part: part id out of range";
@@ -224,18 +247,48 @@ std::string build_level1_mesh(int64_t n, int n_nodes, const int* node_dof, int n
     if (!cnt[i]) return "level-1 part " + std::to_string(i) + " has no element";
   // node graph: two nodes of one element whose lattice offsets differ by at most one per axis
   // (at most 26 neighbours per node), built node by node from the elements holding it
+  // node -> (element, position) lists, ascending by element then position: counted and filled in
+  // parallel with per-node atomic counters, then each node's few entries sorted
   std::vector<int64_t> ne_ptr(n_nodes + 1, 0);
-  for (int v : out.en) ne_ptr[v + 1]++;
-  for (int v = 0; v < n_nodes; ++v) ne_ptr[v + 1] += ne_ptr[v];
-  std::vector<int> ne_el(ne_ptr[n_nodes]), ne_loc(ne_ptr[n_nodes]);
+  RawVec<int> ne_el, ne_loc;
   {
-    std::vector<int64_t> fill(ne_ptr.begin(), ne_ptr.end() - 1);
-    for (int e = 0; e < n_elem; ++e)
-      for (int a = 0; a < 27; ++a) {
-        const int v = out.en[(size_t)e * 27 + a];
-        ne_el[fill[v]] = e;
-        ne_loc[fill[v]++] = a;
-      }
+    std::unique_ptr<std::atomic<int>[]> c(new std::atomic<int>[n_nodes]);
+    auto zero = [&] {
+      parallel_for(n_nodes, nt, [&](int, int v0, int v1) {
+        for (int v = v0; v < v1; ++v) c[v].store(0, std::memory_order_relaxed);
+      });
+    };
+    zero();
+    parallel_for(n_elem, nt, [&](int, int e0, int e1) {
+      for (size_t k = (size_t)e0 * 27; k < (size_t)e1 * 27; ++k) c[out.en[k]].fetch_add(1, std::memory_order_relaxed);
+    });
+    for (int v = 0; v < n_nodes; ++v) ne_ptr[v + 1] = ne_ptr[v] + c[v].load(std::memory_order_relaxed);
+    ne_el.resize(ne_ptr[n_nodes]);
+    ne_loc.resize(ne_ptr[n_nodes]);
+    zero();
+    parallel_for(n_elem, nt, [&](int, int e0, int e1) {
+      for (int e = e0; e < e1; ++e)
+        for (int a = 0; a < 27; ++a) {
+          const int v = out.en[(size_t)e * 27 + a];
+          const int64_t q = ne_ptr[v] + c[v].fetch_add(1, std::memory_order_relaxed);
+          ne_el[q] = e;
+          ne_loc[q] = a;
+        }
+    });
+    parallel_for(n_nodes, nt, [&](int, int v0, int v1) {
+      for (int v = v0; v < v1; ++v)
+        for (int64_t q = ne_ptr[v] + 1; q < ne_ptr[v + 1]; ++q) {   // insertion sort by (element, position)
+          const int e = ne_el[q], a = ne_loc[q];
+          int64_t r = q;
+          while (r > ne_ptr[v] && (ne_el[r - 1] > e || (ne_el[r - 1] == e && ne_loc[r - 1] > a))) {
+            ne_el[r] = ne_el[r - 1];
+            ne_loc[r] = ne_loc[r - 1];
+            --r;
+          }
+          ne_el[r] = e;
+          ne_loc[r] = a;
+        }
+    });
   }
   constexpr int MAXNB = 26;
   // the positions of a 27-node element within one lattice step of each position, ascending
@@ -287,7 +340,7 @@ std::string build_level1_mesh(int64_t n, int n_nodes, const int* node_dof, int n
   if (overflow) return "elem_node: a node lies in more than 8 elements or has more than 26 lattice neighbours";
   std::vector<int64_t> cntp(n_nodes + 1, 0);
   for (int v = 0; v < n_nodes; ++v) cntp[v + 1] = cntp[v] + ncount[v];
-  std::vector<int> nb(cntp[n_nodes]);
+  RawVec<int> nb(cntp[n_nodes]);
   parallel_for(n_nodes, host_threads(), [&](int, int v0, int v1) {
     for (int v = v0; v < v1; ++v)
       std::copy(nbuf.get() + (size_t)v * MAXNB, nbuf.get() + (size_t)v * MAXNB + ncount[v], nb.begin() + cntp[v]);
@@ -302,16 +355,20 @@ std::string build_level1_mesh(int64_t n, int n_nodes, const int* node_dof, int n
 void build_domains(const LevelMesh& mesh, int delta, LevelMaps& m) {
   const int N = mesh.n_parts;
   const int nn = mesh.n_nodes;
-  std::vector<int64_t> ne_ptr;
-  std::vector<int> ne;
-  node_elements(mesh, ne_ptr, ne);
+  std::vector<int64_t> ne_ptr_own;
+  RawVec<int> ne_own;
+  if (mesh.ne_ptr.empty()) node_elements(mesh, ne_ptr_own, ne_own);
+  const std::vector<int64_t>& ne_ptr = mesh.ne_ptr.empty() ? ne_ptr_own : mesh.ne_ptr;
+  const RawVec<int>& ne = mesh.ne_ptr.empty() ? ne_own : mesh.ne;
   // S(v)
   m.s_ptr = ne_ptr;
   m.s.resize(ne.size());
-  for (size_t k = 0; k < ne.size(); ++k) m.s[k] = mesh.elem_part[ne[k]];
+  parallel_for(nn, host_threads(), [&](int, int v0, int v1) {
+    for (int64_t k = ne_ptr[v0]; k < ne_ptr[v1]; ++k) m.s[k] = mesh.elem_part[ne[k]];
+  });
   sort_unique_segments(m.s_ptr, m.s);
   // owning part of every dof (restricted combination): first part of S(v), the element's part for pressure
-  m.owner.assign(mesh.n_dof, -1);
+  fill_n_parallel(m.owner, mesh.n_dof, -1);
   parallel_for(nn, host_threads(), [&](int, int v0, int v1) {     // every dof has one node or element
     for (int v = v0; v < v1; ++v) {
       if (m.s_ptr[v + 1] == m.s_ptr[v]) continue;
@@ -437,27 +494,43 @@ void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m, bool linear_inte
     m.es_ptr[E + 1] = (int64_t)m.es.size();
   }
   // coarse columns: (entity, direction) with a free dof, then one pressure column per part
+  // (counted in parallel, numbered in (entity, direction) order, then filled and sorted in parallel)
+  std::vector<int> ecnt((size_t)n_ent * 3);
+  parallel_for(n_ent, host_threads(), [&](int, int E0, int E1) {
+    for (int E = E0; E < E1; ++E)
+      for (int d = 0; d < 3; ++d) {
+        int c = 0;
+        for (int64_t k = m.ent_ptr[E]; k < m.ent_ptr[E + 1]; ++k) c += mesh.node_dof[3 * m.ent_nodes[k] + d] >= 0;
+        ecnt[(size_t)E * 3 + d] = c;
+      }
+  });
   m.col_entity.clear();
   m.col_dir.clear();
   m.col_ptr.assign(1, 0);
-  m.col_dofs.clear();
   m.ent_col.assign((size_t)n_ent * 3, -1);
-  for (int E = 0; E < n_ent; ++E) {
+  for (int E = 0; E < n_ent; ++E)
     for (int d = 0; d < 3; ++d) {
-      const size_t before = m.col_dofs.size();
-      for (int64_t k = m.ent_ptr[E]; k < m.ent_ptr[E + 1]; ++k) {
-        const int g = mesh.node_dof[3 * m.ent_nodes[k] + d];
-        if (g >= 0) m.col_dofs.push_back(g);
-      }
-      if (m.col_dofs.size() > before) {
-        std::sort(m.col_dofs.begin() + before, m.col_dofs.end());
-        m.ent_col[(size_t)E * 3 + d] = (int)m.col_entity.size();
-        m.col_entity.push_back(E);
-        m.col_dir.push_back(d);
-        m.col_ptr.push_back((int64_t)m.col_dofs.size());
-      }
+      const int c = ecnt[(size_t)E * 3 + d];
+      if (!c) continue;
+      m.ent_col[(size_t)E * 3 + d] = (int)m.col_entity.size();
+      m.col_entity.push_back(E);
+      m.col_dir.push_back(d);
+      m.col_ptr.push_back(m.col_ptr.back() + c);
     }
-  }
+  m.col_dofs.resize(m.col_ptr.back());
+  parallel_for(n_ent, host_threads(), [&](int, int E0, int E1) {
+    for (int E = E0; E < E1; ++E)
+      for (int d = 0; d < 3; ++d) {
+        const int col = m.ent_col[(size_t)E * 3 + d];
+        if (col < 0) continue;
+        int64_t w = m.col_ptr[col];
+        for (int64_t k = m.ent_ptr[E]; k < m.ent_ptr[E + 1]; ++k) {
+          const int g = mesh.node_dof[3 * m.ent_nodes[k] + d];
+          if (g >= 0) m.col_dofs[w++] = g;
+        }
+        std::sort(m.col_dofs.begin() + m.col_ptr[col], m.col_dofs.begin() + w);
+      }
+  });
   std::vector<std::vector<int>> part_elems(N);
   for (int e = 0; e < mesh.n_elem; ++e) part_elems[mesh.elem_part[e]].push_back(e);
   m.part_col.assign(N, -1);
@@ -478,18 +551,24 @@ void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m, bool linear_inte
   m.n_coarse = (int)m.col_entity.size();
   // per-dof tables
   const int n = mesh.n_dof;
-  m.dof_gcol.assign(n, -1);
-  m.dof_ipart.assign(n, -1);
-  m.dof_irow.assign(n, -1);
-  for (int v : m.gamma_nodes)
-    for (int d = 0; d < 3; ++d) {
-      const int g = mesh.node_dof[3 * v + d];
-      if (g >= 0) m.dof_gcol[g] = m.ent_col[(size_t)m.node_ent[v] * 3 + d];
+  fill_n_parallel(m.dof_gcol, n, -1);
+  fill_n_parallel(m.dof_ipart, n, -1);
+  fill_n_parallel(m.dof_irow, n, -1);
+  parallel_for((int)m.gamma_nodes.size(), host_threads(), [&](int, int k0, int k1) {   // distinct dofs
+    for (int k = k0; k < k1; ++k) {
+      const int v = m.gamma_nodes[k];
+      for (int d = 0; d < 3; ++d) {
+        const int g = mesh.node_dof[3 * v + d];
+        if (g >= 0) m.dof_gcol[g] = m.ent_col[(size_t)m.node_ent[v] * 3 + d];
+      }
     }
-  for (int e = 0; e < mesh.n_elem; ++e) {
-    const int g = mesh.elem_pdof[4 * e];
-    if (g >= 0) m.dof_gcol[g] = m.part_col[mesh.elem_part[e]];
-  }
+  });
+  parallel_for(mesh.n_elem, host_threads(), [&](int, int e0, int e1) {
+    for (int e = e0; e < e1; ++e) {
+      const int g = mesh.elem_pdof[4 * e];
+      if (g >= 0) m.dof_gcol[g] = m.part_col[mesh.elem_part[e]];
+    }
+  });
   // interior sets and coarse columns, part by part (in parallel; concatenated in part order)
   struct PartOut {
     std::vector<int> idofs, pcols, z_lc, z_dof;
@@ -633,7 +712,7 @@ std::string build_next_mesh(const LevelMesh& mesh, const LevelMaps& m, const int
     }
   }
   for (int E = 0; E < n_ent; ++E) ac[E + 1] += ac[E];
-  std::vector<int> nb(ac[n_ent]);
+  RawVec<int> nb(ac[n_ent]);
   std::vector<int64_t> af(ac.begin(), ac.end() - 1);
   for (int u : m.gamma_nodes) {
     const int E = m.node_ent[u];

@@ -9,9 +9,36 @@
 #include <cstdint>
 #include <string>
 #include <functional>
+#include <memory>
+#include <new>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 namespace gdsw {
+
+// Allocator whose resize leaves new elements default-initialized (integers are left unset): the
+// large index arrays below are sized and then filled in parallel, without a serial zeroing pass.
+template <typename T>
+struct NoInitAlloc : std::allocator<T> {
+  template <typename U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() noexcept = default;
+  template <typename U>
+  NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+  template <typename U>
+  void construct(U* p) noexcept(std::is_nothrow_default_constructible<U>::value) {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <typename U, typename... A>
+  void construct(U* p, A&&... a) {
+    ::new (static_cast<void*>(p)) U(std::forward<A>(a)...);
+  }
+};
+template <typename T>
+using RawVec = std::vector<T, NoInitAlloc<T>>;
 
 // One level: nodes carrying up to three velocity dofs, elements with a node
 // list and four pressure slots (mode 0 constant, modes 1..3 linear), parts.
@@ -21,14 +48,14 @@ struct LevelMesh {
   std::vector<int> node_dof;          // n_nodes*3, -1 = no dof
   int n_elem = 0;
   std::vector<int64_t> en_ptr;        // element -> nodes (CSR)
-  std::vector<int> en;
+  RawVec<int> en;
   std::vector<int> elem_pdof;         // n_elem*4, -1 = none
   std::vector<int> elem_part;         // n_elem
   int n_parts = 0;
   std::vector<int64_t> adj_ptr;       // node graph (sorted, no self loops)
-  std::vector<int> adj;
+  RawVec<int> adj;
   std::vector<int64_t> ne_ptr;        // node -> elements (ascending), when the builder made it
-  std::vector<int> ne;
+  RawVec<int> ne;
 };
 
 struct LevelMaps {
@@ -52,14 +79,14 @@ struct LevelMaps {
   std::vector<int> part_col;          // n_parts, -1 = no pressure column
   // overlapping sets D_i and interior sets I_i (sorted dof lists)
   std::vector<int64_t> dom_ptr;
-  std::vector<int> dom;
+  RawVec<int> dom;
   std::vector<int64_t> int_ptr;
   std::vector<int> inter;
   // per-dof tables
-  std::vector<int> owner;             // owning part (restricted combination)
-  std::vector<int> dof_gcol;          // coarse column of an interface dof, else -1
-  std::vector<int> dof_ipart;         // part of an interior dof, else -1
-  std::vector<int> dof_irow;          // row of an interior dof inside I_i
+  RawVec<int> owner;                  // owning part (restricted combination)
+  RawVec<int> dof_gcol;               // coarse column of an interface dof, else -1
+  RawVec<int> dof_ipart;              // part of an interior dof, else -1
+  RawVec<int> dof_irow;               // row of an interior dof inside I_i
   // per part: coarse columns touching the part (sorted)
   std::vector<int64_t> pc_ptr;
   std::vector<int> pcols;

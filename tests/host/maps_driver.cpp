@@ -25,8 +25,8 @@ static std::vector<T> load(const std::string& path) {
   return v;
 }
 
-template <typename T>
-static void store(const std::string& path, const std::vector<T>& v) {
+template <typename T, typename A>
+static void store(const std::string& path, const std::vector<T, A>& v) {
   FILE* f = std::fopen(path.c_str(), "wb");
   if (!f) return;
   if (!v.empty()) std::fwrite(v.data(), sizeof(T), v.size(), f);
