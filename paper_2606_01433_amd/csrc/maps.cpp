@@ -457,33 +457,69 @@ void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m, bool linear_inte
   m.node_ent.assign(nn, -1);
   std::vector<char> is_gamma(nn, 0);
   for (int v : m.gamma_nodes) is_gamma[v] = 1;
-  m.ent_ptr.assign(1, 0);
-  m.ent_nodes.clear();
-  m.ent_kind.clear();
-  std::vector<int> stack;
-  for (int v : m.gamma_nodes) {
-    if (m.node_ent[v] >= 0) continue;
-    const int E = (int)m.ent_kind.size();
-    const int64_t first = (int64_t)m.ent_nodes.size();
-    m.node_ent[v] = E;
-    stack.assign(1, v);
-    while (!stack.empty()) {
-      const int u = stack.back();
-      stack.pop_back();
-      m.ent_nodes.push_back(u);
-      for (int64_t k = mesh.adj_ptr[u]; k < mesh.adj_ptr[u + 1]; ++k) {
-        const int w = mesh.adj[k];
-        if (is_gamma[w] && m.node_ent[w] < 0 && same_set(m, u, w)) {
-          m.node_ent[w] = E;
-          stack.push_back(w);
+  // entities: connected components of the interface nodes under "adjacent with the same S",
+  // numbered in order of their smallest node.  Parallel union-find that links the larger root
+  // below the smaller one, so every component's root is its smallest node.
+  const int ng = (int)m.gamma_nodes.size();
+  const int nth = host_threads();
+  std::unique_ptr<std::atomic<int>[]> parent(new std::atomic<int>[nn]);
+  parallel_for(ng, nth, [&](int, int k0, int k1) {
+    for (int k = k0; k < k1; ++k) parent[m.gamma_nodes[k]].store(m.gamma_nodes[k], std::memory_order_relaxed);
+  });
+  auto find = [&](int x) {
+    for (;;) {
+      int p = parent[x].load(std::memory_order_relaxed);
+      if (p == x) return x;
+      const int gp = parent[p].load(std::memory_order_relaxed);
+      if (gp != p) parent[x].compare_exchange_weak(p, gp, std::memory_order_relaxed);   // path halving
+      x = p;
+    }
+  };
+  parallel_for(ng, nth, [&](int, int k0, int k1) {
+    for (int k = k0; k < k1; ++k) {
+      const int u = m.gamma_nodes[k];
+      for (int64_t q = mesh.adj_ptr[u]; q < mesh.adj_ptr[u + 1]; ++q) {
+        const int w = mesh.adj[q];
+        if (w <= u || !is_gamma[w] || !same_set(m, u, w)) continue;
+        for (;;) {
+          int a = find(u), b = find(w);
+          if (a == b) break;
+          if (a > b) std::swap(a, b);
+          if (parent[b].compare_exchange_strong(b, a, std::memory_order_relaxed)) break;   // b stays a root until linked
         }
       }
     }
-    std::sort(m.ent_nodes.begin() + first, m.ent_nodes.end());
-    const int64_t cnt = (int64_t)m.ent_nodes.size() - first;
-    const int64_t ns = nS(v);
-    m.ent_kind.push_back(cnt == 1 ? 0 : (ns == 2 ? 2 : 1));
-    m.ent_ptr.push_back((int64_t)m.ent_nodes.size());
+  });
+  std::vector<int> root(ng);
+  parallel_for(ng, nth, [&](int, int k0, int k1) {
+    for (int k = k0; k < k1; ++k) root[k] = find(m.gamma_nodes[k]);
+  });
+  m.ent_kind.clear();
+  std::vector<int64_t> ecount;
+  for (int k = 0; k < ng; ++k) {                      // gamma nodes ascending: roots open entities in order
+    const int u = m.gamma_nodes[k];
+    if (root[k] == u) {
+      m.node_ent[u] = (int)ecount.size();
+      ecount.push_back(0);
+    }
+  }
+  for (int k = 0; k < ng; ++k) {
+    const int E = m.node_ent[root[k]];
+    m.node_ent[m.gamma_nodes[k]] = E;
+    ecount[E]++;
+  }
+  const int ne_ = (int)ecount.size();
+  m.ent_ptr.assign(ne_ + 1, 0);
+  for (int E = 0; E < ne_; ++E) m.ent_ptr[E + 1] = m.ent_ptr[E] + ecount[E];
+  m.ent_nodes.resize(m.ent_ptr[ne_]);
+  {
+    std::vector<int64_t> fill(m.ent_ptr.begin(), m.ent_ptr.end() - 1);
+    for (int u : m.gamma_nodes) m.ent_nodes[fill[m.node_ent[u]]++] = u;   // ascending within each entity
+  }
+  m.ent_kind.resize(ne_);
+  for (int E = 0; E < ne_; ++E) {
+    const int v = m.ent_nodes[m.ent_ptr[E]];
+    m.ent_kind[E] = ecount[E] == 1 ? 0 : (nS(v) == 2 ? 2 : 1);
   }
   const int n_ent = (int)m.ent_kind.size();
   m.es_ptr.assign(n_ent + 1, 0);
