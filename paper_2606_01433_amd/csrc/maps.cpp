@@ -149,6 +149,35 @@ void fill_n_parallel(RawVec<int>& v, int64_t n, int x) {
   });
 }
 
+// True when the non-negative entries of ids, in array order, are strictly increasing.
+bool increasing_free(const std::vector<int>& ids) {
+  const int n = (int)ids.size();
+  const int nchunk = (n + 65535) / 65536;
+  if (nchunk == 0) return true;
+  std::vector<int> first(nchunk, -1), last(nchunk, -1);
+  std::atomic<bool> ok(true);
+  parallel_for(nchunk, host_threads(), [&](int, int c0, int c1) {
+    for (int c = c0; c < c1; ++c) {
+      int prev = -1;
+      for (int k = c * 65536; k < std::min(n, (c + 1) * 65536); ++k) {
+        const int g = ids[k];
+        if (g < 0) continue;
+        if (prev >= 0 && g <= prev) ok = false;
+        if (first[c] < 0) first[c] = g;
+        prev = g;
+      }
+      last[c] = prev;
+    }
+  });
+  int prev = -1;
+  for (int c = 0; c < nchunk; ++c) {
+    if (first[c] < 0) continue;
+    if (prev >= 0 && first[c] <= prev) return false;
+    prev = last[c];
+  }
+  return ok.load();
+}
+
 // elements containing each node (CSR, ascending), for meshes whose builder did not make them
 void node_elements(const LevelMesh& mesh, std::vector<int64_t>& ptr, RawVec<int>& el) {
   ptr.assign(mesh.n_nodes + 1, 0);
@@ -311,29 +340,36 @@ std::string build_level1_mesh(int64_t n, int n_nodes, const int* node_dof, int n
   std::unique_ptr<int[]> nbuf(new int[(size_t)n_nodes * MAXNB]);   // every row written before it is read
   std::vector<int> ncount(n_nodes, 0);
   std::atomic<bool> overflow(false);
-  parallel_for(n_nodes, host_threads(), [&](int, int v0, int v1) {
-    int cand[8 * 26];
+  // distinct candidates through a per-thread stamp (stamp[w] == v: w already taken for node v), then
+  // the at most 26 neighbours sorted
+  std::vector<std::vector<int>> nstamp(nt);
+  parallel_for(n_nodes, nt, [&](int th, int v0, int v1) {
+    std::vector<int>& stamp = nstamp[th];
+    if (stamp.empty()) stamp.assign(n_nodes, -1);
     for (int v = v0; v < v1; ++v) {
-      int nc = 0;
       if (ne_ptr[v + 1] - ne_ptr[v] > 8) {      // a hexahedral lattice node lies in at most 8 elements
         overflow = true;
         continue;
       }
-      for (int64_t q = ne_ptr[v]; q < ne_ptr[v + 1]; ++q) {
+      int* row = nbuf.get() + (size_t)v * MAXNB;
+      int w = 0;
+      for (int64_t q = ne_ptr[v]; q < ne_ptr[v + 1] && w <= MAXNB; ++q) {
         const int* el = out.en.data() + (size_t)ne_el[q] * 27;
         const Near& t = near[ne_loc[q]];
-        for (int k = 0; k < t.count; ++k) cand[nc++] = el[t.pos[k]];
-      }
-      std::sort(cand, cand + nc);
-      int w = 0;
-      for (int k = 0; k < nc; ++k)
-        if (k == 0 || cand[k] != cand[k - 1]) {
+        for (int k = 0; k < t.count; ++k) {
+          const int c = el[t.pos[k]];
+          if (stamp[c] == v) continue;
+          stamp[c] = v;
           if (w == MAXNB) {
             overflow = true;
+            w = MAXNB + 1;
             break;
           }
-          nbuf[(size_t)v * MAXNB + w++] = cand[k];
+          row[w++] = c;
         }
+      }
+      if (w > MAXNB) continue;
+      std::sort(row, row + w);
       ncount[v] = w;
     }
   });
@@ -391,11 +427,15 @@ void build_domains(const LevelMesh& mesh, int delta, LevelMaps& m) {
   for (int e = 0; e < mesh.n_elem; ++e) part_elems[mesh.elem_part[e]].push_back(e);
   std::vector<std::vector<int>> dofs(N);
   const int nthreads = host_threads();
+  // When the velocity dofs grow with (node, component) and the pressure dofs with (element, mode),
+  // a part's sorted dof list is the merge of its velocity dofs in node order and its pressure dofs
+  // in element order: sorting the nodes (a third as many) replaces sorting the dofs.
+  const bool by_node = increasing_free(mesh.node_dof), by_elem = increasing_free(mesh.elem_pdof);
   std::vector<std::vector<int>> stamps(nthreads);
   parallel_for(N, nthreads, [&](int t, int i0, int i1) {
     std::vector<int>& stamp = stamps[t];
     if (stamp.empty()) stamp.assign(nn, -1);
-    std::vector<int> layer, frontier, next;
+    std::vector<int> layer, frontier, next, vel, prs;
     for (int i = i0; i < i1; ++i) {
       std::vector<int>& o = dofs[i];
       layer.clear();
@@ -420,6 +460,24 @@ void build_domains(const LevelMesh& mesh, int delta, LevelMaps& m) {
           }
         layer.insert(layer.end(), next.begin(), next.end());
         frontier.swap(next);
+      }
+      if (by_node && by_elem) {
+        std::sort(layer.begin(), layer.end());
+        vel.clear();
+        prs.clear();
+        for (int v : layer)
+          for (int d = 0; d < 3; ++d) {
+            const int g = mesh.node_dof[3 * v + d];
+            if (g >= 0) vel.push_back(g);
+          }
+        for (int e : part_elems[i])              // elements ascending
+          for (int q = 0; q < 4; ++q) {
+            const int g = mesh.elem_pdof[4 * e + q];
+            if (g >= 0) prs.push_back(g);
+          }
+        o.resize(vel.size() + prs.size());
+        std::merge(vel.begin(), vel.end(), prs.begin(), prs.end(), o.begin());
+        continue;
       }
       for (int v : layer)
         for (int d = 0; d < 3; ++d) {

@@ -97,6 +97,23 @@ def test_maps_die_four_level_uneven():
     assert len(maps) == 3
 
 
+def test_maps_with_permuted_dof_numbering():
+    """Dof ids in no particular order (velocity ids no longer grow with the node, so the builder sorts
+    each overlapping set's dofs instead of merging them in node order): the maps still equal the
+    oracle's on the same numbering."""
+    _lib()
+    import copy
+    P0 = cached(("die16", 4, 0.3), lambda: die_problem(16, 8, 8, seed=3, levels=4, frac3=0.3))
+    P = copy.copy(P0)
+    perm = np.random.default_rng(5).permutation(P0.n).astype(np.int32)
+    nd = np.asarray(P0.node_dof).copy()
+    nd[nd >= 0] = perm[nd[nd >= 0]]
+    pd = np.asarray(P0.elem_pdof).copy()
+    pd[pd >= 0] = perm[pd[pd >= 0]]
+    P.node_dof, P.elem_pdof = nd, pd
+    _compare(P)
+
+
 def test_invalid_inputs_are_rejected(cube4):
     _lib()
     bad = cube4.with_hierarchy(cube4.elem_part.copy(), [8], [], 2)
