@@ -275,11 +275,12 @@ __device__ __forceinline__ void lsm_tri_upper_one(const T* __restrict__ A, int l
 }
 
 // The panel update of the chunk as a small GEMM on the matrix cores:
-// x[r, s] -= sum_k A[r, q0 + k] x[q0 + k, s] for rows r in [r0, r1), k < pw,
-// s < KC.  Waves take 16-row blocks in turn; one 16x16x4 MFMA per four panel
-// columns, its 16 output columns the right-hand sides (KC of them used), so each
-// lane reads one right-hand-side value per MFMA from LDS instead of one
-// broadcast per FMA.  Operand layout as in the LU's MFMA tiles (transposed
+// x[r, s] -= sum_k A[r, q0 + k] x[q0 + k, s] for the rows r < r1 of the 64-row
+// tiles t0 <= q < t1 whose bit is set in the panel's masks M (the other tiles of
+// the panel are zero), k < pw, s < KC.  Waves take 16-row blocks in turn; one
+// 16x16x4 MFMA per four panel columns, its 16 output columns the right-hand
+// sides (KC of them used), so each lane reads one right-hand-side value per MFMA
+// from LDS instead of one broadcast per FMA.  Operand layout as in the LU's MFMA tiles (transposed
 // product: lane (li, lk) feeds row li / column li and k = 4 step + lk, and
 // holds C[row li][column mfma_col(lk, q)]).
 template <typename T> struct Mma;
