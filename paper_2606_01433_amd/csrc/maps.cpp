@@ -669,11 +669,15 @@ void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m, bool linear_inte
   };
   std::vector<PartOut> outp(N);
   const int nthreads = host_threads();
-  std::vector<std::vector<int>> stamps(nthreads);
+  // With dof ids growing with (node, component) and (element, mode), the sorted lists below come from
+  // the closure's nodes in sorted order and the part's elements in order (merges and a counting sort
+  // by local column) instead of sorts of the dof lists; other numberings take the sorting path.
+  const bool by_order = increasing_free(mesh.node_dof) && increasing_free(mesh.elem_pdof);
+  std::vector<std::vector<int>> stamps(nthreads), cstamps(nthreads), cposs(nthreads);
   parallel_for(N, nthreads, [&](int t, int i0, int i1) {
     std::vector<int>& stamp = stamps[t];
     if (stamp.empty()) stamp.assign(nn, -1);
-    std::vector<int> layer;
+    std::vector<int> layer, ivel, iprs, zv, zp, zall, ccnt;
     std::vector<std::pair<int, int>> zs;
     for (int i = i0; i < i1; ++i) {
       PartOut& o = outp[i];
@@ -686,6 +690,68 @@ void build_maps(const LevelMesh& mesh, int delta, LevelMaps& m, bool linear_inte
             layer.push_back(v);
           }
         }
+      if (by_order) {
+        std::vector<int>& cstamp = cstamps[t];
+        std::vector<int>& cpos = cposs[t];
+        if (cstamp.empty()) {
+          cstamp.assign(m.n_coarse, -1);
+          cpos.assign(m.n_coarse, 0);
+        }
+        std::sort(layer.begin(), layer.end());
+        ivel.clear();
+        iprs.clear();
+        zv.clear();
+        zp.clear();
+        for (int v : layer) {
+          const bool interior = nS(v) == 1 && m.s[m.s_ptr[v]] == i;
+          for (int d = 0; d < 3; ++d) {
+            const int g = mesh.node_dof[3 * v + d];
+            if (g < 0) continue;
+            if (interior) ivel.push_back(g);
+            else if (is_gamma[v]) zv.push_back(g);
+          }
+        }
+        for (int e : part_elems[i])              // elements ascending
+          for (int q = 0; q < 4; ++q) {
+            const int g = mesh.elem_pdof[4 * e + q];
+            if (g < 0) continue;
+            if (q > 0) {
+              if (linear_interior) iprs.push_back(g);
+            } else {
+              zp.push_back(g);
+            }
+          }
+        o.idofs.resize(ivel.size() + iprs.size());
+        std::merge(ivel.begin(), ivel.end(), iprs.begin(), iprs.end(), o.idofs.begin());
+        for (size_t a = 0; a < o.idofs.size(); ++a) {   // interior dofs belong to one part only
+          m.dof_ipart[o.idofs[a]] = i;
+          m.dof_irow[o.idofs[a]] = (int)a;
+        }
+        zall.resize(zv.size() + zp.size());
+        std::merge(zv.begin(), zv.end(), zp.begin(), zp.end(), zall.begin());
+        for (int g : zall) {                      // coarse columns of the part, sorted
+          const int c = m.dof_gcol[g];
+          if (cstamp[c] != i) {
+            cstamp[c] = i;
+            o.pcols.push_back(c);
+          }
+        }
+        std::sort(o.pcols.begin(), o.pcols.end());
+        const int mi = (int)o.pcols.size();
+        for (int a = 0; a < mi; ++a) cpos[o.pcols[a]] = a;
+        ccnt.assign(mi + 1, 0);                   // interface dofs by (local column, dof): a stable
+        for (int g : zall) ccnt[cpos[m.dof_gcol[g]] + 1]++;   // counting sort of the ascending dofs
+        for (int a = 0; a < mi; ++a) ccnt[a + 1] += ccnt[a];
+        o.z_lc.resize(zall.size());
+        o.z_dof.resize(zall.size());
+        for (int g : zall) {
+          const int lc = cpos[m.dof_gcol[g]];
+          const int at = ccnt[lc]++;
+          o.z_lc[at] = lc;
+          o.z_dof[at] = g;
+        }
+        continue;
+      }
       const size_t n_closure = layer.size();
       zs.clear();
       for (size_t k = 0; k < n_closure; ++k) {
