@@ -101,7 +101,7 @@ typedef struct gdsw_problem {
  * precision : GDSW_FP64, or GDSW_MIXED (local factors, interior factors and
  *             Phi_I in FP32; K, Galerkin accumulation, Krylov vectors,
  *             Gram-Schmidt and the coarsest factorization in FP64).
- * restart   : FGMRES restart length m (default 30).
+ * restart   : FGMRES restart length m, 1..250 (default 30; GDSW_EINVAL outside).
  * max_it    : cap on total inner iterations (default 1000).
  * tol       : relative residual target (default 1e-8).
  * no_coarse : 1 = omit the coarsest correction (one-level Schwarz for L = 2).
