@@ -42,3 +42,14 @@ def test_bench_traffic_entries_match_the_local_solve_source():
     for key, rec in bench.LOCAL_SOLVE_TRAFFIC.items():
         assert rec["source_hash"] == h, key
         assert rec["bytes"] > 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus N > 1 exits with a message, before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=root)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
